@@ -1,0 +1,171 @@
+/*
+ * ehdg.h -- C ABI of the MI355X (gfx950) eHDG solver library (libehdg.so).
+ *
+ * The method (Muralikrishnan, Tran, Bui-Thanh, "eHDG: an exponentially
+ * convergent iterative solver for HDG discretizations of hyperbolic PDEs"):
+ * every iteration solves one independent local problem per element, with the
+ * face traces of the previous iterate as data (Algorithm 1, Section 3), and then
+ * recomputes the traces from the new element solutions (eq. transportLocale for
+ * transport; the trace formula below the shallow-water local solver for SWE).
+ *
+ * Supported problems (uniform axis-aligned meshes, constant coefficients, tensor
+ * Lagrange elements of degree p on Gauss-Lobatto-Legendre nodes, Gauss-Legendre
+ * quadrature with p+2 points per direction):
+ *   EHDG_TRANSPORT  beta . grad u + sigma u = f (steady) or its backward-Euler step
+ *                   (Section 3, eq. transportLocal and the time-dependent paragraph)
+ *   EHDG_SWE        linearized shallow water, backward Euler, 2D, Coriolis,
+ *                   friction and wind stress zero (Section 3, linearizedShallow)
+ *
+ * Conventions shared by every entry point
+ *   - Device pointers ("d_") are HIP device memory owned by the caller; host
+ *     pointers are plain host memory.  The library never allocates device memory:
+ *     all of its device state lives in the caller's workspace.
+ *   - Element index e = i0 + n0 (i1 + n1 i2).  Node index a = a0 + (p+1) a1 +
+ *     (p+1)^2 a2 over ascending GLL coordinates.  Faces 0..5 = x-, x+, y-, y+, z-, z+.
+ *     Face nodes are ordered by the tangential node indices in increasing axis
+ *     order, first tangential axis fastest.
+ *   - External solution layout: double u[n_el][m][N_p] (m fields: transport 1;
+ *     SWE 3 = phi, u, v).
+ *   - Every function returns 0 (EHDG_OK) or one of the EHDG_ERR_* codes; no call
+ *     aborts the process.  ehdg_last_error() gives a message for the handle.
+ *   - All work is queued on the HIP stream given at setup.  Asynchronous calls
+ *     report launch errors only; ehdg_solve / ehdg_step synchronize that stream.
+ *   - Calls on one handle must not overlap; distinct handles are independent.
+ */
+#ifndef EHDG_H
+#define EHDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  EHDG_OK = 0,
+  EHDG_ERR_INVALID_ARG = 1,        /* bad pointer, size or descriptor field          */
+  EHDG_ERR_UNSUPPORTED = 2,        /* valid problem this build does not implement    */
+  EHDG_ERR_HIP = 3,                /* a HIP runtime call failed                      */
+  EHDG_ERR_NOT_CONVERGED = 4,      /* iteration cap reached; outputs are valid       */
+  EHDG_ERR_DIVERGED = 5,           /* residual became non-finite                     */
+  EHDG_ERR_WORKSPACE_TOO_SMALL = 6 /* workspace smaller than ehdg_workspace_bytes()  */
+};
+
+enum { EHDG_TRANSPORT = 0, EHDG_SWE = 1 };
+
+/* Arithmetic of the element sweeps.
+ *   EHDG_FP64          every sweep in FP64.
+ *   EHDG_FP32_REFINE   the local operator is applied in FP32 to a correction;
+ *                      an FP64 residual of the fixed-point equation, its norm and
+ *                      the update of the iterate stay in FP64 on the GPU.
+ *   EHDG_BF16_REFINE   as above with BF16 operands on MFMA (FP32 accumulation).
+ * With s inner sweeps per refinement and exact arithmetic, one refinement equals
+ * s plain sweeps (the method is linear; Section 3, reduction to the homogeneous
+ * problem). */
+enum { EHDG_FP64 = 0, EHDG_FP32_REFINE = 1, EHDG_BF16_REFINE = 2 };
+
+typedef struct {
+  int32_t pde;          /* EHDG_TRANSPORT or EHDG_SWE                                 */
+  int32_t dim;          /* 2 or 3 (SWE: 2)                                           */
+  int32_t n[3];         /* elements per axis (unused axes ignored), each >= 1        */
+  double L[3];          /* domain [0, L_a] per axis, L_a > 0                          */
+  int32_t periodic[3];  /* 1 = periodic axis; 0 = boundary: transport inflow data /
+                           outflow; SWE reflecting wall                              */
+  int32_t degree;       /* p: transport 2D 1..6, 3D 1..4; SWE 1..6                    */
+  double beta[3];       /* transport velocity (components may be 0)                  */
+  double sigma;         /* transport reaction coefficient, >= 0                       */
+  double Phi;           /* SWE mean geopotential, > 0                                 */
+  double dt;            /* backward-Euler step; 0 = steady (transport only)           */
+  int32_t precision;    /* EHDG_FP64 / EHDG_FP32_REFINE / EHDG_BF16_REFINE            */
+  int32_t inner_sweeps; /* low-precision sweeps per FP64 refinement (refine modes)    */
+} ehdg_desc;
+
+typedef struct ehdg_problem* ehdg_handle;
+
+/* Reference points used by the discretization, for callers that sample data.
+ * gll_nodes[p+1] (ascending, on [-1,1]); gauss_pts[p+2], gauss_wts[p+2]. Host memory.
+ * Any pointer may be NULL.  Forcing is sampled at the tensor Gauss points of each
+ * element, boundary data at the face GLL nodes, initial states at the GLL nodes. */
+int ehdg_reference_points(int32_t degree, double* gll_nodes, double* gauss_pts, double* gauss_wts);
+
+/* Device workspace (bytes) needed by ehdg_setup for this descriptor. */
+int ehdg_workspace_bytes(const ehdg_desc* desc, size_t* bytes);
+
+/* Builds the local operators on the host (FP64), uploads them into the caller's
+ * workspace (aligned to 256 bytes, at least ehdg_workspace_bytes()) on `stream`
+ * (a hipStream_t, NULL = default stream) and returns a handle.  The workspace must
+ * stay valid until ehdg_destroy.  State after setup: zero forcing, zero boundary
+ * data, zero initial state. */
+int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes, void* stream,
+               ehdg_handle* out);
+
+/* Problem data (Section 3 local equations' right-hand sides).
+ *   d_forcing_q: right-hand side of each field's equation sampled at the tensor Gauss
+ *                points, double [n_el][m][(p+2)^dim], or NULL for zero.  For SWE the
+ *                momentum rows are the equations multiplied by Phi.
+ *   d_bc:        transport inflow boundary data g at the boundary-face GLL nodes, or
+ *                NULL for zero.  Layout: sides x-, x+, y-, y+, z-, z+ of the
+ *                non-periodic axes concatenated; within a side, faces ordered by the
+ *                tangential element indices (first tangential axis fastest), each face
+ *                holding its (p+1)^(dim-1) nodes in face-node order.  Only inflow sides
+ *                (beta . n < 0) are read.  Size: sum over non-periodic sides of
+ *                (faces on the side) * (p+1)^(dim-1) doubles.
+ * May be called again between steps; the current iterate is kept. */
+int ehdg_set_forcing(ehdg_handle h, const double* d_forcing_q, const double* d_bc);
+
+/* Initial state u^0 (external layout [n_el][m][N_p]) or NULL for zero.  Steady
+ * problems: initial guess of Algorithm 1.  Backward Euler: the solution at the
+ * current time level.  Recomputes the initial traces and resets the iteration count. */
+int ehdg_set_initial(ehdg_handle h, const double* d_u0);
+
+/* Asynchronous: exactly n_iters sweeps of Algorithm 1 (local solves + new traces),
+ * with no stopping test.  Each sweep's relative trace increment
+ * ||s^{k+1} - s^k||_2 / ||s^{k+1}||_2 is recorded (ehdg_get_residuals). */
+int ehdg_iterate(ehdg_handle h, int32_t n_iters);
+
+/* Synchronous: sweeps until the relative trace increment is below rel_tol (checked
+ * after every sweep on the device), then recovers the element solution from the
+ * last local solve.  *iters = local solves performed in this call; *rel_res = the
+ * last increment.  Returns EHDG_ERR_NOT_CONVERGED after max_iters sweeps,
+ * EHDG_ERR_DIVERGED if the increment became non-finite.  Backward-Euler handles:
+ * solves the current step's system (use ehdg_step to advance in time). */
+int ehdg_solve(ehdg_handle h, double rel_tol, int32_t max_iters, int32_t* iters, double* rel_res);
+
+/* Synchronous: n_steps backward-Euler steps, each solved to rel_tol from the
+ * previous step's traces (warm start).  iters_per_step: host int32_t[n_steps] or NULL. */
+int ehdg_step(ehdg_handle h, int32_t n_steps, double rel_tol, int32_t max_iters_per_step,
+              int32_t* iters_per_step);
+
+/* Asynchronous: the element solution of the current iterate (the last local solve,
+ * or the initial / previous-step state if no sweep ran since) into d_u [n_el][m][N_p]. */
+int ehdg_get_solution(ehdg_handle h, double* d_u);
+
+/* Synchronous: residual history of sweeps [first, first+count) since the last
+ * ehdg_set_initial or time step, into host memory.  Returns INVALID_ARG if out of range. */
+int ehdg_get_residuals(ehdg_handle h, int32_t first, int32_t count, double* out);
+
+/* Sizes of the handle's problem (host pointers, any may be NULL): element count,
+ * fields m, nodes per element N_p, trace-state values per element S, gathered
+ * inputs per element I, sweeps completed since the last reset. */
+int ehdg_sizes(ehdg_handle h, int64_t* n_el, int32_t* m, int32_t* n_p, int32_t* s, int32_t* i,
+               int32_t* iters);
+
+/* Checkpoint / resume.  The state is the double-buffered traces, the iteration
+ * count and the current time-level solution.  ehdg_state_bytes gives its size;
+ * get/set copy it to/from caller device memory on the handle's stream. */
+int ehdg_state_bytes(ehdg_handle h, size_t* bytes);
+int ehdg_get_state(ehdg_handle h, void* d_dst, size_t bytes);
+int ehdg_set_state(ehdg_handle h, const void* d_src, size_t bytes);
+
+/* Releases the host-side handle (the workspace stays the caller's). */
+int ehdg_destroy(ehdg_handle h);
+
+const char* ehdg_error_string(int code);
+const char* ehdg_last_error(ehdg_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EHDG_H */

@@ -1,0 +1,601 @@
+// C ABI of the eHDG library: handles, workspace layout and the iteration drivers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ehdg.h"
+#include "kernels.h"
+#include "setup.h"
+
+using namespace ehdg;
+
+struct ehdg_problem {
+  ehdg_desc desc;
+  Operators ops;
+  DevProblem dp;
+  const KernelSet* ks = nullptr;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  // workspace regions used only at setup / data time
+  double* Q = nullptr;
+  double* W = nullptr;
+  double* Bfull = nullptr;  // n x (m * nq_el), block diagonal load matrix
+  double* scratch = nullptr;
+  int base = 0;        // buffer holding the trace state s^0 of the current solve
+  int recovered = -1;  // sweep count for which u_new holds the recovered solution
+  std::string err;
+};
+
+namespace {
+
+constexpr int kHistCap = 1 << 16;
+constexpr int kBlockHost = 256;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int fail(ehdg_problem* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+#define HIP_TRY(h, call)                                                                    \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail((h), EHDG_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+Desc to_desc(const ehdg_desc* d) {
+  Desc o;
+  o.pde = d->pde;
+  o.dim = d->dim;
+  for (int a = 0; a < 3; ++a) {
+    o.n[a] = (a < d->dim) ? d->n[a] : 1;
+    o.L[a] = (a < d->dim) ? d->L[a] : 1.0;
+    o.periodic[a] = (a < d->dim) ? (d->periodic[a] ? 1 : 0) : 0;
+    o.beta[a] = (a < d->dim) ? d->beta[a] : 0.0;
+  }
+  o.degree = d->degree;
+  o.sigma = d->sigma;
+  o.Phi = d->Phi;
+  o.dt = d->dt;
+  return o;
+}
+
+struct Layout {
+  size_t off_ctrl, off_partials, off_hist, off_T64, off_T32, off_T16, off_R, off_Q, off_W, off_P, off_G, off_B;
+  size_t off_s0, off_s1, off_g, off_gsrc, off_wsrc, off_u, off_unew, off_lo0, off_lo1, off_rlo0, off_rlo1, off_scratch;
+  size_t total;
+};
+
+Layout layout_for(const Operators& o, long long nel, bool lowp) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += align256(bytes);
+    return at;
+  };
+  const size_t nb = (size_t)((nel + kBlockHost - 1) / kBlockHost);
+  const size_t S = o.S, I = o.I, n = o.n, ne = (size_t)nel;
+  L.off_ctrl = take(sizeof(Ctrl));
+  L.off_partials = take(2 * nb * sizeof(double));
+  L.off_hist = take(kHistCap * sizeof(double));
+  L.off_T64 = take(S * I * 8);
+  L.off_T32 = take(S * I * 4);
+  L.off_T16 = take(S * I * 2);
+  L.off_R = take(n * I * 8);
+  L.off_Q = take(S * n * 8);
+  L.off_W = take(n * n * 8);
+  L.off_P = take(o.be ? n * n * 8 : 8);
+  L.off_G = take(o.be ? S * n * 8 : 8);
+  L.off_B = take(n * (size_t)o.m * o.nq_el * 8);
+  L.off_s0 = take(S * ne * 8);
+  L.off_s1 = take(S * ne * 8);
+  L.off_g = take(S * ne * 8);
+  L.off_gsrc = take(S * ne * 8);
+  L.off_wsrc = take(n * ne * 8);
+  L.off_u = take(n * ne * 8);
+  L.off_unew = take(n * ne * 8);
+  L.off_lo0 = take(lowp ? S * ne * 4 : 8);
+  L.off_lo1 = take(lowp ? S * ne * 4 : 8);
+  L.off_rlo0 = take(lowp ? S * ne * 4 : 8);
+  L.off_rlo1 = take(lowp ? S * ne * 4 : 8);
+  const size_t scr = std::max((size_t)o.m * o.nq_el, I);
+  L.off_scratch = take(scr * ne * 8);
+  L.total = off;
+  return L;
+}
+
+long long nel_of(const ehdg_desc* d) {
+  long long n = 1;
+  for (int a = 0; a < d->dim; ++a) n *= d->n[a];
+  return n;
+}
+
+std::string validate(const ehdg_desc* d) {
+  if (!d) return "null descriptor";
+  if (d->dim != 2 && d->dim != 3) return "dim must be 2 or 3";
+  for (int a = 0; a < d->dim; ++a)
+    if (d->n[a] < 1) return "n[a] must be >= 1";
+  if (nel_of(d) > (1LL << 31) - 1024) return "too many elements";
+  if (d->precision < EHDG_FP64 || d->precision > EHDG_BF16_REFINE) return "unknown precision";
+  if (d->precision != EHDG_FP64 && d->inner_sweeps < 1) return "inner_sweeps must be >= 1";
+  return "";
+}
+
+int upload(ehdg_problem* h, void* dst, const void* src, size_t bytes) {
+  HIP_TRY(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
+  return EHDG_OK;
+}
+
+int check_launch(ehdg_problem* h) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(h, EHDG_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return EHDG_OK;
+}
+
+int read_ctrl(ehdg_problem* h, Ctrl& c) {
+  HIP_TRY(h, hipMemcpyAsync(&c, h->dp.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return EHDG_OK;
+}
+
+// g for the current time level: steady g = g_src; backward Euler g = g_src + G u
+void rebuild_g(ehdg_problem* h) {
+  DevProblem& dp = h->dp;
+  const size_t cnt = (size_t)dp.S * dp.mesh.nel;
+  hipMemcpyAsync(dp.g, dp.g_src, cnt * 8, hipMemcpyDeviceToDevice, h->stream);
+  if (dp.be) launch_matvec(dp.G, dp.S, dp.n, dp.u, dp.g, dp.mesh.nel, true, h->stream);
+}
+
+// Sweeps until the device flag is raised or max_iters; returns the Ctrl snapshot.
+int run_plain(ehdg_problem* h, double tol, int max_iters, Ctrl& c) {
+  DevProblem& dp = h->dp;
+  int launched = 0, chunk = 4;
+  for (;;) {
+    const int n = std::min(chunk, max_iters - launched);
+    for (int j = 0; j < n; ++j) h->ks->sweep64(dp, h->base + launched + j, true, tol, h->stream);
+    launched += n;
+    int rc = check_launch(h);
+    if (rc) return rc;
+    rc = read_ctrl(h, c);
+    if (rc) return rc;
+    if (c.done || launched >= max_iters) return EHDG_OK;
+    chunk = std::min(chunk * 2, 64);
+  }
+}
+
+int run_refine(ehdg_problem* h, double tol, int max_outer, Ctrl& c) {
+  DevProblem& dp = h->dp;
+  const bool bf = h->desc.precision == EHDG_BF16_REFINE;
+  auto refine = bf ? h->ks->refine16 : h->ks->refine32;
+  auto inner = bf ? h->ks->inner16 : h->ks->inner32;
+  const int s = h->desc.inner_sweeps;
+  int launched = 0, chunk = 2;
+  const void* lo_prev = nullptr;
+  for (;;) {
+    const int n = std::min(chunk, max_outer - launched);
+    for (int j = 0; j < n; ++j) {
+      const int k = h->base + launched + j;
+      // refinement j writes residual buffer rlo[k & 1]; the correction it reads
+      // (rlo of the previous refinement or an inner buffer) is never that one
+      void* r = dp.rlo[k & 1];
+      refine(dp, dp.s[k & 1], lo_prev, dp.s[(k + 1) & 1], r, tol, h->stream);
+      const void* cur = r;
+      for (int q = 1; q < s; ++q) {
+        void* out = dp.lo[q & 1];
+        inner(dp, r, cur, out, h->stream);
+        cur = out;
+      }
+      lo_prev = cur;
+    }
+    launched += n;
+    int rc = check_launch(h);
+    if (rc) return rc;
+    rc = read_ctrl(h, c);
+    if (rc) return rc;
+    if (c.done || launched >= max_outer) return EHDG_OK;
+    chunk = std::min(chunk * 2, 32);
+  }
+}
+
+// Solve the current (steady or backward-Euler) system to tol.  On return the
+// buffer holding the state from which the solution is recovered is *rec_buf.
+int solve_current(ehdg_problem* h, double tol, int max_iters, int* iters_out, double* res_out, int* rec_buf,
+                  int* next_base) {
+  DevProblem& dp = h->dp;
+  // a new segment starts from the latest state: after j sweeps (or refinements)
+  // of the previous segment it sits in buffer (base + j) & 1
+  Ctrl c;
+  int rc = read_ctrl(h, c);
+  if (rc) return rc;
+  h->base = (h->base + c.iters) & 1;
+  launch_ctrl_reset(dp.ctrl, h->stream);
+  const bool mixed = h->desc.precision != EHDG_FP64;
+  if (!mixed) {
+    rc = run_plain(h, tol, max_iters, c);
+    if (rc) return rc;
+    const int K = c.iters;
+    *iters_out = K;
+    *rec_buf = (h->base + K - 1) & 1;  // u^K is the local solve that read s^{K-1}
+    *next_base = (h->base + K) & 1;
+  } else {
+    const int s = h->desc.inner_sweeps;
+    const int max_outer = std::max(1, (max_iters + s - 1) / s);
+    rc = run_refine(h, tol, max_outer, c);
+    if (rc) return rc;
+    const int K = c.iters;
+    *iters_out = K * s;
+    *rec_buf = (h->base + K) & 1;  // the refined iterate whose residual passed
+    *next_base = *rec_buf;
+  }
+  *res_out = c.last_res;
+  if (c.status == 2) return fail(h, EHDG_ERR_DIVERGED, "relative trace increment became non-finite");
+  if (c.status != 1) return fail(h, EHDG_ERR_NOT_CONVERGED, "iteration cap reached");
+  return EHDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ehdg_reference_points(int32_t degree, double* gll_nodes, double* gauss_pts, double* gauss_wts) {
+  if (degree < 1 || degree > 16) return EHDG_ERR_INVALID_ARG;
+  Basis1D b = make_basis(degree);
+  if (gll_nodes) std::memcpy(gll_nodes, b.x.data(), b.x.size() * sizeof(double));
+  if (gauss_pts) std::memcpy(gauss_pts, b.xq.data(), b.xq.size() * sizeof(double));
+  if (gauss_wts) std::memcpy(gauss_wts, b.wq.data(), b.wq.size() * sizeof(double));
+  return EHDG_OK;
+}
+
+int ehdg_workspace_bytes(const ehdg_desc* desc, size_t* bytes) {
+  if (!bytes) return EHDG_ERR_INVALID_ARG;
+  std::string v = validate(desc);
+  if (!v.empty()) return EHDG_ERR_INVALID_ARG;
+  Operators ops;
+  std::string e = build_operators(to_desc(desc), ops);
+  if (!e.empty()) return EHDG_ERR_UNSUPPORTED;
+  *bytes = layout_for(ops, nel_of(desc), desc->precision != EHDG_FP64).total;
+  return EHDG_OK;
+}
+
+int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes, void* stream, ehdg_handle* out) {
+  if (!out || !desc) return EHDG_ERR_INVALID_ARG;
+  *out = nullptr;
+  std::string v = validate(desc);
+  if (!v.empty()) return EHDG_ERR_INVALID_ARG;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255)) return EHDG_ERR_INVALID_ARG;
+  ehdg_problem* h = new (std::nothrow) ehdg_problem();
+  if (!h) return EHDG_ERR_INVALID_ARG;
+  h->desc = *desc;
+  h->stream = (hipStream_t)stream;
+  std::string e = build_operators(to_desc(desc), h->ops);
+  if (!e.empty()) {
+    delete h;
+    return EHDG_ERR_UNSUPPORTED;
+  }
+  const Operators& o = h->ops;
+  h->ks = find_kernels(desc->pde, desc->dim, desc->pde == 0 ? o.na : 4, desc->degree);
+  const bool lowp = desc->precision != EHDG_FP64;
+  if (!h->ks || (desc->precision == EHDG_BF16_REFINE && !h->ks->refine16) ||
+      (desc->precision == EHDG_FP32_REFINE && !h->ks->refine32)) {
+    delete h;
+    return EHDG_ERR_UNSUPPORTED;
+  }
+  const long long nel = nel_of(desc);
+  Layout L = layout_for(o, nel, lowp);
+  if (workspace_bytes < L.total) {
+    delete h;
+    return EHDG_ERR_WORKSPACE_TOO_SMALL;
+  }
+  char* ws = (char*)d_workspace;
+  h->ws = ws;
+  h->ws_bytes = workspace_bytes;
+  DevProblem& dp = h->dp;
+  std::memset(&dp, 0, sizeof(dp));
+  dp.mesh.nel = (int)nel;
+  for (int a = 0; a < 3; ++a) {
+    dp.mesh.n[a] = (a < desc->dim) ? desc->n[a] : 1;
+    dp.mesh.periodic[a] = (a < desc->dim) ? (desc->periodic[a] ? 1 : 0) : 0;
+    dp.mesh.ax[a] = o.ax[a];
+    dp.mesh.dir[a] = o.dir[a];
+  }
+  dp.pde = desc->pde;
+  dp.dim = desc->dim;
+  dp.nf = o.nf;
+  dp.S = o.S;
+  dp.I = o.I;
+  dp.n = o.n;
+  dp.m = o.m;
+  dp.Np = o.Np;
+  dp.na = o.na;
+  dp.be = o.be;
+  dp.ctrl = (Ctrl*)(ws + L.off_ctrl);
+  dp.partials = (double*)(ws + L.off_partials);
+  dp.hist = (double*)(ws + L.off_hist);
+  dp.hist_cap = kHistCap;
+  dp.T64 = (const double*)(ws + L.off_T64);
+  dp.T32 = (const float*)(ws + L.off_T32);
+  dp.T16 = (const uint16_t*)(ws + L.off_T16);
+  dp.R = (const double*)(ws + L.off_R);
+  dp.P = (const double*)(ws + L.off_P);
+  dp.G = (const double*)(ws + L.off_G);
+  dp.s[0] = (double*)(ws + L.off_s0);
+  dp.s[1] = (double*)(ws + L.off_s1);
+  dp.g = (double*)(ws + L.off_g);
+  dp.g_src = (double*)(ws + L.off_gsrc);
+  dp.w_src = (double*)(ws + L.off_wsrc);
+  dp.u = (double*)(ws + L.off_u);
+  dp.u_new = (double*)(ws + L.off_unew);
+  dp.lo[0] = ws + L.off_lo0;
+  dp.lo[1] = ws + L.off_lo1;
+  dp.rlo[0] = ws + L.off_rlo0;
+  dp.rlo[1] = ws + L.off_rlo1;
+  h->Q = (double*)(ws + L.off_Q);
+  h->W = (double*)(ws + L.off_W);
+  h->Bfull = (double*)(ws + L.off_B);
+  h->scratch = (double*)(ws + L.off_scratch);
+  int rc = 0;
+  const size_t SI = (size_t)o.S * o.I;
+  // operators (FP64 host -> device) and their low-precision copies
+  if ((rc = upload(h, (void*)dp.T64, o.T.a.data(), SI * 8)) ||
+      (rc = upload(h, (void*)dp.R, o.R.a.data(), (size_t)o.n * o.I * 8)) ||
+      (rc = upload(h, h->Q, o.Q.a.data(), (size_t)o.S * o.n * 8)) ||
+      (rc = upload(h, h->W, o.W.a.data(), (size_t)o.n * o.n * 8))) {
+    std::string m = h->err;
+    delete h;
+    return rc;
+  }
+  if (o.be) {
+    if ((rc = upload(h, (void*)dp.P, o.P.a.data(), (size_t)o.n * o.n * 8)) ||
+        (rc = upload(h, (void*)dp.G, o.G.a.data(), (size_t)o.S * o.n * 8))) {
+      delete h;
+      return rc;
+    }
+  }
+  {
+    const int cols = o.m * o.nq_el;
+    std::vector<double> B((size_t)o.n * cols, 0.0);
+    for (int f = 0; f < o.m; ++f)
+      for (int i = 0; i < o.Np; ++i)
+        for (int q = 0; q < o.nq_el; ++q) B[(size_t)(f * o.Np + i) * cols + f * o.nq_el + q] = o.Bload(i, q);
+    if ((rc = upload(h, h->Bfull, B.data(), B.size() * 8))) {
+      delete h;
+      return rc;
+    }
+  }
+  launch_cast(dp.T64, (void*)dp.T32, SI, 0, h->stream);
+  launch_cast(dp.T64, (void*)dp.T16, SI, 1, h->stream);
+  launch_fill_bytes(dp.partials, L.off_hist - L.off_partials, h->stream);
+  launch_fill(dp.hist, 0.0, kHistCap, h->stream);
+  launch_ctrl_reset(dp.ctrl, h->stream);
+  *out = h;
+  rc = ehdg_set_forcing(h, nullptr, nullptr);
+  if (!rc) rc = ehdg_set_initial(h, nullptr);
+  if (rc) {
+    *out = nullptr;
+    delete h;
+    return rc;
+  }
+  return EHDG_OK;
+}
+
+int ehdg_set_forcing(ehdg_handle h, const double* d_forcing_q, const double* d_bc) {
+  if (!h) return EHDG_ERR_INVALID_ARG;
+  DevProblem& dp = h->dp;
+  const int nel = dp.mesh.nel;
+  hipStream_t st = h->stream;
+  const Operators& o = h->ops;
+  if (d_forcing_q) {
+    // F = (f, psi) per field, then w_src = A^{-1} F   (u_new serves as F's buffer)
+    launch_ext_to_soa(d_forcing_q, h->scratch, o.m * o.nq_el, nel, st);
+    launch_matvec(h->Bfull, o.n, o.m * o.nq_el, h->scratch, dp.u_new, nel, false, st);
+    launch_matvec(h->W, o.n, o.n, dp.u_new, dp.w_src, nel, false, st);
+  } else {
+    launch_fill(dp.w_src, 0.0, (size_t)o.n * nel, st);
+  }
+  if (d_bc) {
+    if (dp.pde != 0) return fail(h, EHDG_ERR_INVALID_ARG, "boundary data applies to transport only");
+    launch_bc_inputs(dp, d_bc, h->scratch, st);
+    launch_matvec(dp.R, o.n, o.I, h->scratch, dp.w_src, nel, true, st);
+  }
+  launch_matvec(h->Q, o.S, o.n, dp.w_src, dp.g_src, nel, false, st);
+  rebuild_g(h);
+  h->recovered = -1;
+  return check_launch(h);
+}
+
+int ehdg_set_initial(ehdg_handle h, const double* d_u0) {
+  if (!h) return EHDG_ERR_INVALID_ARG;
+  DevProblem& dp = h->dp;
+  const int nel = dp.mesh.nel;
+  if (d_u0)
+    launch_ext_to_soa(d_u0, dp.u, dp.n, nel, h->stream);
+  else
+    launch_fill(dp.u, 0.0, (size_t)dp.n * nel, h->stream);
+  h->base = 0;
+  launch_matvec(h->Q, dp.S, dp.n, dp.u, dp.s[0], nel, false, h->stream);
+  rebuild_g(h);
+  launch_ctrl_reset(dp.ctrl, h->stream);
+  h->recovered = -1;
+  return check_launch(h);
+}
+
+int ehdg_iterate(ehdg_handle h, int32_t n_iters) {
+  if (!h || n_iters < 0) return EHDG_ERR_INVALID_ARG;
+  if (h->desc.precision != EHDG_FP64) return fail(h, EHDG_ERR_UNSUPPORTED, "iterate runs the FP64 sweep");
+  Ctrl c;
+  int rc = read_ctrl(h, c);
+  if (rc) return rc;
+  if (c.done) {  // a finished solve: a new segment continues from its last iterate
+    h->base = (h->base + c.iters) & 1;
+    launch_ctrl_reset(h->dp.ctrl, h->stream);
+    c.iters = 0;
+  }
+  for (int j = 0; j < n_iters; ++j) h->ks->sweep64(h->dp, h->base + c.iters + j, true, -1.0, h->stream);
+  h->recovered = -1;
+  return check_launch(h);
+}
+
+int ehdg_solve(ehdg_handle h, double rel_tol, int32_t max_iters, int32_t* iters, double* rel_res) {
+  if (!h || max_iters < 1 || !(rel_tol >= 0.0)) return EHDG_ERR_INVALID_ARG;
+  int K = 0, rec = 0, nb = 0;
+  double res = 0.0;
+  int rc = solve_current(h, rel_tol, max_iters, &K, &res, &rec, &nb);
+  if (iters) *iters = K;
+  if (rel_res) *rel_res = res;
+  if (rc == EHDG_ERR_HIP) return rc;
+  h->recovered = -1;
+  if (K > 0 && rc != EHDG_ERR_DIVERGED) {
+    h->ks->volume(h->dp, h->dp.s[rec], false, h->stream);
+    int rc2 = check_launch(h);
+    if (rc2) return rc2;
+    h->recovered = 1;
+  }
+  return rc;
+}
+
+int ehdg_step(ehdg_handle h, int32_t n_steps, double rel_tol, int32_t max_iters_per_step, int32_t* iters_per_step) {
+  if (!h || n_steps < 0 || max_iters_per_step < 1 || !(rel_tol >= 0.0)) return EHDG_ERR_INVALID_ARG;
+  if (!h->dp.be) return fail(h, EHDG_ERR_INVALID_ARG, "ehdg_step needs a backward-Euler problem (dt > 0)");
+  for (int s = 0; s < n_steps; ++s) {
+    int K = 0, rec = 0, nb = 0;
+    double res = 0.0;
+    int rc = solve_current(h, rel_tol, max_iters_per_step, &K, &res, &rec, &nb);
+    if (iters_per_step) iters_per_step[s] = K;
+    if (rc) return rc;
+    // u^{m+1} from the last local solve; next step's g from it; warm start from the last traces
+    h->ks->volume(h->dp, h->dp.s[rec], true, h->stream);
+    std::swap(h->dp.u, h->dp.u_new);
+    h->base = nb;
+    launch_ctrl_reset(h->dp.ctrl, h->stream);
+    h->recovered = -1;
+    rc = check_launch(h);
+    if (rc) return rc;
+  }
+  return EHDG_OK;
+}
+
+int ehdg_get_solution(ehdg_handle h, double* d_u) {
+  if (!h || !d_u) return EHDG_ERR_INVALID_ARG;
+  DevProblem& dp = h->dp;
+  Ctrl c;
+  int rc = read_ctrl(h, c);
+  if (rc) return rc;
+  const double* src = dp.u;
+  if (h->recovered == 1) {
+    src = dp.u_new;
+  } else if (c.iters > 0) {
+    h->ks->volume(dp, dp.s[(h->base + c.iters - 1) & 1], false, h->stream);
+    h->recovered = 1;
+    src = dp.u_new;
+  }
+  launch_soa_to_ext(src, d_u, dp.n, dp.mesh.nel, h->stream);
+  return check_launch(h);
+}
+
+int ehdg_get_residuals(ehdg_handle h, int32_t first, int32_t count, double* out) {
+  if (!h || first < 0 || count < 0 || (count > 0 && !out)) return EHDG_ERR_INVALID_ARG;
+  Ctrl c;
+  int rc = read_ctrl(h, c);
+  if (rc) return rc;
+  if ((long long)first + count > c.iters || count > kHistCap || c.iters - first > kHistCap)
+    return fail(h, EHDG_ERR_INVALID_ARG, "residual range not recorded");
+  std::vector<double> ring(kHistCap);
+  HIP_TRY(h, hipMemcpyAsync(ring.data(), h->dp.hist, kHistCap * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  for (int i = 0; i < count; ++i) out[i] = ring[(first + i) % kHistCap];
+  return EHDG_OK;
+}
+
+int ehdg_sizes(ehdg_handle h, int64_t* n_el, int32_t* m, int32_t* n_p, int32_t* s, int32_t* i, int32_t* iters) {
+  if (!h) return EHDG_ERR_INVALID_ARG;
+  if (n_el) *n_el = h->dp.mesh.nel;
+  if (m) *m = h->dp.m;
+  if (n_p) *n_p = h->dp.Np;
+  if (s) *s = h->dp.S;
+  if (i) *i = h->dp.I;
+  if (iters) {
+    Ctrl c;
+    int rc = read_ctrl(h, c);
+    if (rc) return rc;
+    *iters = c.iters;
+  }
+  return EHDG_OK;
+}
+
+// state blob: [Ctrl (256 B)][base int (256 B)][s0][s1][u]
+int ehdg_state_bytes(ehdg_handle h, size_t* bytes) {
+  if (!h || !bytes) return EHDG_ERR_INVALID_ARG;
+  const size_t ne = (size_t)h->dp.mesh.nel;
+  *bytes = 512 + align256(h->dp.S * ne * 8) * 2 + align256(h->dp.n * ne * 8);
+  return EHDG_OK;
+}
+
+int ehdg_get_state(ehdg_handle h, void* d_dst, size_t bytes) {
+  size_t need = 0;
+  if (!h || !d_dst || ehdg_state_bytes(h, &need) || bytes < need) return EHDG_ERR_INVALID_ARG;
+  DevProblem& dp = h->dp;
+  const size_t ne = (size_t)dp.mesh.nel;
+  char* d = (char*)d_dst;
+  const size_t sb = align256(dp.S * ne * 8);
+  HIP_TRY(h, hipMemcpyAsync(d, dp.ctrl, sizeof(Ctrl), hipMemcpyDeviceToDevice, h->stream));
+  static thread_local int base_host;
+  base_host = h->base;
+  HIP_TRY(h, hipMemcpyAsync(d + 256, &base_host, sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(d + 512, dp.s[0], dp.S * ne * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(d + 512 + sb, dp.s[1], dp.S * ne * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(d + 512 + 2 * sb, dp.u, dp.n * ne * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return EHDG_OK;
+}
+
+int ehdg_set_state(ehdg_handle h, const void* d_src, size_t bytes) {
+  size_t need = 0;
+  if (!h || !d_src || ehdg_state_bytes(h, &need) || bytes < need) return EHDG_ERR_INVALID_ARG;
+  DevProblem& dp = h->dp;
+  const size_t ne = (size_t)dp.mesh.nel;
+  const char* d = (const char*)d_src;
+  const size_t sb = align256(dp.S * ne * 8);
+  int base_host = 0;
+  HIP_TRY(h, hipMemcpyAsync(dp.ctrl, d, sizeof(Ctrl), hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(&base_host, d + 256, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(dp.s[0], d + 512, dp.S * ne * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(dp.s[1], d + 512 + sb, dp.S * ne * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(dp.u, d + 512 + 2 * sb, dp.n * ne * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (base_host != 0 && base_host != 1) return fail(h, EHDG_ERR_INVALID_ARG, "corrupt state blob");
+  h->base = base_host;
+  rebuild_g(h);
+  h->recovered = -1;
+  return check_launch(h);
+}
+
+int ehdg_destroy(ehdg_handle h) {
+  if (!h) return EHDG_ERR_INVALID_ARG;
+  delete h;
+  return EHDG_OK;
+}
+
+const char* ehdg_error_string(int code) {
+  switch (code) {
+    case EHDG_OK: return "ok";
+    case EHDG_ERR_INVALID_ARG: return "invalid argument";
+    case EHDG_ERR_UNSUPPORTED: return "unsupported problem";
+    case EHDG_ERR_HIP: return "HIP runtime error";
+    case EHDG_ERR_NOT_CONVERGED: return "not converged within the iteration cap";
+    case EHDG_ERR_DIVERGED: return "iteration diverged";
+    case EHDG_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+  }
+  return "unknown error";
+}
+
+const char* ehdg_last_error(ehdg_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+}  // extern "C"

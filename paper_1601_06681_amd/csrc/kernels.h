@@ -1,0 +1,86 @@
+// Device-side data of one eHDG problem and the kernel entry points (host view).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ehdg {
+
+// Device-resident iteration control, one per handle.
+struct Ctrl {
+  int done;          // set once the stopping test holds (or the increment is non-finite)
+  int iters;         // sweeps completed since the last reset
+  int status;        // 0 running, 1 converged, 2 non-finite increment
+  unsigned counter;  // arrival counter of the last-block reduction
+  double last_res;   // last relative increment
+  double pad[5];
+};
+
+// Mesh indexing shared by every kernel.
+struct MeshDev {
+  int nel;
+  int n[3];
+  int periodic[3];
+  int ax[3];   // transport: active axes
+  int dir[3];  // transport: +1 if beta_ax > 0 (upwind neighbour at i-1), -1 otherwise
+};
+
+// All device pointers of a problem (SoA: component k of element e at [k * nel + e]).
+struct DevProblem {
+  MeshDev mesh;
+  int pde, dim, nf, S, I, n, m, Np, na;
+  bool be;
+  const double* T64;       // S x I
+  const float* T32;        // S x I
+  const uint16_t* T16;     // S x I (bf16 bits)
+  const double* R;         // n x I
+  const double* P;         // n x n (BE)
+  const double* G;         // S x n (BE)
+  double* s[2];            // trace state, double buffered
+  double* g;               // S
+  double* g_src;           // S
+  double* w_src;           // n
+  double* u;               // n: current time-level / last recovered solution
+  double* u_new;           // n: recovery output
+  void* lo[2];             // low-precision correction, double buffered (S)
+  void* rlo[2];            // low-precision residual, double buffered (S)
+  double* partials;        // 2 per block
+  Ctrl* ctrl;
+  double* hist;            // residual ring
+  int hist_cap;
+};
+
+// Kernels of one (pde, dim, active axes, face nodes) family.
+struct KernelSet {
+  // s[k&1] -> s[(k+1)&1]; with resid, a relative-increment reduction (tol < 0: never stops)
+  void (*sweep64)(const DevProblem&, int k, bool resid, double tol, hipStream_t);
+  // u_new = w_src + R in(s_prev) (+ P u for BE); BE: g = g_src + G u_new
+  void (*volume)(const DevProblem&, const double* s_prev, bool update_g, hipStream_t);
+  // mixed precision outer step: s_out = s_in + lo_in (lo_in may be null);
+  // r = g + T in(s_out) - s_out in FP64; r_out = r in the low precision (it is also
+  // the first inner iterate); residual reduction of ||r|| / ||s_out + r||
+  void (*refine32)(const DevProblem&, const double* s_in, const void* lo_in, double* s_out, void* r_out,
+                   double tol, hipStream_t);
+  // inner sweep on the correction: lo_out = r_lo + T_lo in(lo_in)
+  void (*inner32)(const DevProblem&, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t);
+  void (*refine16)(const DevProblem&, const double* s_in, const void* lo_in, double* s_out, void* r_out,
+                   double tol, hipStream_t);
+  void (*inner16)(const DevProblem&, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t);
+};
+
+const KernelSet* find_kernels(int pde, int dim, int na, int nf);
+
+// Generic setup-time kernels (FP64, runtime sizes).
+// y[r][e] = (accumulate ? y[r][e] : 0) + sum_c M[r][c] x[c][e]
+void launch_matvec(const double* M, int rows, int cols, const double* x, double* y, int nel, bool accumulate,
+                   hipStream_t st);
+// SoA [K][nel] <-> external [nel][K]
+void launch_ext_to_soa(const double* ext, double* soa, int K, int nel, hipStream_t st);
+void launch_soa_to_ext(const double* soa, double* ext, int K, int nel, hipStream_t st);
+void launch_fill(double* p, double v, size_t count, hipStream_t st);
+void launch_fill_bytes(void* p, size_t bytes, hipStream_t st);
+// transport boundary inputs: in_bc[c][e] (I rows) from the compact side layout
+void launch_bc_inputs(const DevProblem& dp, const double* bc, double* in_bc, hipStream_t st);
+void launch_ctrl_reset(Ctrl* c, hipStream_t st);
+void launch_cast(const double* src, void* dst, size_t count, int to_bf16, hipStream_t st);
+
+}  // namespace ehdg

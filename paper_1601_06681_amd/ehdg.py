@@ -1,0 +1,297 @@
+"""Python binding of the eHDG C ABI (include/ehdg.h): argument marshalling only.
+
+Every function below has the name of the C entry point it calls.  Device memory
+and streams come from PyTorch (ROCm); all computation happens in libehdg.so.
+`Problem` bundles a handle with its workspace tensor and samples closed-form data
+at the library's own reference points.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (EHDG_BF16_REFINE, EHDG_ERR_DIVERGED, EHDG_ERR_NOT_CONVERGED, EHDG_FP32_REFINE, EHDG_FP64,
+                   EHDG_OK, EHDG_SWE, EHDG_TRANSPORT, ehdg_desc)
+
+__all__ = [
+    "EhdgError", "Problem", "make_desc", *_lib.EXPORTED,
+    "EHDG_TRANSPORT", "EHDG_SWE", "EHDG_FP64", "EHDG_FP32_REFINE", "EHDG_BF16_REFINE",
+]
+
+
+class EhdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ehdg error {code}: {msg}")
+        self.code = code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check(rc, h=None, ok=(EHDG_OK,)):
+    if rc in ok:
+        return rc
+    lib = _lib.load()
+    msg = lib.ehdg_error_string(rc).decode()
+    if h is not None:
+        last = lib.ehdg_last_error(h).decode()
+        if last:
+            msg += f" ({last})"
+    raise EhdgError(rc, msg)
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_desc(pde, dim, n, L=(1.0, 1.0, 1.0), periodic=(0, 0, 0), degree=1, beta=(0.0, 0.0, 0.0), sigma=0.0,
+              Phi=1.0, dt=0.0, precision=EHDG_FP64, inner_sweeps=1):
+    d = ehdg_desc()
+    d.pde, d.dim, d.degree = int(pde), int(dim), int(degree)
+    for a in range(3):
+        d.n[a] = int(n[a]) if a < len(n) else 1
+        d.L[a] = float(L[a]) if a < len(L) else 1.0
+        d.periodic[a] = int(periodic[a]) if a < len(periodic) else 0
+        d.beta[a] = float(beta[a]) if a < len(beta) else 0.0
+    d.sigma, d.Phi, d.dt = float(sigma), float(Phi), float(dt)
+    d.precision, d.inner_sweeps = int(precision), int(inner_sweeps)
+    return d
+
+
+# ---------------------------------------------------------------------------- C ABI
+def ehdg_reference_points(degree):
+    lib = _lib.load()
+    x = np.zeros(degree + 1)
+    q = np.zeros(degree + 2)
+    w = np.zeros(degree + 2)
+    _check(lib.ehdg_reference_points(degree, x.ctypes.data_as(ctypes.c_void_p), q.ctypes.data_as(ctypes.c_void_p),
+                                     w.ctypes.data_as(ctypes.c_void_p)))
+    return x, q, w
+
+
+def ehdg_workspace_bytes(desc):
+    lib = _lib.load()
+    out = ctypes.c_size_t(0)
+    _check(lib.ehdg_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def ehdg_setup(desc, workspace, stream=None):
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    _check(lib.ehdg_setup(ctypes.byref(desc), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                          _stream_ptr(stream), ctypes.byref(h)))
+    return h
+
+
+def ehdg_set_forcing(h, forcing_q=None, bc=None):
+    _check(_lib.load().ehdg_set_forcing(h, _ptr(forcing_q), _ptr(bc)), h)
+
+
+def ehdg_set_initial(h, u0=None):
+    _check(_lib.load().ehdg_set_initial(h, _ptr(u0)), h)
+
+
+def ehdg_iterate(h, n_iters):
+    _check(_lib.load().ehdg_iterate(h, int(n_iters)), h)
+
+
+def ehdg_solve(h, rel_tol, max_iters, allow=(EHDG_OK,)):
+    it = ctypes.c_int32(0)
+    res = ctypes.c_double(0.0)
+    rc = _lib.load().ehdg_solve(h, float(rel_tol), int(max_iters), ctypes.byref(it), ctypes.byref(res))
+    _check(rc, h, ok=allow)
+    return rc, it.value, res.value
+
+
+def ehdg_step(h, n_steps, rel_tol, max_iters_per_step, allow=(EHDG_OK,)):
+    its = np.zeros(max(n_steps, 1), dtype=np.int32)
+    rc = _lib.load().ehdg_step(h, int(n_steps), float(rel_tol), int(max_iters_per_step),
+                               its.ctypes.data_as(ctypes.c_void_p))
+    _check(rc, h, ok=allow)
+    return rc, its[:n_steps].tolist()
+
+
+def ehdg_get_solution(h, out):
+    _check(_lib.load().ehdg_get_solution(h, _ptr(out)), h)
+
+
+def ehdg_get_residuals(h, first, count):
+    out = np.zeros(max(count, 1))
+    _check(_lib.load().ehdg_get_residuals(h, int(first), int(count), out.ctypes.data_as(ctypes.c_void_p)), h)
+    return out[:count]
+
+
+def ehdg_sizes(h):
+    n_el = ctypes.c_int64(0)
+    vals = [ctypes.c_int32(0) for _ in range(5)]
+    _check(_lib.load().ehdg_sizes(h, ctypes.byref(n_el), *[ctypes.byref(v) for v in vals]), h)
+    m, n_p, s, i, iters = (v.value for v in vals)
+    return dict(n_el=n_el.value, m=m, n_p=n_p, S=s, I=i, iters=iters)
+
+
+def ehdg_state_bytes(h):
+    out = ctypes.c_size_t(0)
+    _check(_lib.load().ehdg_state_bytes(h, ctypes.byref(out)), h)
+    return out.value
+
+
+def ehdg_get_state(h, dst):
+    _check(_lib.load().ehdg_get_state(h, _ptr(dst), dst.numel() * dst.element_size()), h)
+
+
+def ehdg_set_state(h, src):
+    _check(_lib.load().ehdg_set_state(h, _ptr(src), src.numel() * src.element_size()), h)
+
+
+def ehdg_destroy(h):
+    _check(_lib.load().ehdg_destroy(h))
+
+
+def ehdg_error_string(code):
+    return _lib.load().ehdg_error_string(int(code)).decode()
+
+
+def ehdg_last_error(h):
+    return _lib.load().ehdg_last_error(h).decode()
+
+
+# ---------------------------------------------------------------------------- convenience
+class Problem:
+    """A handle with its device workspace.  Closed-form data are sampled on the device
+    at the physical points implied by the library's reference points."""
+
+    def __init__(self, pde, dim, n, L=(1.0, 1.0, 1.0), periodic=(0, 0, 0), degree=1, beta=(0.0, 0.0, 0.0),
+                 sigma=0.0, Phi=1.0, dt=0.0, precision=EHDG_FP64, inner_sweeps=1, device="cuda", stream=None):
+        torch = _torch()
+        self.torch = torch
+        self.desc = make_desc(pde, dim, n, L, periodic, degree, beta, sigma, Phi, dt, precision, inner_sweeps)
+        self.pde, self.dim, self.p = pde, dim, degree
+        self.n = tuple(int(v) for v in n[:dim])
+        self.L = tuple(float(v) for v in L[:dim])
+        self.periodic = tuple(int(v) for v in periodic[:dim])
+        self.device = torch.device(device)
+        self.stream = stream
+        nbytes = ehdg_workspace_bytes(self.desc)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.h = ehdg_setup(self.desc, self.workspace, stream)
+        sz = ehdg_sizes(self.h)
+        self.nel, self.m, self.Np, self.S, self.I = sz["n_el"], sz["m"], sz["n_p"], sz["S"], sz["I"]
+        self.gll, self.gq, self.gw = ehdg_reference_points(degree)
+
+    def close(self):
+        if self.h is not None:
+            ehdg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- sampling points --------------------------------------------------------
+    def _elem_corners(self):
+        torch = self.torch
+        e = torch.arange(self.nel, device=self.device, dtype=torch.int64)
+        idx = []
+        r = e
+        for a in range(self.dim):
+            idx.append(r % self.n[a])
+            r = r // self.n[a]
+        h = [self.L[a] / self.n[a] for a in range(self.dim)]
+        return torch.stack([idx[a].double() * h[a] for a in range(self.dim)], dim=-1), h
+
+    def _tensor_ref(self, pts1d):
+        torch = self.torch
+        k = len(pts1d)
+        g = torch.tensor(pts1d, dtype=torch.float64, device=self.device)
+        grids = torch.meshgrid(*([g] * self.dim), indexing="ij")       # last axis fastest
+        return torch.stack([grids[self.dim - 1 - a].reshape(-1) for a in range(self.dim)], dim=-1)  # axis 0 fastest
+
+    def points(self, which="nodes"):
+        """Physical points (n_el, npts, dim): 'nodes' (GLL) or 'quad' (Gauss)."""
+        x0, h = self._elem_corners()
+        ref = self._tensor_ref(self.gll if which == "nodes" else self.gq)
+        hh = self.torch.tensor(h, dtype=self.torch.float64, device=self.device)
+        return x0[:, None, :] + (ref[None, :, :] + 1.0) * 0.5 * hh
+
+    def boundary_points(self):
+        """Face-node points of every non-periodic side, in the C ABI's bc layout: (nbc, dim)."""
+        torch = self.torch
+        out = []
+        h = [self.L[a] / self.n[a] for a in range(self.dim)]
+        g = torch.tensor(self.gll, dtype=torch.float64, device=self.device)
+        for side in range(2 * self.dim):
+            ax = side // 2
+            if self.periodic[ax]:
+                continue
+            tang = [t for t in range(self.dim) if t != ax]
+            # faces: tangential element indices (first fastest); nodes: tangential node indices
+            shape = [self.n[t] for t in tang]
+            fidx = torch.stack(torch.meshgrid(*[torch.arange(s, device=self.device) for s in shape[::-1]],
+                                              indexing="ij"), dim=-1).reshape(-1, len(tang)).flip(-1)
+            nidx = torch.stack(torch.meshgrid(*[torch.arange(self.p + 1, device=self.device)] * len(tang),
+                                              indexing="ij"), dim=-1).reshape(-1, len(tang)).flip(-1)
+            pts = torch.zeros(fidx.shape[0], nidx.shape[0], self.dim, dtype=torch.float64, device=self.device)
+            pts[..., ax] = 0.0 if side % 2 == 0 else self.L[ax]
+            for j, t in enumerate(tang):
+                pts[..., t] = fidx[:, None, j].double() * h[t] + (g[nidx[None, :, j]] + 1.0) * 0.5 * h[t]
+            out.append(pts.reshape(-1, self.dim))
+        if not out:
+            return torch.zeros(0, self.dim, dtype=torch.float64, device=self.device)
+        return torch.cat(out, dim=0)
+
+    # -- data ---------------------------------------------------------------------
+    def set_forcing(self, f_fns=None, g_fn=None):
+        """f_fns: list of callables (X, xp) -> values, one per field (or None); g_fn: inflow data."""
+        torch = self.torch
+        fq = None
+        if f_fns is not None:
+            X = self.points("quad")
+            fq = torch.stack([torch.as_tensor(fn(X, torch), dtype=torch.float64, device=self.device).expand(X.shape[:2])
+                              if fn is not None else torch.zeros(X.shape[:2], dtype=torch.float64,
+                                                                 device=self.device) for fn in f_fns], dim=1)
+            fq = fq.contiguous()
+        bc = None
+        if g_fn is not None:
+            Xb = self.boundary_points()
+            bc = g_fn(Xb, torch).to(torch.float64).contiguous() if Xb.shape[0] else None
+        ehdg_set_forcing(self.h, fq, bc)
+
+    def set_initial(self, u0=None):
+        """u0: tensor (n_el, m, N_p), list of callables per field, or None."""
+        torch = self.torch
+        if u0 is not None and not isinstance(u0, torch.Tensor):
+            X = self.points("nodes")
+            u0 = torch.stack([fn(X, torch).to(torch.float64) for fn in u0], dim=1).contiguous()
+        ehdg_set_initial(self.h, u0)
+
+    def solution(self):
+        out = self.torch.empty(self.nel, self.m, self.Np, dtype=self.torch.float64, device=self.device)
+        ehdg_get_solution(self.h, out)
+        return out
+
+    def iterate(self, n):
+        ehdg_iterate(self.h, n)
+
+    def solve(self, tol, max_iters=100000, allow=(EHDG_OK,)):
+        return ehdg_solve(self.h, tol, max_iters, allow)
+
+    def step(self, n_steps, tol, max_iters=100000, allow=(EHDG_OK,)):
+        return ehdg_step(self.h, n_steps, tol, max_iters, allow)
+
+    def residuals(self, first, count):
+        return ehdg_get_residuals(self.h, first, count)
+
+    def iters(self):
+        return ehdg_sizes(self.h)["iters"]

@@ -1,0 +1,237 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (FP64 path): every iterate k equal to the oracle's iterate k within 1e-12
+relative (max-norm over the mesh, relative to the largest value); converged
+solutions within 1e-10 relative with the same iteration count.  Both sides run the
+same number of sweeps on the same closed-form inputs; their only difference is
+rounding (the library applies precomputed condensed operators, the oracle solves
+with an LU factorisation every sweep), so agreement is expected at ~1e-14.
+"""
+import numpy as np
+import pytest
+
+from oracle import ehdg as O
+from tests._cases import (gpu_transport, oracle_swe, oracle_transport, rel_err, swe_initial_fns,
+                          swe_random_fns)
+
+pytestmark = pytest.mark.gpu
+
+ITER_TOL = 1e-12
+CONV_TOL = 1e-10
+
+
+def _gpu_u(prob):
+    return prob.solution().cpu().numpy().reshape(prob.nel, -1)
+
+
+# ------------------------------------------------------------------ transport 2D
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("beta", [(1.0, 0.5), (-0.8, 0.3), (0.4, -1.1), (-0.6, -0.9), (1.0, 0.0), (0.0, -0.7)])
+def test_transport2d_iterates(p, beta):
+    n, L = (13, 7), (1.0, 0.8)
+    op, F, _, _ = oracle_transport(n, L, p, beta, 1.0)
+    prob = gpu_transport(n, L, p, beta, 1.0)
+    u = np.zeros((op.mesh.nel, op.ref.Np))
+    done = 0
+    for k in (1, 2, 5, 9):
+        u, _ = O.iterate(op, F, u, k - done)
+        prob.iterate(k - done)
+        done = k
+        assert rel_err(_gpu_u(prob), u) < ITER_TOL, (k, rel_err(_gpu_u(prob), u))
+
+
+@pytest.mark.parametrize("n", [(8, 8), (37, 29), (64, 5)])
+def test_transport2d_converged_c1(n):
+    """The 8 x 8 degree-2 workload (and larger ragged meshes) solved to 1e-10."""
+    p, beta, sigma = 2, (1.0, 0.5), 1.0
+    op, F, ue, _ = oracle_transport(n, (1.0, 1.0), p, beta, sigma)
+    ref = O.solve(op, F, np.zeros((op.mesh.nel, op.ref.Np)), tol=1e-10, max_iter=5000)
+    prob = gpu_transport(n, (1.0, 1.0), p, beta, sigma)
+    rc, iters, res = prob.solve(1e-10, 5000)
+    assert iters == ref["iters"]
+    assert rel_err(_gpu_u(prob), ref["u"]) < CONV_TOL
+    hist = prob.residuals(0, iters)
+    np.testing.assert_allclose(hist, ref["hist"], rtol=1e-6, atol=1e-14)
+
+
+# ------------------------------------------------------------------ transport 3D
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("beta", [(1.0, 0.7, 0.3), (-0.5, 0.9, -0.4), (0.0, 1.0, -0.6)])
+def test_transport3d_iterates(p, beta):
+    n, L = (9, 7, 5), (1.0, 1.0, 0.7)
+    op, F, _, _ = oracle_transport(n, L, p, beta, 1.0)
+    prob = gpu_transport(n, L, p, beta, 1.0)
+    u = np.zeros((op.mesh.nel, op.ref.Np))
+    done = 0
+    for k in (1, 3, 7):
+        u, _ = O.iterate(op, F, u, k - done)
+        prob.iterate(k - done)
+        done = k
+        assert rel_err(_gpu_u(prob), u) < ITER_TOL, (k, rel_err(_gpu_u(prob), u))
+
+
+def test_transport3d_converged_small_c3():
+    n, p, beta, sigma = (6, 6, 6), 3, (1.0, 0.7, 0.3), 1.0
+    op, F, _, _ = oracle_transport(n, (1.0, 1.0, 1.0), p, beta, sigma)
+    ref = O.solve(op, F, np.zeros((op.mesh.nel, op.ref.Np)), tol=1e-8, max_iter=5000)
+    prob = gpu_transport(n, (1.0, 1.0, 1.0), p, beta, sigma)
+    rc, iters, res = prob.solve(1e-8, 5000)
+    assert iters == ref["iters"]
+    assert rel_err(_gpu_u(prob), ref["u"]) < CONV_TOL
+
+
+def test_transport_periodic_axis():
+    """A periodic axis closes the upwind chain into a cycle (no boundary data on it)."""
+    n, p, beta = (10, 6), 2, (0.9, -0.4)
+    op, F, _, _ = oracle_transport(n, (1.0, 1.0), p, beta, 2.0, periodic=(True, False), manufactured=False)
+    rng = np.random.default_rng(4)
+    u0 = rng.standard_normal((op.mesh.nel, op.ref.Np))
+    import torch
+    prob = gpu_transport(n, (1.0, 1.0), p, beta, 2.0, periodic=(1, 0, 0), manufactured=False)
+    prob.set_initial(torch.tensor(u0.reshape(op.mesh.nel, 1, -1), device="cuda"))
+    u, _ = O.iterate(op, F, u0, 6)
+    prob.iterate(6)
+    assert rel_err(_gpu_u(prob), u) < ITER_TOL
+
+
+# ------------------------------------------------------------------ backward Euler transport
+def test_transport_backward_euler_steps():
+    import torch
+    n, p, beta, dt = (10, 8), 3, (0.6, -0.8), 0.02
+    op, F, ue, f = oracle_transport(n, (1.0, 1.0), p, beta, 0.5, dt=dt)
+    u0 = op.interpolate(lambda X: np.cos(3 * X[..., 0]) * np.sin(2 * X[..., 1]))
+    load = lambda um: op.load(lambda X: f(X, np), um)
+    ref_u, ref_its = O.be_steps(op, u0, 4, tol=1e-10, load=load)
+    prob = gpu_transport(n, (1.0, 1.0), p, beta, 0.5, dt=dt)
+    prob.set_initial(torch.tensor(u0.reshape(op.mesh.nel, 1, -1), device="cuda"))
+    rc, its = prob.step(4, 1e-10, 1000)
+    assert its == ref_its
+    assert rel_err(_gpu_u(prob), ref_u) < CONV_TOL
+
+
+# ------------------------------------------------------------------ shallow water
+def _gpu_swe(n, p, Phi, dt, periodic=True, L=(1.0, 1.0), precision=0, inner=1):
+    from paper_1601_06681_amd.ehdg import EHDG_SWE, Problem
+    per = (1, 1, 0) if periodic else (0, 0, 0)
+    return Problem(EHDG_SWE, 2, n, L=L, periodic=per, degree=p, Phi=Phi, dt=dt, precision=precision,
+                   inner_sweeps=inner)
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_swe_iterates(p, periodic):
+    n, Phi, dt = (11, 9), 1.3, 2e-3
+    op = oracle_swe(n, p, Phi, dt, periodic)
+    fns = swe_random_fns(p)
+    u0 = op.interpolate([lambda X, fn=fn: fn(X, np) for fn in fns])
+    F = op.load(u0)
+    prob = _gpu_swe(n, p, Phi, dt, periodic)
+    prob.set_initial(fns)
+    u = u0
+    done = 0
+    for k in (1, 2, 6):
+        u, _ = O.iterate(op, F, u, k - done)
+        prob.iterate(k - done)
+        done = k
+        assert rel_err(_gpu_u(prob), u) < ITER_TOL, (k, rel_err(_gpu_u(prob), u))
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_swe_steps_hump(periodic):
+    n, p, Phi, dt = (16, 16), 4, 1.0, 1e-3
+    op = oracle_swe(n, p, Phi, dt, periodic)
+    fns = swe_initial_fns(0)
+    u0 = op.interpolate([lambda X, fn=fn: fn(X, np) for fn in fns])
+    ref_u, ref_its = O.be_steps(op, u0, 5, tol=1e-10)
+    prob = _gpu_swe(n, p, Phi, dt, periodic)
+    prob.set_initial(fns)
+    rc, its = prob.step(5, 1e-10, 1000)
+    assert its == ref_its
+    assert rel_err(_gpu_u(prob), ref_u) < CONV_TOL
+
+
+# ------------------------------------------------------------------ mixed precision
+@pytest.mark.parametrize("inner", [1, 3, 8])
+def test_fp32_refine_transport(inner):
+    """FP32 correction sweeps + FP64 residual refinement reach the FP64 fixed point
+    within 1e-8 relative."""
+    n, p, beta, sigma = (16, 16), 3, (1.0, 0.5), 1.0
+    op, F, _, _ = oracle_transport(n, (1.0, 1.0), p, beta, sigma)
+    ref = O.solve(op, F, np.zeros((op.mesh.nel, op.ref.Np)), tol=1e-14, max_iter=20000)
+    prob = gpu_transport(n, (1.0, 1.0), p, beta, sigma, precision=1, inner=inner)
+    rc, iters, res = prob.solve(1e-11, 20000)
+    assert res < 1e-11
+    assert rel_err(_gpu_u(prob), ref["u"]) < 1e-8
+
+
+def test_fp32_refine_swe_steps():
+    n, p, Phi, dt = (16, 16), 4, 1.0, 1e-3
+    op = oracle_swe(n, p, Phi, dt, True)
+    fns = swe_initial_fns(0)
+    u0 = op.interpolate([lambda X, fn=fn: fn(X, np) for fn in fns])
+    ref_u, _ = O.be_steps(op, u0, 3, tol=1e-14)
+    prob = _gpu_swe(n, p, Phi, dt, True, precision=1, inner=4)
+    prob.set_initial(fns)
+    prob.step(3, 1e-11, 2000)
+    assert rel_err(_gpu_u(prob), ref_u) < 1e-8
+
+
+# ------------------------------------------------------------------ semantics
+def test_deterministic_and_resumable():
+    """Bitwise repeatable; iterate 20 + checkpoint + resume 20 == iterate 40."""
+    import torch
+    from paper_1601_06681_amd import ehdg as E
+    n, p, beta = (21, 17), 3, (1.0, 0.5)
+    a = gpu_transport(n, (1.0, 1.0), p, beta, 1.0)
+    a.iterate(40)
+    ua = a.solution()
+    b = gpu_transport(n, (1.0, 1.0), p, beta, 1.0)
+    b.iterate(40)
+    assert torch.equal(ua, b.solution())
+    c = gpu_transport(n, (1.0, 1.0), p, beta, 1.0)
+    c.iterate(20)
+    blob = torch.empty(E.ehdg_state_bytes(c.h), dtype=torch.uint8, device="cuda")
+    E.ehdg_get_state(c.h, blob)
+    d = gpu_transport(n, (1.0, 1.0), p, beta, 1.0)
+    E.ehdg_set_state(d.h, blob)
+    d.iterate(20)
+    assert torch.equal(ua, d.solution())
+
+
+def test_divergence_and_iteration_cap_are_reported():
+    from paper_1601_06681_amd import ehdg as E
+    # dt (p+1)(p+2)/h = 1e-2 * 30 * 32 = 9.6: the shallow-water iteration diverges
+    prob = _gpu_swe((32, 32), 4, 1.0, 1e-2, True)
+    prob.set_initial(swe_initial_fns(0))
+    rc, iters, res = prob.solve(1e-10, 5000, allow=(E.EHDG_ERR_DIVERGED,))
+    assert rc == E.EHDG_ERR_DIVERGED and not np.isfinite(res)
+    c1 = gpu_transport((8, 8), (1.0, 1.0), 2, (1.0, 0.5), 1.0)
+    rc, iters, res = c1.solve(1e-10, 5, allow=(E.EHDG_ERR_NOT_CONVERGED,))
+    assert rc == E.EHDG_ERR_NOT_CONVERGED and iters == 5
+
+
+# ------------------------------------------------------------------ full-size workloads
+def test_swe_full_size_first_sweeps():
+    """256^2, degree 4 (the shallow-water benchmark mesh): three sweeps from the
+    Gaussian hump, every element compared with the oracle."""
+    from paper_1601_06681_amd import workloads as W
+    cfg = W.SWE2D
+    op = oracle_swe(cfg["n"], cfg["degree"], cfg["Phi"], cfg["dt"], True)
+    fns = swe_initial_fns(cfg["seed"])
+    u0 = op.interpolate([lambda X, fn=fn: fn(X, np) for fn in fns])
+    u, _ = O.iterate(op, op.load(u0), u0, 3)
+    prob = _gpu_swe(cfg["n"], cfg["degree"], cfg["Phi"], cfg["dt"], True)
+    prob.set_initial(fns)
+    prob.iterate(3)
+    assert rel_err(_gpu_u(prob), u) < ITER_TOL
+
+
+def test_transport3d_full_size_first_sweeps():
+    """64^3, degree 3 (the 3D benchmark mesh): three sweeps, every element compared."""
+    from paper_1601_06681_amd import workloads as W
+    cfg = W.TRANSPORT3D
+    op, F, _, _ = oracle_transport(cfg["n"], cfg["L"], cfg["degree"], cfg["beta"], cfg["sigma"])
+    u, _ = O.iterate(op, F, np.zeros((op.mesh.nel, op.ref.Np)), 3)
+    prob = gpu_transport(cfg["n"], cfg["L"], cfg["degree"], cfg["beta"], cfg["sigma"])
+    prob.iterate(3)
+    assert rel_err(_gpu_u(prob), u) < ITER_TOL
