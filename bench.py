@@ -1,0 +1,199 @@
+"""Benchmark of the eHDG hot path on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload swe2d|transport3d|transport2d]
+                [--no-cpu-baseline] [--no-forms]
+
+A step is one backward-Euler time step of the linearized shallow-water workload
+(256 x 256 periodic quads, degree 4, 3 fields, 4 915 200 DOFs): build the step's
+right-hand side, sweep the eHDG iteration (gather neighbour traces, apply the
+condensed local operator, write new traces, FP64 residual) until the relative trace
+increment is below 1e-10, recover the element solution.  K = 20 steps is the whole
+workload.  The printed value is whole-job throughput: DOFs x sweeps / wall time of
+the K timed steps, inputs resident in HBM.
+
+One JSON line on stdout; progress on stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+FP64_PEAK = 78.6e12        # MI355X FP64 vector / matrix, flop/s
+BF16_PEAK = 2.5e15
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_src_sha():
+    with open(os.path.join(ROOT, "paper_1601_06681_amd", "csrc", "kernels.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_tag, per_launch_alg_bytes):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_src_sha") != kernel_src_sha():
+        return None
+    return d.get("hbm_bytes_per_dispatch")
+
+
+def swe_problem(cfg, precision=0, inner=1):
+    from paper_1601_06681_amd.ehdg import EHDG_SWE, Problem
+    return Problem(EHDG_SWE, 2, cfg["n"], L=cfg["L"], periodic=(1, 1, 0), degree=cfg["degree"], Phi=cfg["Phi"],
+                   dt=cfg["dt"], precision=precision, inner_sweeps=inner)
+
+
+def time_sweeps(torch, prob, n):
+    """Average duration of one sweep launch over n back-to-back sweeps, HIP events on
+    the stream the library launches on (torch's current stream)."""
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    prob.iterate(2)
+    torch.cuda.synchronize()
+    e0.record(st)
+    prob.iterate(n)
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / n
+
+
+def cpu_baseline_swe(cfg, fns, target_s=15.0):
+    """The oracle (numpy FP64 volume form) on whole backward-Euler steps of the same
+    workload, as many as fit in about target_s seconds."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import ehdg as O
+    from oracle.mesh import StructuredMesh
+    from oracle.swe import ShallowWater
+    mesh = StructuredMesh(cfg["n"], L=cfg["L"], periodic=(True, True))
+    op = ShallowWater(mesh, cfg["degree"], cfg["Phi"], cfg["dt"])
+    u = op.interpolate([lambda X, fn=fn: fn(X, np) for fn in fns])
+    dofs = mesh.nel * 3 * op.ref.Np
+    sweeps, steps = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < target_s and steps < cfg["steps"]:
+        out = O.solve(op, op.load(u), u, tol=cfg["tol"], max_iter=1000)
+        u = out["u"]
+        sweeps += out["iters"]
+        steps += 1
+    dt = time.perf_counter() - t0
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    return {"value": dofs * sweeps / dt, "unit": "DOF-updates/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{steps} backward-Euler steps ({sweeps} sweeps) of the same 256x256 p=4 workload, "
+                      f"numpy FP64 volume-form Algorithm 1, {dt:.1f} s"}
+
+
+def run_swe(args, torch):
+    from paper_1601_06681_amd import workloads as W
+    cfg = W.SWE2D
+    fns = W.gaussian_hump(W.hump_centre(cfg["seed"]))
+    prob = swe_problem(cfg)
+    dofs = prob.nel * prob.m * prob.Np
+    log(f"[bench] swe2d {cfg['n']} p={cfg['degree']} dofs={dofs} dt={cfg['dt']}")
+    # warmup
+    prob.set_initial(fns)
+    if args.warmup:
+        prob.step(args.warmup, cfg["tol"], 1000)
+    prob.set_initial(fns)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, its = prob.step(args.steps, cfg["tol"], 1000)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sweeps = int(sum(its))
+    value = dofs * sweeps / wall
+    log(f"[bench] {args.steps} steps, {sweeps} sweeps, {wall * 1e3:.3f} ms, {value:.3e} DOF-updates/s")
+    u64 = prob.solution()
+
+    # roofline of the dominant kernel (the FP64 sweep)
+    t_sweep = time_sweeps(torch, prob, 200)
+    S, nel = prob.S, prob.nel
+    alg_bytes = 3 * S * 8 * nel            # read own state, read g, write new state (neighbour reads cached)
+    achieved = alg_bytes / t_sweep
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK,
+                "traffic": traffic_from_profiles("swe_sweep_p4_256x256", alg_bytes),
+                "kernel": "k_sweep<SweFam<5>, double> (FP64 sweep, residual fused)",
+                "alg_bytes_per_launch": alg_bytes, "avg_launch_us": t_sweep * 1e6}
+    log(f"[bench] sweep {t_sweep * 1e6:.2f} us/launch, {achieved / 1e9:.0f} GB/s algorithmic")
+
+    out = {
+        "metric": "DOF-updates/s per eHDG iteration", "value": value, "unit": "DOF-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / max(args.steps, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg["name"], "mesh": "256x256 periodic unit square", "degree": cfg["degree"],
+                   "fields": 3, "dofs": dofs, "Phi": cfg["Phi"], "dt": cfg["dt"], "dt_stated": cfg["dt_stated"],
+                   "rho_at_stated_dt": 7.68, "be_steps": args.steps, "rel_tol": cfg["tol"], "sweeps": sweeps,
+                   "iters_per_step": its},
+        "roofline": roofline,
+    }
+    if not args.no_forms:
+        forms = {}
+        for inner in (4,):
+            p32 = swe_problem(cfg, precision=1, inner=inner)
+            p32.set_initial(fns)
+            if args.warmup:
+                p32.step(args.warmup, cfg["tol"], 1000)
+            p32.set_initial(fns)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, its32 = p32.step(args.steps, cfg["tol"], 1000)
+            torch.cuda.synchronize()
+            w32 = time.perf_counter() - t0
+            err = float(((p32.solution() - u64).abs().max() / u64.abs().max()).item())
+            forms[f"fp32_refine_s{inner}"] = {
+                "value": dofs * sum(its32) / w32, "ms_per_step": w32 * 1e3 / max(args.steps, 1),
+                "equivalent_sweeps": int(sum(its32)), "rel_err_vs_fp64_form": err,
+                "speedup_vs_fp64_form": wall / w32}
+            log(f"[bench] fp32 refine s={inner}: {w32 * 1e3:.3f} ms, err vs fp64 {err:.2e}")
+            p32.close()
+        out["forms"] = forms
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline_swe(cfg, fns)
+        log(f"[bench] cpu baseline {out['cpu_baseline']['value']:.3e} DOF-updates/s")
+    prob.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="swe2d")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the eHDG sweep of one mesh is measured "
+                                   "on a single MI355X (multi-GPU sharding is a design, not a measured path)"}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    torch.cuda.init()
+    if args.workload != "swe2d":
+        print(json.dumps({"error": f"unknown workload {args.workload}"}))
+        sys.exit(2)
+    out = run_swe(args, torch)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -28,14 +28,16 @@ struct ehdg_problem {
   double* Bfull = nullptr;  // n x (m * nq_el), block diagonal load matrix
   double* scratch = nullptr;
   int base = 0;        // buffer holding the trace state s^0 of the current solve
-  int recovered = -1;  // sweep count for which u_new holds the recovered solution
+  int recovered = -1;  // 1 when u_new holds the solution of the current iterate
+  bool fresh = false;  // the control block is known to be reset (no sweep since)
+  int predict = 4;     // sweeps the next solve is expected to need (last count)
+  int predict_outer = 2;  // refinements the next mixed-precision solve is expected to need
   std::string err;
 };
 
 namespace {
 
 constexpr int kHistCap = 1 << 16;
-constexpr int kBlockHost = 256;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -68,7 +70,8 @@ Desc to_desc(const ehdg_desc* d) {
 }
 
 struct Layout {
-  size_t off_ctrl, off_partials, off_hist, off_T64, off_T32, off_T16, off_R, off_Q, off_W, off_P, off_G, off_B;
+  size_t off_ctrl, off_partials, off_hist, off_T64, off_T32, off_T16, off_R, off_Q, off_W, off_P, off_G, off_B,
+      off_Mv, off_gbe;
   size_t off_s0, off_s1, off_g, off_gsrc, off_wsrc, off_u, off_unew, off_lo0, off_lo1, off_rlo0, off_rlo1, off_scratch;
   size_t total;
 };
@@ -81,14 +84,17 @@ Layout layout_for(const Operators& o, long long nel, bool lowp) {
     off += align256(bytes);
     return at;
   };
-  const size_t nb = (size_t)((nel + kBlockHost - 1) / kBlockHost);
+  const size_t nb = (size_t)((nel + kElemsPerGroup - 1) / kElemsPerGroup);
   const size_t S = o.S, I = o.I, n = o.n, ne = (size_t)nel;
+  const size_t Sp = (size_t)padded_rows(o.S);
   L.off_ctrl = take(sizeof(Ctrl));
   L.off_partials = take(2 * nb * sizeof(double));
   L.off_hist = take(kHistCap * sizeof(double));
-  L.off_T64 = take(S * I * 8);
-  L.off_T32 = take(S * I * 4);
-  L.off_T16 = take(S * I * 2);
+  L.off_T64 = take(Sp * I * 8);
+  L.off_T32 = take(Sp * I * 4);
+  L.off_T16 = take(Sp * I * 2);
+  L.off_Mv = take((size_t)padded_rows(o.Mvol.r) * o.Mvol.c * 8);
+  L.off_gbe = take(o.be ? S * ne * 8 : 8);
   L.off_R = take(n * I * 8);
   L.off_Q = take(S * n * 8);
   L.off_W = take(n * n * 8);
@@ -155,9 +161,12 @@ void rebuild_g(ehdg_problem* h) {
 }
 
 // Sweeps until the device flag is raised or max_iters; returns the Ctrl snapshot.
+// The first batch launches as many sweeps as the previous solve needed (warm-started
+// time steps need about the same count); later batches grow geometrically.  Sweeps
+// launched after convergence exit at once on the device flag.
 int run_plain(ehdg_problem* h, double tol, int max_iters, Ctrl& c) {
   DevProblem& dp = h->dp;
-  int launched = 0, chunk = 4;
+  int launched = 0, chunk = std::max(1, h->predict), next = 2;
   for (;;) {
     const int n = std::min(chunk, max_iters - launched);
     for (int j = 0; j < n; ++j) h->ks->sweep64(dp, h->base + launched + j, true, tol, h->stream);
@@ -166,8 +175,12 @@ int run_plain(ehdg_problem* h, double tol, int max_iters, Ctrl& c) {
     if (rc) return rc;
     rc = read_ctrl(h, c);
     if (rc) return rc;
-    if (c.done || launched >= max_iters) return EHDG_OK;
-    chunk = std::min(chunk * 2, 64);
+    if (c.done || launched >= max_iters) {
+      if (c.status == 1) h->predict = c.iters;
+      return EHDG_OK;
+    }
+    chunk = next;
+    next = std::min(next * 2, 64);
   }
 }
 
@@ -177,7 +190,7 @@ int run_refine(ehdg_problem* h, double tol, int max_outer, Ctrl& c) {
   auto refine = bf ? h->ks->refine16 : h->ks->refine32;
   auto inner = bf ? h->ks->inner16 : h->ks->inner32;
   const int s = h->desc.inner_sweeps;
-  int launched = 0, chunk = 2;
+  int launched = 0, chunk = std::max(1, h->predict_outer), next = 2;
   const void* lo_prev = nullptr;
   for (;;) {
     const int n = std::min(chunk, max_outer - launched);
@@ -200,8 +213,12 @@ int run_refine(ehdg_problem* h, double tol, int max_outer, Ctrl& c) {
     if (rc) return rc;
     rc = read_ctrl(h, c);
     if (rc) return rc;
-    if (c.done || launched >= max_outer) return EHDG_OK;
-    chunk = std::min(chunk * 2, 32);
+    if (c.done || launched >= max_outer) {
+      if (c.status == 1) h->predict_outer = c.iters;
+      return EHDG_OK;
+    }
+    chunk = next;
+    next = std::min(next * 2, 32);
   }
 }
 
@@ -213,10 +230,14 @@ int solve_current(ehdg_problem* h, double tol, int max_iters, int* iters_out, do
   // a new segment starts from the latest state: after j sweeps (or refinements)
   // of the previous segment it sits in buffer (base + j) & 1
   Ctrl c;
-  int rc = read_ctrl(h, c);
-  if (rc) return rc;
-  h->base = (h->base + c.iters) & 1;
-  launch_ctrl_reset(dp.ctrl, h->stream);
+  int rc;
+  if (!h->fresh) {
+    rc = read_ctrl(h, c);
+    if (rc) return rc;
+    h->base = (h->base + c.iters) & 1;
+    launch_ctrl_reset(dp.ctrl, h->stream);
+  }
+  h->fresh = false;
   const bool mixed = h->desc.precision != EHDG_FP64;
   if (!mixed) {
     rc = run_plain(h, tol, max_iters, c);
@@ -324,6 +345,9 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   dp.T32 = (const float*)(ws + L.off_T32);
   dp.T16 = (const uint16_t*)(ws + L.off_T16);
   dp.R = (const double*)(ws + L.off_R);
+  dp.Mvol = (const double*)(ws + L.off_Mv);
+  dp.gbe = (double*)(ws + L.off_gbe);
+  dp.has_src = false;
   dp.P = (const double*)(ws + L.off_P);
   dp.G = (const double*)(ws + L.off_G);
   dp.s[0] = (double*)(ws + L.off_s0);
@@ -342,9 +366,14 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   h->Bfull = (double*)(ws + L.off_B);
   h->scratch = (double*)(ws + L.off_scratch);
   int rc = 0;
-  const size_t SI = (size_t)o.S * o.I;
-  // operators (FP64 host -> device) and their low-precision copies
-  if ((rc = upload(h, (void*)dp.T64, o.T.a.data(), SI * 8)) ||
+  const size_t SI = (size_t)padded_rows(o.S) * o.I;
+  // operators (FP64 host -> device, rows zero-padded to whole row groups) and the
+  // low-precision copies of T
+  std::vector<double> Tpad(SI, 0.0), Mvpad((size_t)padded_rows(o.Mvol.r) * o.Mvol.c, 0.0);
+  std::copy(o.T.a.begin(), o.T.a.end(), Tpad.begin());
+  std::copy(o.Mvol.a.begin(), o.Mvol.a.end(), Mvpad.begin());
+  if ((rc = upload(h, (void*)dp.T64, Tpad.data(), SI * 8)) ||
+      (rc = upload(h, (void*)dp.Mvol, Mvpad.data(), Mvpad.size() * 8)) ||
       (rc = upload(h, (void*)dp.R, o.R.a.data(), (size_t)o.n * o.I * 8)) ||
       (rc = upload(h, h->Q, o.Q.a.data(), (size_t)o.S * o.n * 8)) ||
       (rc = upload(h, h->W, o.W.a.data(), (size_t)o.n * o.n * 8))) {
@@ -406,6 +435,12 @@ int ehdg_set_forcing(ehdg_handle h, const double* d_forcing_q, const double* d_b
     launch_matvec(dp.R, o.n, o.I, h->scratch, dp.w_src, nel, true, st);
   }
   launch_matvec(h->Q, o.S, o.n, dp.w_src, dp.g_src, nel, false, st);
+  dp.has_src = d_forcing_q != nullptr || d_bc != nullptr;
+  if (dp.be) {
+    // source part of the next step's g: Q A^{-1} (F_src + Mbt A^{-1} F_src)
+    hipMemcpyAsync(dp.gbe, dp.g_src, (size_t)o.S * nel * 8, hipMemcpyDeviceToDevice, st);
+    launch_matvec(dp.G, o.S, o.n, dp.w_src, dp.gbe, nel, true, st);
+  }
   rebuild_g(h);
   h->recovered = -1;
   return check_launch(h);
@@ -424,6 +459,7 @@ int ehdg_set_initial(ehdg_handle h, const double* d_u0) {
   rebuild_g(h);
   launch_ctrl_reset(dp.ctrl, h->stream);
   h->recovered = -1;
+  h->fresh = true;
   return check_launch(h);
 }
 
@@ -440,6 +476,7 @@ int ehdg_iterate(ehdg_handle h, int32_t n_iters) {
   }
   for (int j = 0; j < n_iters; ++j) h->ks->sweep64(h->dp, h->base + c.iters + j, true, -1.0, h->stream);
   h->recovered = -1;
+  h->fresh = false;
   return check_launch(h);
 }
 
@@ -470,11 +507,12 @@ int ehdg_step(ehdg_handle h, int32_t n_steps, double rel_tol, int32_t max_iters_
     int rc = solve_current(h, rel_tol, max_iters_per_step, &K, &res, &rec, &nb);
     if (iters_per_step) iters_per_step[s] = K;
     if (rc) return rc;
-    // u^{m+1} from the last local solve; next step's g from it; warm start from the last traces
+    // u^{m+1} from the last local solve, the next step's g from it, and the control
+    // block reset (one kernel); warm start from the last traces
     h->ks->volume(h->dp, h->dp.s[rec], true, h->stream);
     std::swap(h->dp.u, h->dp.u_new);
     h->base = nb;
-    launch_ctrl_reset(h->dp.ctrl, h->stream);
+    h->fresh = true;
     h->recovered = -1;
     rc = check_launch(h);
     if (rc) return rc;
@@ -574,6 +612,7 @@ int ehdg_set_state(ehdg_handle h, const void* d_src, size_t bytes) {
   h->base = base_host;
   rebuild_g(h);
   h->recovered = -1;
+  h->fresh = false;
   return check_launch(h);
 }
 

@@ -5,6 +5,13 @@
 
 namespace ehdg {
 
+// Elements per workgroup (one per lane of a wavefront) and wavefronts per
+// workgroup; each wavefront applies a block of ceil(rows / kRowGroups) operator rows,
+// so operators are stored with their row count padded to a multiple of kRowGroups.
+constexpr int kElemsPerGroup = 64;
+constexpr int kRowGroups = 4;
+inline int padded_rows(int rows) { return (rows + kRowGroups - 1) / kRowGroups * kRowGroups; }
+
 // Device-resident iteration control, one per handle.
 struct Ctrl {
   int done;          // set once the stopping test holds (or the increment is non-finite)
@@ -35,6 +42,9 @@ struct DevProblem {
   const double* R;         // n x I
   const double* P;         // n x n (BE)
   const double* G;         // S x n (BE)
+  const double* Mvol;      // recovery: steady R (n x I); BE [[P, R], [G P, G R]]; rows padded
+  double* gbe;             // BE source part of the next g: g_src + G w_src  (S)
+  bool has_src;            // forcing or boundary data present (w_src, g_src nonzero)
   double* s[2];            // trace state, double buffered
   double* g;               // S
   double* g_src;           // S
@@ -53,8 +63,9 @@ struct DevProblem {
 struct KernelSet {
   // s[k&1] -> s[(k+1)&1]; with resid, a relative-increment reduction (tol < 0: never stops)
   void (*sweep64)(const DevProblem&, int k, bool resid, double tol, hipStream_t);
-  // u_new = w_src + R in(s_prev) (+ P u for BE); BE: g = g_src + G u_new
-  void (*volume)(const DevProblem&, const double* s_prev, bool update_g, hipStream_t);
+  // u_new = w_src + R in(s_prev) (+ P u for BE).  With step (BE): also the next
+  // step's g = g_src + G u_new, and the iteration control is reset for that step.
+  void (*volume)(const DevProblem&, const double* s_prev, bool step, hipStream_t);
   // mixed precision outer step: s_out = s_in + lo_in (lo_in may be null);
   // r = g + T in(s_out) - s_out in FP64; r_out = r in the low precision (it is also
   // the first inner iterate); residual reduction of ||r|| / ||s_out + r||

@@ -36,22 +36,48 @@ __device__ __forceinline__ int remap_block(int b, int nb) {
   return xcd * per + min(xcd, rem) + idx;
 }
 
-__device__ __forceinline__ void coords(const MeshDev& m, int e, int c[3]) {
-  c[0] = e % m.n[0];
+// element coordinates (i0, i1, i2) of e
+struct Ijk {
+  int c0, c1, c2;
+};
+
+__device__ __forceinline__ Ijk coords(const MeshDev& m, int e) {
+  Ijk c;
+  c.c0 = e % m.n[0];
   const int r = e / m.n[0];
-  c[1] = r % m.n[1];
-  c[2] = r / m.n[1];
+  c.c1 = r % m.n[1];
+  c.c2 = r / m.n[1];
+  return c;
 }
 
-// neighbour of e one step along `axis` (wrapping on periodic axes), -1 outside
-__device__ __forceinline__ int neighbour(const MeshDev& m, int e, const int c[3], int axis, int step) {
-  int v = c[axis] + step;
-  const int stride = axis == 0 ? 1 : (axis == 1 ? m.n[0] : m.n[0] * m.n[1]);
-  if (v < 0 || v >= m.n[axis]) {
-    if (!m.periodic[axis]) return -1;
-    v = v < 0 ? v + m.n[axis] : v - m.n[axis];
+__device__ __forceinline__ int sel3(int a0, int a1, int a2, int i) {
+  return a0 * (int)(i == 0) + a1 * (int)(i == 1) + a2 * (int)(i == 2);
+}
+
+// neighbour of e one step along `axis` (wrapping on periodic axes), -1 outside.
+// Written with selects: indexing a register array by a runtime axis would move it to scratch.
+__device__ __forceinline__ int neighbour(const MeshDev& m, int e, const Ijk& c, int axis, int step) {
+  const int ci = sel3(c.c0, c.c1, c.c2, axis);
+  const int ni = sel3(m.n[0], m.n[1], m.n[2], axis);
+  const int per = sel3(m.periodic[0], m.periodic[1], m.periodic[2], axis);
+  const int stride = sel3(1, m.n[0], m.n[0] * m.n[1], axis);
+  int v = ci + step;
+  if (v < 0 || v >= ni) {
+    if (!per) return -1;
+    v = v < 0 ? v + ni : v - ni;
   }
-  return e + (v - c[axis]) * stride;
+  return e + (v - ci) * stride;
+}
+
+// Index of the wavefront within the workgroup, pinned to an SGPR so that operator
+// rows selected by it are fetched with scalar loads.  (The compiler folds the
+// readfirstlane builtin away here but then keeps the value in a VGPR, which turns
+// every operator fetch into a per-lane vector load.)
+__device__ __forceinline__ int wave_id() {
+  int w;
+  const int v = (int)(threadIdx.x >> 6);
+  asm volatile("v_readfirstlane_b32 %0, %1" : "=s"(w) : "v"(v));
+  return w;
 }
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
@@ -87,65 +113,82 @@ template <typename T>
 __device__ __forceinline__ T fmadd(T a, T b, T c) { return fma(a, b, c); }
 
 // ---------------------------------------------------------------------------
-// gathers: in_e(s) for each problem family
+// gathers: in_e(s) for each problem family, one input row at a time
 // ---------------------------------------------------------------------------
+// A workgroup owns kLanes consecutive elements (one per lane).  Input row c of all
+// its elements is read by one wavefront, so every row read is a contiguous run of
+// the component-major state (coalesced), then staged in LDS for the contraction.
+constexpr int kLanes = kElemsPerGroup;
+constexpr int kWaves = kRowGroups;
+constexpr int kThreads = kLanes * kWaves;
+
+// neighbour indices of one element, kept in named registers.  get() selects by a
+// mask-weighted sum: a select chain over the fields may be folded into an indexed
+// load from a stack copy, which would live in scratch memory.
+struct Nb {
+  int n0 = -1, n1 = -1, n2 = -1, n3 = -1;
+  __device__ __forceinline__ int get(int i) const {
+    return n0 * (int)(i == 0) + n1 * (int)(i == 1) + n2 * (int)(i == 2) + n3 * (int)(i == 3);
+  }
+};
+
 // Transport, NA active axes, P1 = p + 1.  State per element: the outflow-face
-// values of each active axis.  Inputs: [inflow face of each active axis (the
-// upwind neighbour's outflow values; 0 on an inflow boundary, whose data is folded
-// into g) | own outflow values].  The upwind trace (eq. transportLocale) is the
-// upwind element's value, so no arithmetic is needed in the gather.
+// values of each active axis (row t*NF + k).  Inputs: rows [0, NA*NF) are the
+// inflow faces, i.e. the upwind neighbour's state rows (0 on an inflow boundary,
+// whose data is folded into g); rows [NA*NF, 2*NA*NF) are the element's own state.
+// The upwind trace (eq. transportLocale) is the upwind element's value, so the
+// gather is pure data movement.
 template <int DIM, int NA, int P1>
 struct TransportFam {
   static constexpr int NF = DIM == 2 ? P1 : P1 * P1;
   static constexpr int NP = DIM == 2 ? P1 * P1 : P1 * P1 * P1;
   static constexpr int S = NA * NF, I = 2 * NA * NF, N = NP;
-  template <class LD, typename T>
-  __device__ __forceinline__ static void gather(const MeshDev& m, int e, const LD& ld, T* in) {
-    int c[3];
-    coords(m, e, c);
-    const size_t nel = (size_t)m.nel;
-#pragma unroll
-    for (int t = 0; t < NA; ++t) {
-      const int nb = neighbour(m, e, c, m.ax[t], -m.dir[t]);
-      const int src = nb >= 0 ? nb : e;
-      const T keep = nb >= 0 ? T(1) : T(0);
-#pragma unroll
-      for (int k = 0; k < NF; ++k) {
-        const size_t row = (size_t)(t * NF + k) * nel;
-        in[(NA + t) * NF + k] = (T)ld(row + e);
-        in[t * NF + k] = keep * (T)ld(row + src);
-      }
-    }
+  __device__ __forceinline__ static void neighbours(const MeshDev& m, int e, Nb& nb) {
+    const Ijk c = coords(m, e);
+    if (NA > 0) nb.n0 = neighbour(m, e, c, m.ax[0], -m.dir[0]);
+    if (NA > 1) nb.n1 = neighbour(m, e, c, m.ax[1], -m.dir[1]);
+    if (NA > 2) nb.n2 = neighbour(m, e, c, m.ax[2], -m.dir[2]);
   }
+  template <class LD>
+  __device__ __forceinline__ static auto row(const MeshDev& m, int e, const Nb& nb, const LD& ld, int c)
+      -> decltype(ld(0)) {
+    using V = decltype(ld(0));
+    const size_t nel = (size_t)m.nel;
+    if (c < NA * NF) {
+      const int n = nb.get(c / NF);
+      return n >= 0 ? ld((size_t)c * nel + n) : V(0);
+    }
+    return ld((size_t)(c - NA * NF) * nel + e);
+  }
+  __device__ __forceinline__ static int own_row(int r) { return NA * NF + r; }
 };
 
 // Shallow water, P1 = p + 1.  State per element side f: c_f = (phi + sqrt(Phi)
-// vel.n_f) / 2 at the face nodes.  Input on face f: the trace
+// vel.n_f) / 2 at the face nodes (row f*NF + k).  Input row f*NF + k: the trace
 // phihat = c_own + c_neighbour (the trace formula below the local solver in
 // Section 3); on a wall phihat = phi + sqrt(Phi) vel.n = 2 c_own.
 template <int P1>
 struct SweFam {
   static constexpr int NF = P1, NP = P1 * P1;
   static constexpr int S = 4 * NF, I = 4 * NF, N = 3 * NP;
-  template <class LD, typename T>
-  __device__ __forceinline__ static void gather(const MeshDev& m, int e, const LD& ld, T* in) {
-    int c[3];
-    coords(m, e, c);
-    const size_t nel = (size_t)m.nel;
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const int nb = neighbour(m, e, c, f >> 1, (f & 1) ? 1 : -1);
-      const bool wall = nb < 0;
-      const int src = wall ? e : nb;
-      const int fs = wall ? f : (f ^ 1);
-#pragma unroll
-      for (int k = 0; k < NF; ++k) {
-        const T own = (T)ld((size_t)(f * NF + k) * nel + e);
-        const T oth = (T)ld((size_t)(fs * NF + k) * nel + src);
-        in[f * NF + k] = own + oth;
-      }
-    }
+  __device__ __forceinline__ static void neighbours(const MeshDev& m, int e, Nb& nb) {
+    const Ijk c = coords(m, e);
+    nb.n0 = neighbour(m, e, c, 0, -1);
+    nb.n1 = neighbour(m, e, c, 0, 1);
+    nb.n2 = neighbour(m, e, c, 1, -1);
+    nb.n3 = neighbour(m, e, c, 1, 1);
   }
+  template <class LD>
+  __device__ __forceinline__ static auto row(const MeshDev& m, int e, const Nb& nb, const LD& ld, int c)
+      -> decltype(ld(0)) {
+    const size_t nel = (size_t)m.nel;
+    const int f = c / NF, k = c - f * NF;
+    const auto own = ld((size_t)c * nel + e);
+    const int n = nb.get(f);
+    const auto oth = n >= 0 ? ld((size_t)((f ^ 1) * NF + k) * nel + n) : own;
+    return own + oth;
+  }
+  __device__ __forceinline__ static int own_row(int) { return -1; }
 };
 
 // ---------------------------------------------------------------------------
@@ -167,9 +210,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
-  __shared__ double sd[kBlock / 64][2];
+  __shared__ double sd[kWaves][2];
   __shared__ int is_last;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = wave_id();
   d2 = wave_sum(d2);
   n2 = wave_sum(n2);
   if (lane == 0) {
@@ -179,7 +222,7 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
   __syncthreads();
   if (threadIdx.x == 0) {
     double a = 0.0, b = 0.0;
-    for (int i = 0; i < kBlock / 64; ++i) {
+    for (int i = 0; i < kWaves; ++i) {
       a += sd[i][0];
       b += sd[i][1];
     }
@@ -193,7 +236,7 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
   if (!is_last) return;
   __threadfence();
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += kBlock) {
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads) {
     a += __hip_atomic_load(&ra.partials[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     b += __hip_atomic_load(&ra.partials[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -208,7 +251,7 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
   if (threadIdx.x == 0) {
     a = 0.0;
     b = 0.0;
-    for (int i = 0; i < kBlock / 64; ++i) {
+    for (int i = 0; i < kWaves; ++i) {
       a += sd[i][0];
       b += sd[i][1];
     }
@@ -232,28 +275,65 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
 // ---------------------------------------------------------------------------
 // the sweep
 // ---------------------------------------------------------------------------
-// out[r][e] = g[r][e] + sum_c T[r][c] in_e[c]   (r < S, c < I)
+// Rows of the (zero-padded) operator handled by one wavefront.
+template <int ROWS>
+struct RowSplit {
+  static constexpr int RW = (ROWS + kWaves - 1) / kWaves;
+  static constexpr int PAD = RW * kWaves;
+};
+
+extern __shared__ __align__(16) unsigned char g_smem[];
+
+// Gathers input rows [c_begin, c_end) of the workgroup's elements into LDS rows
+// starting at lds_row (wavefront w takes rows w, w + kWaves, ...).
+template <class F, typename T, class LD>
+__device__ __forceinline__ void stage_inputs(const MeshDev& m, int e, bool valid, const Nb& nb, const LD& ld,
+                                             T* x, int lds_row) {
+  const int lane = threadIdx.x & 63, w = wave_id();
+  for (int c = w; c < F::I; c += kWaves)
+    x[(lds_row + c) * kLanes + lane] = valid ? (T)F::row(m, e, nb, ld, c) : T(0);
+}
+
+// out[r][e] = g[r][e] + sum_c T[r][c] in_e[c]   (r < S, c < I).  T has RowSplit<S>::PAD rows.
 template <class F, typename T, class LD, bool RESID>
-__global__ __launch_bounds__(kBlock) void k_sweep(MeshDev m, LD ld, const T* __restrict__ g,
-                                                   const T* __restrict__ Tm, T* __restrict__ out,
-                                                   ResidArgs ra) {
+__global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* __restrict__ g,
+                                                     const T* __restrict__ Tm, T* __restrict__ out,
+                                                     ResidArgs ra) {
   if (ra.ctrl->done) return;
-  const int e = remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  double d2 = 0.0, n2 = 0.0;
-  if (e < m.nel) {
-    T in[F::I];
-    F::gather(m, e, ld, in);
-    const size_t nel = (size_t)m.nel;
-#pragma unroll 2
-    for (int r = 0; r < F::S; ++r) {
-      T acc = g[(size_t)r * nel + e];
+  T* x = reinterpret_cast<T*>(g_smem);
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int e = remap_block(blockIdx.x, gridDim.x) * kLanes + lane;
+  const bool valid = e < m.nel;
+  const size_t nel = (size_t)m.nel;
+  Nb nb;
+  if (valid) F::neighbours(m, e, nb);
+  stage_inputs<F, T>(m, e, valid, nb, ld, x, 0);
+  __syncthreads();
+  constexpr int RW = RowSplit<F::S>::RW;
+  const int r0 = w * RW;
+  T acc[RW];
 #pragma unroll
-      for (int c = 0; c < F::I; ++c) acc = fmadd(Tm[r * F::I + c], in[c], acc);
-      out[(size_t)r * nel + e] = acc;
-      if (RESID) {
-        const double dd = (double)acc - (double)ld((size_t)r * nel + e);
-        d2 += dd * dd;
-        n2 += (double)acc * (double)acc;
+  for (int i = 0; i < RW; ++i) acc[i] = (valid && r0 + i < F::S) ? g[(size_t)(r0 + i) * nel + e] : T(0);
+#pragma unroll 4
+  for (int c = 0; c < F::I; ++c) {
+    const T xc = x[c * kLanes + lane];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) acc[i] = fmadd(Tm[(r0 + i) * F::I + c], xc, acc[i]);
+  }
+  double d2 = 0.0, n2 = 0.0;
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+      const int r = r0 + i;
+      if (r < F::S) {
+        out[(size_t)r * nel + e] = acc[i];
+        if (RESID) {
+          const int orow = F::own_row(r);
+          const double old = orow >= 0 ? (double)x[orow * kLanes + lane] : (double)ld((size_t)r * nel + e);
+          const double dd = (double)acc[i] - old;
+          d2 += dd * dd;
+          n2 += (double)acc[i] * (double)acc[i];
+        }
       }
     }
   }
@@ -263,75 +343,104 @@ __global__ __launch_bounds__(kBlock) void k_sweep(MeshDev m, LD ld, const T* __r
 // mixed precision outer step: s_out = s_in (+ lo_in); r = g + T in(s_out) - s_out (FP64);
 // r_lo = r in the low precision; norms of r and of s_out + r.
 template <class F, class LD, typename Lo>
-__global__ __launch_bounds__(kBlock) void k_refine(MeshDev m, LD ld, const double* __restrict__ g,
-                                                    const double* __restrict__ Tm, double* __restrict__ s_out,
-                                                    Lo* __restrict__ r_lo, ResidArgs ra) {
+__global__ __launch_bounds__(kThreads) void k_refine(MeshDev m, LD ld, const double* __restrict__ g,
+                                                      const double* __restrict__ Tm, double* __restrict__ s_out,
+                                                      Lo* __restrict__ r_lo, ResidArgs ra) {
   if (ra.ctrl->done) return;
-  const int e = remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  double d2 = 0.0, n2 = 0.0;
-  if (e < m.nel) {
-    double in[F::I];
-    F::gather(m, e, ld, in);
-    const size_t nel = (size_t)m.nel;
-#pragma unroll 2
-    for (int r = 0; r < F::S; ++r) {
-      double acc = g[(size_t)r * nel + e];
+  double* x = reinterpret_cast<double*>(g_smem);
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int e = remap_block(blockIdx.x, gridDim.x) * kLanes + lane;
+  const bool valid = e < m.nel;
+  const size_t nel = (size_t)m.nel;
+  Nb nb;
+  if (valid) F::neighbours(m, e, nb);
+  stage_inputs<F, double>(m, e, valid, nb, ld, x, 0);
+  __syncthreads();
+  constexpr int RW = RowSplit<F::S>::RW;
+  const int r0 = w * RW;
+  double acc[RW];
 #pragma unroll
-      for (int c = 0; c < F::I; ++c) acc = fma(Tm[r * F::I + c], in[c], acc);
-      const double s1 = ld((size_t)r * nel + e);
-      const double res = acc - s1;
-      s_out[(size_t)r * nel + e] = s1;
-      if constexpr (sizeof(Lo) == 4)
-        r_lo[(size_t)r * nel + e] = (float)res;
-      else
-        r_lo[(size_t)r * nel + e] = f32_to_bf16((float)res);
-      d2 += res * res;
-      n2 += acc * acc;
+  for (int i = 0; i < RW; ++i) acc[i] = (valid && r0 + i < F::S) ? g[(size_t)(r0 + i) * nel + e] : 0.0;
+#pragma unroll 4
+  for (int c = 0; c < F::I; ++c) {
+    const double xc = x[c * kLanes + lane];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) acc[i] = fma(Tm[(r0 + i) * F::I + c], xc, acc[i]);
+  }
+  double d2 = 0.0, n2 = 0.0;
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+      const int r = r0 + i;
+      if (r < F::S) {
+        const int orow = F::own_row(r);
+        const double s1 = orow >= 0 ? x[orow * kLanes + lane] : ld((size_t)r * nel + e);
+        const double res = acc[i] - s1;
+        s_out[(size_t)r * nel + e] = s1;
+        if constexpr (sizeof(Lo) == 4)
+          r_lo[(size_t)r * nel + e] = (float)res;
+        else
+          r_lo[(size_t)r * nel + e] = f32_to_bf16((float)res);
+        d2 += res * res;
+        n2 += acc[i] * acc[i];
+      }
     }
   }
   finish_residual(d2, n2, ra);
 }
 
-// element solution from the traces of the last sweep's input:
-//   u_new = w_src + R in(s_prev) (+ P u for backward Euler);
-//   backward Euler, next step: g = g_src + G u_new
+// Element solution from the traces of the last local solve, as one stacked contraction
+//   steady:          u_new = w_src + R in(s_prev)
+//   backward Euler:  [u_new; g_next] = [w_src; gbe] + [[P, R], [G P, G R]] [u_old; in(s_prev)]
+// (u_new = A^{-1}(F_src + Mbt u_old + L in) and g_next = Q A^{-1}(F_src + Mbt u_new)).
+// Optionally resets the iteration control for the next time step.
 template <class F, bool BE>
-__global__ __launch_bounds__(kBlock) void k_volume(MeshDev m, const double* __restrict__ s_prev,
-                                                    const double* __restrict__ R, const double* __restrict__ P,
-                                                    const double* __restrict__ Gm,
-                                                    const double* __restrict__ w_src,
-                                                    const double* __restrict__ u_old, double* __restrict__ u_new,
-                                                    const double* __restrict__ g_src, double* __restrict__ g_out,
-                                                    int update_g) {
-  const int e = remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (e >= m.nel) return;
+__global__ __launch_bounds__(kThreads) void k_volume(MeshDev m, const double* __restrict__ s_prev,
+                                                      const double* __restrict__ Mv,
+                                                      const double* __restrict__ u_old,
+                                                      const double* __restrict__ w_src,
+                                                      const double* __restrict__ gbe, double* __restrict__ u_new,
+                                                      double* __restrict__ g_out, Ctrl* ctrl_reset) {
+  constexpr int COLS = (BE ? F::N : 0) + F::I;
+  constexpr int ROWS = F::N + (BE ? F::S : 0);
+  constexpr int RW = RowSplit<ROWS>::RW;
+  double* x = reinterpret_cast<double*>(g_smem);
+  const int lane = threadIdx.x & 63, w = wave_id();
+  if (ctrl_reset && blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl_reset->done = 0;
+    ctrl_reset->iters = 0;
+    ctrl_reset->status = 0;
+    ctrl_reset->counter = 0u;
+  }
+  const int e = remap_block(blockIdx.x, gridDim.x) * kLanes + lane;
+  const bool valid = e < m.nel;
   const size_t nel = (size_t)m.nel;
-  double in[F::I];
-  F::gather(m, e, Ld64{s_prev}, in);
-  double uo[BE ? F::N : 1];
-  double gacc[BE ? F::S : 1];
+  Nb nb;
+  if (valid) F::neighbours(m, e, nb);
   if constexpr (BE) {
-#pragma unroll
-    for (int c = 0; c < F::N; ++c) uo[c] = u_old[(size_t)c * nel + e];
-#pragma unroll
-    for (int i = 0; i < F::S; ++i) gacc[i] = g_src ? g_src[(size_t)i * nel + e] : 0.0;
+    for (int c = w; c < F::N; c += kWaves) x[c * kLanes + lane] = valid ? u_old[(size_t)c * nel + e] : 0.0;
   }
-  for (int r = 0; r < F::N; ++r) {
-    double acc = w_src ? w_src[(size_t)r * nel + e] : 0.0;
+  stage_inputs<F, double>(m, e, valid, nb, Ld64{s_prev}, x, BE ? F::N : 0);
+  __syncthreads();
+  const int r0 = w * RW;
+  double acc[RW];
 #pragma unroll
-    for (int c = 0; c < F::I; ++c) acc = fma(R[r * F::I + c], in[c], acc);
-    if constexpr (BE) {
+  for (int i = 0; i < RW; ++i) acc[i] = 0.0;
+#pragma unroll 4
+  for (int c = 0; c < COLS; ++c) {
+    const double xc = x[c * kLanes + lane];
 #pragma unroll
-      for (int c = 0; c < F::N; ++c) acc = fma(P[r * F::N + c], uo[c], acc);
-#pragma unroll
-      for (int i = 0; i < F::S; ++i) gacc[i] = fma(Gm[i * F::N + r], acc, gacc[i]);
-    }
-    u_new[(size_t)r * nel + e] = acc;
+    for (int i = 0; i < RW; ++i) acc[i] = fma(Mv[(r0 + i) * COLS + c], xc, acc[i]);
   }
-  if constexpr (BE) {
-    if (update_g) {
+  if (!valid) return;
 #pragma unroll
-      for (int i = 0; i < F::S; ++i) g_out[(size_t)i * nel + e] = gacc[i];
+  for (int i = 0; i < RW; ++i) {
+    const int q = r0 + i;
+    if (q < F::N) {
+      u_new[(size_t)q * nel + e] = acc[i] + (w_src ? w_src[(size_t)q * nel + e] : 0.0);
+    } else if (BE && q < ROWS && g_out) {
+      const int r = q - F::N;
+      g_out[(size_t)r * nel + e] = acc[i] + (gbe ? gbe[(size_t)r * nel + e] : 0.0);
     }
   }
 }
@@ -340,6 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_volume(MeshDev m, const double* __re
 // host launchers of one family
 // ---------------------------------------------------------------------------
 static inline int nblocks(int nel) { return (nel + kBlock - 1) / kBlock; }
+static inline int ngroups(int nel) { return (nel + kLanes - 1) / kLanes; }
 
 static inline ResidArgs resid_args(const DevProblem& dp, double tol, int stop) {
   ResidArgs ra;
@@ -352,43 +462,71 @@ static inline ResidArgs resid_args(const DevProblem& dp, double tol, int stop) {
   return ra;
 }
 
+// dynamic LDS above 64 KB must be enabled per kernel
+template <typename K>
+static void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 template <class F>
 struct Family {
+  static constexpr size_t lds_in64 = (size_t)F::I * kLanes * 8;
+  static constexpr size_t lds_in32 = (size_t)F::I * kLanes * 4;
   static void sweep64(const DevProblem& dp, int k, bool resid, double tol, hipStream_t st) {
     const ResidArgs ra = resid_args(dp, tol, tol >= 0.0 ? 1 : 0);
     const Ld64 ld{dp.s[k & 1]};
-    if (resid)
-      hipLaunchKernelGGL((k_sweep<F, double, Ld64, true>), dim3(nblocks(dp.mesh.nel)), dim3(kBlock), 0, st, dp.mesh,
-                         ld, (const double*)dp.g, dp.T64, dp.s[(k + 1) & 1], ra);
-    else
-      hipLaunchKernelGGL((k_sweep<F, double, Ld64, false>), dim3(nblocks(dp.mesh.nel)), dim3(kBlock), 0, st,
-                         dp.mesh, ld, (const double*)dp.g, dp.T64, dp.s[(k + 1) & 1], ra);
+    const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
+    if (resid) {
+      auto kern = k_sweep<F, double, Ld64, true>;
+      allow_lds(kern, lds_in64);
+      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, ld, (const double*)dp.g, dp.T64,
+                         dp.s[(k + 1) & 1], ra);
+    } else {
+      auto kern = k_sweep<F, double, Ld64, false>;
+      allow_lds(kern, lds_in64);
+      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, ld, (const double*)dp.g, dp.T64,
+                         dp.s[(k + 1) & 1], ra);
+    }
   }
-  static void volume(const DevProblem& dp, const double* s_prev, bool update_g, hipStream_t st) {
-    if (dp.be)
-      hipLaunchKernelGGL((k_volume<F, true>), dim3(nblocks(dp.mesh.nel)), dim3(kBlock), 0, st, dp.mesh, s_prev, dp.R,
-                         dp.P, dp.G, (const double*)dp.w_src, (const double*)dp.u, dp.u_new,
-                         (const double*)dp.g_src, dp.g, update_g ? 1 : 0);
-    else
-      hipLaunchKernelGGL((k_volume<F, false>), dim3(nblocks(dp.mesh.nel)), dim3(kBlock), 0, st, dp.mesh, s_prev,
-                         dp.R, dp.P, dp.G, (const double*)dp.w_src, (const double*)dp.u, dp.u_new,
-                         (const double*)dp.g_src, dp.g, 0);
+  static void volume(const DevProblem& dp, const double* s_prev, bool step, hipStream_t st) {
+    const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
+    if (dp.be) {
+      const size_t lds = (size_t)(F::N + F::I) * kLanes * 8;
+      auto kern = k_volume<F, true>;
+      allow_lds(kern, lds);
+      hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, s_prev, dp.Mvol, (const double*)dp.u,
+                         (const double*)(dp.has_src ? dp.w_src : nullptr), (const double*)(dp.has_src ? dp.gbe : nullptr),
+                         dp.u_new, step ? dp.g : nullptr, step ? dp.ctrl : nullptr);
+    } else {
+      auto kern = k_volume<F, false>;
+      allow_lds(kern, lds_in64);
+      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, s_prev, dp.Mvol, (const double*)nullptr,
+                         (const double*)(dp.has_src ? dp.w_src : nullptr), (const double*)nullptr, dp.u_new,
+                         (double*)nullptr, (Ctrl*)nullptr);
+    }
   }
   static void refine32(const DevProblem& dp, const double* s_in, const void* lo_in, double* s_out, void* r_out,
                        double tol, hipStream_t st) {
     const ResidArgs ra = resid_args(dp, tol, 1);
+    const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
     if (lo_in) {
       const LdSum<Ld32> ld{s_in, Ld32{(const float*)lo_in}};
-      hipLaunchKernelGGL((k_refine<F, LdSum<Ld32>, float>), dim3(nblocks(dp.mesh.nel)), dim3(kBlock), 0, st, dp.mesh,
-                         ld, (const double*)dp.g, dp.T64, s_out, (float*)r_out, ra);
+      auto kern = k_refine<F, LdSum<Ld32>, float>;
+      allow_lds(kern, lds_in64);
+      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, ld, (const double*)dp.g, dp.T64, s_out,
+                         (float*)r_out, ra);
     } else {
-      hipLaunchKernelGGL((k_refine<F, Ld64, float>), dim3(nblocks(dp.mesh.nel)), dim3(kBlock), 0, st, dp.mesh,
-                         Ld64{s_in}, (const double*)dp.g, dp.T64, s_out, (float*)r_out, ra);
+      auto kern = k_refine<F, Ld64, float>;
+      allow_lds(kern, lds_in64);
+      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, Ld64{s_in}, (const double*)dp.g, dp.T64, s_out,
+                         (float*)r_out, ra);
     }
   }
   static void inner32(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
     const ResidArgs ra = resid_args(dp, -1.0, 0);
-    hipLaunchKernelGGL((k_sweep<F, float, Ld32, false>), dim3(nblocks(dp.mesh.nel)), dim3(kBlock), 0, st, dp.mesh,
+    auto kern = k_sweep<F, float, Ld32, false>;
+    allow_lds(kern, lds_in32);
+    hipLaunchKernelGGL(kern, dim3(ngroups(dp.mesh.nel)), dim3(kThreads), lds_in32, st, dp.mesh,
                        Ld32{(const float*)lo_in}, (const float*)r_lo, dp.T32, (float*)lo_out, ra);
   }
 };
@@ -560,12 +698,12 @@ __global__ void k_bc_inputs(BcArgs a, const double* __restrict__ bc, double* __r
   const MeshDev& m = a.mesh;
   if (e >= m.nel) return;
   const size_t nel = (size_t)m.nel;
-  int c[3];
-  coords(m, e, c);
+  const Ijk ijk = coords(m, e);
+  const int c[3] = {ijk.c0, ijk.c1, ijk.c2};
   for (int r = 0; r < a.I; ++r) in_bc[r * nel + e] = 0.0;
   for (int t = 0; t < a.na; ++t) {
     const int ax = m.ax[t];
-    if (neighbour(m, e, c, ax, -m.dir[t]) >= 0) continue;
+    if (neighbour(m, e, ijk, ax, -m.dir[t]) >= 0) continue;
     const int side = 2 * ax + (m.dir[t] > 0 ? 0 : 1);
     long long fi = 0, stride = 1;
     for (int q = 0; q < a.dim; ++q)

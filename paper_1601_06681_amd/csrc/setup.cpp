@@ -411,6 +411,19 @@ std::string build_operators(const Desc& d, Operators& ops) {
   if (ops.be) {
     ops.P = matmul(ops.W, Mbt);
     ops.G = matmul(ops.Q, ops.P);
+    const Mat GP = matmul(ops.G, ops.P), GR = matmul(ops.G, ops.R);
+    const int n = ops.n;
+    ops.Mvol = Mat(n + ops.S, n + ops.I);
+    for (int i = 0; i < n; ++i) {
+      for (int j = 0; j < n; ++j) ops.Mvol(i, j) = ops.P(i, j);
+      for (int j = 0; j < ops.I; ++j) ops.Mvol(i, n + j) = ops.R(i, j);
+    }
+    for (int i = 0; i < ops.S; ++i) {
+      for (int j = 0; j < n; ++j) ops.Mvol(n + i, j) = GP(i, j);
+      for (int j = 0; j < ops.I; ++j) ops.Mvol(n + i, n + j) = GR(i, j);
+    }
+  } else {
+    ops.Mvol = ops.R;
   }
   // load matrix: F_i = (f, psi_i) = sum_q J w_q psi_i(x_q) f(x_q)
   const int nq = b.nq, n1 = p + 1;

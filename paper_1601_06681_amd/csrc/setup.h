@@ -60,6 +60,9 @@ struct Operators {
   Mat P;            // n x n  (A^{-1} Mbt), BE only
   Mat G;            // S x n  (Q A^{-1} Mbt), BE only
   Mat Bload;        // Np x nq_el: F_i = sum_q Bload(i,q) f_q for one field
+  // recovery as one contraction: steady u = w + R in; BE [u; g_next] = [w; gbe] +
+  // [[P, R], [G P, G R]] [u_old; in]
+  Mat Mvol;
 };
 
 struct Desc {
