@@ -170,6 +170,59 @@ def run_swe(args, torch):
     return out
 
 
+def run_transport3d(torch, args):
+    """64^3 hexes, degree 3, steady transport: time to a relative trace increment of 1e-8,
+    plain FP64 vs FP32- and BF16-MFMA-correction forms with FP64 refinement."""
+    from paper_1601_06681_amd import workloads as W
+    from paper_1601_06681_amd.ehdg import EHDG_TRANSPORT, Problem
+    cfg = W.TRANSPORT3D
+    ue, f = W.transport_manufactured_3d(cfg["beta"], cfg["sigma"])
+
+    def make(precision=0, inner=1):
+        prob = Problem(EHDG_TRANSPORT, 3, cfg["n"], L=cfg["L"], degree=cfg["degree"], beta=cfg["beta"],
+                       sigma=cfg["sigma"], precision=precision, inner_sweeps=inner)
+        prob.set_forcing([f], ue)
+        return prob
+
+    def solve_timed(prob):
+        prob.set_initial(None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, iters, res = prob.solve(cfg["tol"], 100000)
+        u = prob.solution()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, iters, res, u
+
+    p64 = make()
+    solve_timed(p64)                                   # warm-up (kernel loading, caches)
+    t64, it64, res64, u64 = solve_timed(p64)
+    dofs = p64.nel * p64.Np
+    p64.set_initial(None)
+    t_sweep = time_sweeps(torch, p64, 50)
+    alg_bytes = 3 * p64.S * 8 * p64.nel
+    flops = 2 * p64.S * p64.I * p64.nel
+    ex = p64.points("nodes")
+    err_exact = float(((u64[:, 0, :] - ue(ex, torch)).abs().max()).item())
+    out = {"workload": cfg["name"], "dofs": dofs, "rel_tol": cfg["tol"],
+           "fp64": {"time_to_tol_ms": t64 * 1e3, "sweeps": it64, "rel_res": res64,
+                    "dof_updates_per_s": dofs * it64 / t64, "max_err_vs_manufactured": err_exact,
+                    "sweep_us": t_sweep * 1e6, "sweep_hbm_frac": alg_bytes / t_sweep / HBM_PEAK,
+                    "sweep_fp64_frac": flops / t_sweep / FP64_PEAK}}
+    log(f"[bench] 3d fp64: {it64} sweeps in {t64 * 1e3:.2f} ms; sweep {t_sweep * 1e6:.1f} us "
+        f"({alg_bytes / t_sweep / 1e9:.0f} GB/s, {flops / t_sweep / 1e12:.1f} TF/s)")
+    p64.close()
+    for name, prec, inner in (("fp32_refine_s8", 1, 8), ("bf16_mfma_refine_s8", 2, 8)):
+        pr = make(prec, inner)
+        solve_timed(pr)
+        t, it, res, u = solve_timed(pr)
+        err = float(((u - u64).abs().max() / u64.abs().max()).item())
+        out[name] = {"time_to_tol_ms": t * 1e3, "equivalent_sweeps": it, "rel_res": res,
+                     "rel_err_vs_fp64_form": err, "speedup_vs_fp64_form": t64 / t}
+        log(f"[bench] 3d {name}: {t * 1e3:.2f} ms, {it} equivalent sweeps, err vs fp64 {err:.2e}")
+        pr.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +231,7 @@ def main():
     ap.add_argument("--workload", default="swe2d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the eHDG sweep of one mesh is measured "
@@ -192,6 +246,8 @@ def main():
         print(json.dumps({"error": f"unknown workload {args.workload}"}))
         sys.exit(2)
     out = run_swe(args, torch)
+    if not args.no_3d:
+        out["transport3d"] = run_transport3d(torch, args)
     print(json.dumps(out))
 
 

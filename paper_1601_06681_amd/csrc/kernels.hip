@@ -88,25 +88,28 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
-// loaders: component-major arrays, value type per precision
-struct Ld64 {
+// loaders: value of state row r of element e, per storage layout and precision
+struct Ld64 {  // FP64, component-major
   const double* p;
-  __device__ __forceinline__ double operator()(size_t i) const { return p[i]; }
+  size_t nel;
+  __device__ __forceinline__ double operator()(int r, int e) const { return p[(size_t)r * nel + e]; }
 };
-struct Ld32 {
+struct Ld32 {  // FP32, component-major
   const float* p;
-  __device__ __forceinline__ float operator()(size_t i) const { return p[i]; }
+  size_t nel;
+  __device__ __forceinline__ float operator()(int r, int e) const { return p[(size_t)r * nel + e]; }
 };
-struct Ld16 {
+template <int S>
+struct Ld16Aos {  // BF16, element-major: the S values of an element are contiguous
   const uint16_t* p;
-  __device__ __forceinline__ float operator()(size_t i) const { return bf16_to_f32(p[i]); }
+  __device__ __forceinline__ float operator()(int r, int e) const { return bf16_to_f32(p[(size_t)e * S + r]); }
 };
 // FP64 iterate plus a low-precision correction: s + delta
 template <class LD>
 struct LdSum {
-  const double* s;
+  Ld64 s;
   LD d;
-  __device__ __forceinline__ double operator()(size_t i) const { return s[i] + (double)d(i); }
+  __device__ __forceinline__ double operator()(int r, int e) const { return s(r, e) + (double)d(r, e); }
 };
 
 template <typename T>
@@ -151,14 +154,13 @@ struct TransportFam {
   }
   template <class LD>
   __device__ __forceinline__ static auto row(const MeshDev& m, int e, const Nb& nb, const LD& ld, int c)
-      -> decltype(ld(0)) {
-    using V = decltype(ld(0));
-    const size_t nel = (size_t)m.nel;
+      -> decltype(ld(0, 0)) {
+    using V = decltype(ld(0, 0));
     if (c < NA * NF) {
       const int n = nb.get(c / NF);
-      return n >= 0 ? ld((size_t)c * nel + n) : V(0);
+      return n >= 0 ? ld(c, n) : V(0);
     }
-    return ld((size_t)(c - NA * NF) * nel + e);
+    return ld(c - NA * NF, e);
   }
   __device__ __forceinline__ static int own_row(int r) { return NA * NF + r; }
 };
@@ -180,12 +182,11 @@ struct SweFam {
   }
   template <class LD>
   __device__ __forceinline__ static auto row(const MeshDev& m, int e, const Nb& nb, const LD& ld, int c)
-      -> decltype(ld(0)) {
-    const size_t nel = (size_t)m.nel;
+      -> decltype(ld(0, 0)) {
     const int f = c / NF, k = c - f * NF;
-    const auto own = ld((size_t)c * nel + e);
+    const auto own = ld(c, e);
     const int n = nb.get(f);
-    const auto oth = n >= 0 ? ld((size_t)((f ^ 1) * NF + k) * nel + n) : own;
+    const auto oth = n >= 0 ? ld((f ^ 1) * NF + k, n) : own;
     return own + oth;
   }
   __device__ __forceinline__ static int own_row(int) { return -1; }
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* _
         out[(size_t)r * nel + e] = acc[i];
         if (RESID) {
           const int orow = F::own_row(r);
-          const double old = orow >= 0 ? (double)x[orow * kLanes + lane] : (double)ld((size_t)r * nel + e);
+          const double old = orow >= 0 ? (double)x[orow * kLanes + lane] : (double)ld(r, e);
           const double dd = (double)acc[i] - old;
           d2 += dd * dd;
           n2 += (double)acc[i] * (double)acc[i];
@@ -342,10 +343,23 @@ __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* _
 
 // mixed precision outer step: s_out = s_in (+ lo_in); r = g + T in(s_out) - s_out (FP64);
 // r_lo = r in the low precision; norms of r and of s_out + r.
-template <class F, class LD, typename Lo>
+struct StSoa32 {  // FP32, component-major
+  float* p;
+  size_t nel;
+  __device__ __forceinline__ void operator()(int r, int e, double v) const { p[(size_t)r * nel + e] = (float)v; }
+};
+template <int S>
+struct StAos16 {  // BF16, element-major
+  uint16_t* p;
+  __device__ __forceinline__ void operator()(int r, int e, double v) const {
+    p[(size_t)e * S + r] = f32_to_bf16((float)v);
+  }
+};
+
+template <class F, class LD, class ST>
 __global__ __launch_bounds__(kThreads) void k_refine(MeshDev m, LD ld, const double* __restrict__ g,
                                                       const double* __restrict__ Tm, double* __restrict__ s_out,
-                                                      Lo* __restrict__ r_lo, ResidArgs ra) {
+                                                      ST r_lo, ResidArgs ra) {
   if (ra.ctrl->done) return;
   double* x = reinterpret_cast<double*>(g_smem);
   const int lane = threadIdx.x & 63, w = wave_id();
@@ -374,13 +388,10 @@ __global__ __launch_bounds__(kThreads) void k_refine(MeshDev m, LD ld, const dou
       const int r = r0 + i;
       if (r < F::S) {
         const int orow = F::own_row(r);
-        const double s1 = orow >= 0 ? x[orow * kLanes + lane] : ld((size_t)r * nel + e);
+        const double s1 = orow >= 0 ? x[orow * kLanes + lane] : ld(r, e);
         const double res = acc[i] - s1;
         s_out[(size_t)r * nel + e] = s1;
-        if constexpr (sizeof(Lo) == 4)
-          r_lo[(size_t)r * nel + e] = (float)res;
-        else
-          r_lo[(size_t)r * nel + e] = f32_to_bf16((float)res);
+        r_lo(r, e, res);
         d2 += res * res;
         n2 += acc[i] * acc[i];
       }
@@ -420,7 +431,7 @@ __global__ __launch_bounds__(kThreads) void k_volume(MeshDev m, const double* __
   if constexpr (BE) {
     for (int c = w; c < F::N; c += kWaves) x[c * kLanes + lane] = valid ? u_old[(size_t)c * nel + e] : 0.0;
   }
-  stage_inputs<F, double>(m, e, valid, nb, Ld64{s_prev}, x, BE ? F::N : 0);
+  stage_inputs<F, double>(m, e, valid, nb, Ld64{s_prev, nel}, x, BE ? F::N : 0);
   __syncthreads();
   const int r0 = w * RW;
   double acc[RW];
@@ -474,7 +485,7 @@ struct Family {
   static constexpr size_t lds_in32 = (size_t)F::I * kLanes * 4;
   static void sweep64(const DevProblem& dp, int k, bool resid, double tol, hipStream_t st) {
     const ResidArgs ra = resid_args(dp, tol, tol >= 0.0 ? 1 : 0);
-    const Ld64 ld{dp.s[k & 1]};
+    const Ld64 ld{dp.s[k & 1], (size_t)dp.mesh.nel};
     const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
     if (resid) {
       auto kern = k_sweep<F, double, Ld64, true>;
@@ -510,16 +521,17 @@ struct Family {
     const ResidArgs ra = resid_args(dp, tol, 1);
     const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
     if (lo_in) {
-      const LdSum<Ld32> ld{s_in, Ld32{(const float*)lo_in}};
-      auto kern = k_refine<F, LdSum<Ld32>, float>;
+      const size_t ne = (size_t)dp.mesh.nel;
+      const LdSum<Ld32> ld{Ld64{s_in, ne}, Ld32{(const float*)lo_in, ne}};
+      auto kern = k_refine<F, LdSum<Ld32>, StSoa32>;
       allow_lds(kern, lds_in64);
       hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, ld, (const double*)dp.g, dp.T64, s_out,
-                         (float*)r_out, ra);
+                         StSoa32{(float*)r_out, ne}, ra);
     } else {
-      auto kern = k_refine<F, Ld64, float>;
+      auto kern = k_refine<F, Ld64, StSoa32>;
       allow_lds(kern, lds_in64);
-      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, Ld64{s_in}, (const double*)dp.g, dp.T64, s_out,
-                         (float*)r_out, ra);
+      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, Ld64{s_in, (size_t)dp.mesh.nel},
+                         (const double*)dp.g, dp.T64, s_out, StSoa32{(float*)r_out, (size_t)dp.mesh.nel}, ra);
     }
   }
   static void inner32(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
@@ -527,8 +539,125 @@ struct Family {
     auto kern = k_sweep<F, float, Ld32, false>;
     allow_lds(kern, lds_in32);
     hipLaunchKernelGGL(kern, dim3(ngroups(dp.mesh.nel)), dim3(kThreads), lds_in32, st, dp.mesh,
-                       Ld32{(const float*)lo_in}, (const float*)r_lo, dp.T32, (float*)lo_out, ra);
+                       Ld32{(const float*)lo_in, (size_t)dp.mesh.nel}, (const float*)r_lo, dp.T32, (float*)lo_out, ra);
   }
+};
+
+
+// ---------------------------------------------------------------------------
+// BF16 correction sweep on MFMA (3D transport, degree 3: S = 48, I = 96)
+// ---------------------------------------------------------------------------
+// lo_out = r + T in(lo_in) with T, in and r in BF16 and FP32 accumulation, as
+// D(48 x 16 elements) = T(48 x 96) B(96 x 16) per tile of 16 elements: 3 x 3
+// v_mfma_f32_16x16x32_bf16.  Fragment layout (16x16x32): lane l holds A[l%16][8(l/16)+0..7],
+// B[8(l/16)+0..7][l%16] and D[4(l/16)+0..3][l%16].  The correction is element-major
+// (48 BF16 per element), so each B fragment is one 16-byte load: 8 consecutive
+// state rows of the lane's element or of its upwind neighbour.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+typedef unsigned short ushort4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaTilesPerWave = 8;
+
+template <class F>
+__global__ __launch_bounds__(kThreads) void k_inner_mfma(MeshDev m, const uint16_t* __restrict__ lo_in,
+                                                          const uint16_t* __restrict__ r_lo,
+                                                          const uint16_t* __restrict__ T16,
+                                                          uint16_t* __restrict__ lo_out, const Ctrl* ctrl) {
+  static_assert(F::S == 48 && F::I == 96 && F::NF == 16, "tiling assumes S = 48, I = 96");
+  if (ctrl->done) return;
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int j = lane & 15, kg = lane >> 4;
+  // A fragments of T (3 row tiles x 3 k tiles), held for the whole wave
+  bf16x8_t a[3][3];
+#pragma unroll
+  for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+    for (int kt = 0; kt < 3; ++kt)
+      a[mt][kt] = *reinterpret_cast<const bf16x8_t*>(T16 + (size_t)(mt * 16 + j) * 96 + kt * 32 + 8 * kg);
+  const int tile0 = (remap_block(blockIdx.x, gridDim.x) * kWaves + w) * kMfmaTilesPerWave;
+  for (int t = 0; t < kMfmaTilesPerWave; ++t) {
+    const int e = (tile0 + t) * 16 + j;
+    const bool valid = e < m.nel;
+    Nb nb;
+    if (valid) F::neighbours(m, e, nb);
+    floatx4_t acc[3];
+#pragma unroll
+    for (int mt = 0; mt < 3; ++mt) acc[mt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < 3; ++kt) {
+      // inputs 8q .. 8q+7, q = 4 kt + kg: q < 6 -> upwind neighbour of face q/2, its
+      // state rows 8q..; q >= 6 -> own state rows 8q - 48 ..
+      const int q = 4 * kt + kg;
+      const int src = q < 6 ? nb.get(q >> 1) : e;
+      const int row = q < 6 ? 8 * q : 8 * q - 48;
+      bf16x8_t b;
+      if (valid && src >= 0)
+        b = *reinterpret_cast<const bf16x8_t*>(lo_in + (size_t)src * 48 + row);
+      else
+        b = bf16x8_t{};
+#pragma unroll
+      for (int mt = 0; mt < 3; ++mt) acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][kt], b, acc[mt], 0, 0, 0);
+    }
+    if (!valid) continue;
+#pragma unroll
+    for (int mt = 0; mt < 3; ++mt) {
+      const size_t off = (size_t)e * 48 + mt * 16 + 4 * kg;
+      const ushort4_t rr = *reinterpret_cast<const ushort4_t*>(r_lo + off);
+      ushort4_t o;
+      o.x = f32_to_bf16(acc[mt].x + bf16_to_f32(rr.x));
+      o.y = f32_to_bf16(acc[mt].y + bf16_to_f32(rr.y));
+      o.z = f32_to_bf16(acc[mt].z + bf16_to_f32(rr.z));
+      o.w = f32_to_bf16(acc[mt].w + bf16_to_f32(rr.w));
+      *reinterpret_cast<ushort4_t*>(lo_out + off) = o;
+    }
+  }
+}
+
+// BF16-MFMA refinement launchers (only where the tiling applies)
+template <class F, bool ENABLE>
+struct Bf16Ops {
+  static constexpr auto refine = nullptr;
+  static constexpr auto inner = nullptr;
+};
+
+template <class F>
+struct Bf16Ops<F, true> {
+  static void refine(const DevProblem& dp, const double* s_in, const void* lo_in, double* s_out, void* r_out,
+                     double tol, hipStream_t st) {
+    const ResidArgs ra = resid_args(dp, tol, 1);
+    const size_t ne = (size_t)dp.mesh.nel;
+    const size_t lds = (size_t)F::I * kLanes * 8;
+    const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
+    const StAos16<F::S> store{(uint16_t*)r_out};
+    if (lo_in) {
+      const LdSum<Ld16Aos<F::S>> ld{Ld64{s_in, ne}, Ld16Aos<F::S>{(const uint16_t*)lo_in}};
+      auto kern = k_refine<F, LdSum<Ld16Aos<F::S>>, StAos16<F::S>>;
+      allow_lds(kern, lds);
+      hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, ld, (const double*)dp.g, dp.T64, s_out, store, ra);
+    } else {
+      auto kern = k_refine<F, Ld64, StAos16<F::S>>;
+      allow_lds(kern, lds);
+      hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, Ld64{s_in, ne}, (const double*)dp.g, dp.T64, s_out,
+                         store, ra);
+    }
+  }
+  static void inner(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
+    const int tiles = (dp.mesh.nel + 15) / 16;
+    const int per_group = kWaves * kMfmaTilesPerWave;
+    const dim3 grid((tiles + per_group - 1) / per_group), block(kThreads);
+    hipLaunchKernelGGL(k_inner_mfma<F>, grid, block, 0, st, dp.mesh, (const uint16_t*)lo_in, (const uint16_t*)r_lo,
+                       dp.T16, (uint16_t*)lo_out, (const Ctrl*)dp.ctrl);
+  }
+};
+
+template <class F>
+struct HasMfmaTiling {
+  static constexpr bool value = false;
+};
+template <>
+struct HasMfmaTiling<TransportFam<3, 3, 4>> {
+  static constexpr bool value = true;
 };
 
 // ---------------------------------------------------------------------------
@@ -536,8 +665,9 @@ struct Family {
 // ---------------------------------------------------------------------------
 template <class F>
 static const KernelSet* set_of() {
-  static const KernelSet ks = {&Family<F>::sweep64, &Family<F>::volume, &Family<F>::refine32,
-                               &Family<F>::inner32, nullptr, nullptr};
+  static const KernelSet ks = {&Family<F>::sweep64, &Family<F>::volume, &Family<F>::refine32, &Family<F>::inner32,
+                               Bf16Ops<F, HasMfmaTiling<F>::value>::refine,
+                               Bf16Ops<F, HasMfmaTiling<F>::value>::inner};
   return &ks;
 }
 

@@ -10,8 +10,8 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (EHDG_BF16_REFINE, EHDG_ERR_DIVERGED, EHDG_ERR_NOT_CONVERGED, EHDG_FP32_REFINE, EHDG_FP64,
-                   EHDG_OK, EHDG_SWE, EHDG_TRANSPORT, ehdg_desc)
+from ._lib import (EHDG_BF16_REFINE, EHDG_ERR_DIVERGED, EHDG_ERR_NOT_CONVERGED, EHDG_ERR_UNSUPPORTED,
+                   EHDG_FP32_REFINE, EHDG_FP64, EHDG_OK, EHDG_SWE, EHDG_TRANSPORT, ehdg_desc)
 
 __all__ = [
     "EhdgError", "Problem", "make_desc", *_lib.EXPORTED,

@@ -235,3 +235,33 @@ def test_transport3d_full_size_first_sweeps():
     prob = gpu_transport(cfg["n"], cfg["L"], cfg["degree"], cfg["beta"], cfg["sigma"])
     prob.iterate(3)
     assert rel_err(_gpu_u(prob), u) < ITER_TOL
+
+
+@pytest.mark.parametrize("inner", [2, 6])
+def test_bf16_mfma_refine_transport3d(inner):
+    """BF16 correction sweeps on MFMA (FP32 accumulation) + FP64 residual refinement
+    reach the FP64 fixed point within 1e-8 relative (3D transport, degree 3)."""
+    n, p, beta, sigma = (12, 10, 9), 3, (1.0, 0.7, 0.3), 1.0
+    op, F, _, _ = oracle_transport(n, (1.0, 1.0, 1.0), p, beta, sigma)
+    ref = O.solve(op, F, np.zeros((op.mesh.nel, op.ref.Np)), tol=1e-14, max_iter=20000)
+    prob = gpu_transport(n, (1.0, 1.0, 1.0), p, beta, sigma, precision=2, inner=inner)
+    rc, iters, res = prob.solve(1e-11, 50000)
+    assert res < 1e-11
+    assert rel_err(_gpu_u(prob), ref["u"]) < 1e-8
+
+
+def test_bf16_mfma_refine_negative_beta_ragged():
+    """Other flow directions and an element count that is not a multiple of 16."""
+    n, p, beta, sigma = (7, 5, 3), 3, (-0.6, 0.8, -1.0), 0.5
+    op, F, _, _ = oracle_transport(n, (1.0, 0.9, 0.8), p, beta, sigma)
+    ref = O.solve(op, F, np.zeros((op.mesh.nel, op.ref.Np)), tol=1e-14, max_iter=20000)
+    prob = gpu_transport(n, (1.0, 0.9, 0.8), p, beta, sigma, precision=2, inner=4)
+    rc, iters, res = prob.solve(1e-11, 50000)
+    assert rel_err(_gpu_u(prob), ref["u"]) < 1e-8
+
+
+def test_bf16_refine_unsupported_elsewhere():
+    from paper_1601_06681_amd import ehdg as E
+    with pytest.raises(E.EhdgError) as ei:
+        gpu_transport((8, 8), (1.0, 1.0), 2, (1.0, 0.5), 1.0, precision=2, inner=4)
+    assert ei.value.code == E.EHDG_ERR_UNSUPPORTED
