@@ -223,6 +223,36 @@ def run_transport3d(torch, args):
     return out
 
 
+def run_counter_sample(torch, args):
+    """For rocprofv3 --pmc runs: a plain device-to-device copy of 256 MiB (the
+    calibration kernel: it must fetch and write exactly 256 MiB each), then 20 FP64
+    sweeps of the shallow-water workload and, unless --no-3d, 5 sweeps of the 64^3
+    transport workload.  Nothing else is launched."""
+    from paper_1601_06681_amd import workloads as W
+    n = 256 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    cfg = W.SWE2D
+    prob = swe_problem(cfg)
+    prob.set_initial(W.gaussian_hump(W.hump_centre(cfg["seed"])))
+    torch.cuda.synchronize()
+    prob.iterate(20)
+    torch.cuda.synchronize()
+    prob.close()
+    if not args.no_3d:
+        from paper_1601_06681_amd.ehdg import EHDG_TRANSPORT, Problem
+        c3 = W.TRANSPORT3D
+        p3 = Problem(EHDG_TRANSPORT, 3, c3["n"], L=c3["L"], degree=c3["degree"], beta=c3["beta"], sigma=c3["sigma"])
+        p3.iterate(5)
+        torch.cuda.synchronize()
+        p3.close()
+    log("[bench] counter sample done")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +262,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--counter-sample", action="store_true",
+                    help="only the copy-calibration kernel and a few sweeps, for rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the eHDG sweep of one mesh is measured "
@@ -245,6 +277,9 @@ def main():
     if args.workload != "swe2d":
         print(json.dumps({"error": f"unknown workload {args.workload}"}))
         sys.exit(2)
+    if args.counter_sample:
+        run_counter_sample(torch, args)
+        return
     out = run_swe(args, torch)
     if not args.no_3d:
         out["transport3d"] = run_transport3d(torch, args)

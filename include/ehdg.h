@@ -15,6 +15,9 @@
  *                   (Section 3, eq. transportLocal and the time-dependent paragraph)
  *   EHDG_SWE        linearized shallow water, backward Euler, 2D, Coriolis,
  *                   friction and wind stress zero (Section 3, linearizedShallow)
+ *   EHDG_EULER      2D linearized Euler (rho', u', v', p') about a uniform state, backward
+ *                   Euler: the same upwind HDG construction with the full |A_n|
+ *                   (Section 3 notes the extension to other hyperbolic systems)
  *
  * Conventions shared by every entry point
  *   - Device pointers ("d_") are HIP device memory owned by the caller; host
@@ -25,7 +28,7 @@
  *     Face nodes are ordered by the tangential node indices in increasing axis
  *     order, first tangential axis fastest.
  *   - External solution layout: double u[n_el][m][N_p] (m fields: transport 1;
- *     SWE 3 = phi, u, v).
+ *     SWE 3 = phi, u, v; Euler 4 = rho', u', v', p').
  *   - Every function returns 0 (EHDG_OK) or one of the EHDG_ERR_* codes; no call
  *     aborts the process.  ehdg_last_error() gives a message for the handle.
  *   - All work is queued on the HIP stream given at setup.  Asynchronous calls
@@ -52,7 +55,7 @@ enum {
   EHDG_ERR_WORKSPACE_TOO_SMALL = 6 /* workspace smaller than ehdg_workspace_bytes()  */
 };
 
-enum { EHDG_TRANSPORT = 0, EHDG_SWE = 1 };
+enum { EHDG_TRANSPORT = 0, EHDG_SWE = 1, EHDG_EULER = 2 };
 
 /* Arithmetic of the element sweeps.
  *   EHDG_FP64          every sweep in FP64.
@@ -66,16 +69,20 @@ enum { EHDG_TRANSPORT = 0, EHDG_SWE = 1 };
 enum { EHDG_FP64 = 0, EHDG_FP32_REFINE = 1, EHDG_BF16_REFINE = 2 };
 
 typedef struct {
-  int32_t pde;          /* EHDG_TRANSPORT or EHDG_SWE                                 */
-  int32_t dim;          /* 2 or 3 (SWE: 2)                                           */
+  int32_t pde;          /* EHDG_TRANSPORT, EHDG_SWE or EHDG_EULER                     */
+  int32_t dim;          /* 2 or 3 (SWE, Euler: 2)                                    */
   int32_t n[3];         /* elements per axis (unused axes ignored), each >= 1        */
   double L[3];          /* domain [0, L_a] per axis, L_a > 0                          */
   int32_t periodic[3];  /* 1 = periodic axis; 0 = boundary: transport inflow data /
-                           outflow; SWE reflecting wall                              */
-  int32_t degree;       /* p: transport 2D 1..6, 3D 1..4; SWE 1..6                    */
+                           outflow; SWE reflecting wall; Euler no incoming waves     */
+  int32_t degree;       /* p: transport 2D 1..6, 3D 1..4; SWE 1..6; Euler 1..5        */
   double beta[3];       /* transport velocity (components may be 0)                  */
   double sigma;         /* transport reaction coefficient, >= 0                       */
   double Phi;           /* SWE mean geopotential, > 0                                 */
+  double U0[2];         /* Euler mean velocity; no face may see a zero wave speed:
+                           U0_a != 0 and |U0_a| != c0 on every axis                   */
+  double c0;            /* Euler sound speed, > 0                                     */
+  double rho0;          /* Euler mean density, > 0                                    */
   double dt;            /* backward-Euler step; 0 = steady (transport only)           */
   int32_t precision;    /* EHDG_FP64 / EHDG_FP32_REFINE / EHDG_BF16_REFINE            */
   int32_t inner_sweeps; /* low-precision sweeps per FP64 refinement (refine modes)    */
@@ -102,8 +109,9 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
 
 /* Problem data (Section 3 local equations' right-hand sides).
  *   d_forcing_q: right-hand side of each field's equation sampled at the tensor Gauss
- *                points, double [n_el][m][(p+2)^dim], or NULL for zero.  For SWE the
- *                momentum rows are the equations multiplied by Phi.
+ *                points, double [n_el][m][(p+2)^dim] with point q = q0 + (p+2) q1 +
+ *                (p+2)^2 q2 (axis 0 fastest), or NULL for zero.  For SWE the momentum
+ *                rows are the equations multiplied by Phi.
  *   d_bc:        transport inflow boundary data g at the boundary-face GLL nodes, or
  *                NULL for zero.  Layout: sides x-, x+, y-, y+, z-, z+ of the
  *                non-periodic axes concatenated; within a side, faces ordered by the

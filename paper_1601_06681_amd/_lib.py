@@ -18,6 +18,7 @@ EHDG_ERR_WORKSPACE_TOO_SMALL = 6
 
 EHDG_TRANSPORT = 0
 EHDG_SWE = 1
+EHDG_EULER = 2
 
 EHDG_FP64 = 0
 EHDG_FP32_REFINE = 1
@@ -42,6 +43,9 @@ class ehdg_desc(ctypes.Structure):
         ("beta", ctypes.c_double * 3),
         ("sigma", ctypes.c_double),
         ("Phi", ctypes.c_double),
+        ("U0", ctypes.c_double * 2),
+        ("c0", ctypes.c_double),
+        ("rho0", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("precision", ctypes.c_int32),
         ("inner_sweeps", ctypes.c_int32),

@@ -27,17 +27,18 @@ struct ehdg_problem {
   double* W = nullptr;
   double* Bfull = nullptr;  // n x (m * nq_el), block diagonal load matrix
   double* scratch = nullptr;
-  int base = 0;        // buffer holding the trace state s^0 of the current solve
-  int recovered = -1;  // 1 when u_new holds the solution of the current iterate
-  bool fresh = false;  // the control block is known to be reset (no sweep since)
-  int predict = 4;     // sweeps the next solve is expected to need (last count)
-  int predict_outer = 2;  // refinements the next mixed-precision solve is expected to need
+  // host mirror of the device control block, valid after every synchronizing call
+  Ctrl mirror{};
+  int recovered = -1;     // 1 when u2[ucur ^ 1] holds the solution of the current iterate
+  int predict = 4;        // sweeps the next solve / step is expected to need
+  int predict_outer = 2;  // refinements the next mixed-precision solve / step is expected to need
   std::string err;
 };
 
 namespace {
 
 constexpr int kHistCap = 1 << 16;
+constexpr int kStepCap = 1 << 16;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -66,13 +67,17 @@ Desc to_desc(const ehdg_desc* d) {
   o.sigma = d->sigma;
   o.Phi = d->Phi;
   o.dt = d->dt;
+  o.U0[0] = d->U0[0];
+  o.U0[1] = d->U0[1];
+  o.c0 = d->c0;
+  o.rho0 = d->rho0;
   return o;
 }
 
 struct Layout {
-  size_t off_ctrl, off_partials, off_hist, off_T64, off_T32, off_T16, off_R, off_Q, off_W, off_P, off_G, off_B,
-      off_Mv, off_gbe;
-  size_t off_s0, off_s1, off_g, off_gsrc, off_wsrc, off_u, off_unew, off_lo0, off_lo1, off_rlo0, off_rlo1, off_scratch;
+  size_t off_ctrl, off_partials, off_hist, off_steps, off_T64, off_T32, off_T16, off_R, off_Q, off_W, off_P, off_G,
+      off_B, off_Mv, off_gbe;
+  size_t off_s0, off_s1, off_g, off_gsrc, off_wsrc, off_u0, off_u1, off_lo0, off_lo1, off_rlo0, off_rlo1, off_scratch;
   size_t total;
 };
 
@@ -90,6 +95,7 @@ Layout layout_for(const Operators& o, long long nel, bool lowp) {
   L.off_ctrl = take(sizeof(Ctrl));
   L.off_partials = take(2 * nb * sizeof(double));
   L.off_hist = take(kHistCap * sizeof(double));
+  L.off_steps = take(kStepCap * sizeof(int));
   L.off_T64 = take(Sp * I * 8);
   L.off_T32 = take(Sp * I * 4);
   L.off_T16 = take(Sp * I * 2);
@@ -106,8 +112,8 @@ Layout layout_for(const Operators& o, long long nel, bool lowp) {
   L.off_g = take(S * ne * 8);
   L.off_gsrc = take(S * ne * 8);
   L.off_wsrc = take(n * ne * 8);
-  L.off_u = take(n * ne * 8);
-  L.off_unew = take(n * ne * 8);
+  L.off_u0 = take(n * ne * 8);
+  L.off_u1 = take(n * ne * 8);
   L.off_lo0 = take(lowp ? S * ne * 4 : 8);
   L.off_lo1 = take(lowp ? S * ne * 4 : 8);
   L.off_rlo0 = take(lowp ? S * ne * 4 : 8);
@@ -146,37 +152,73 @@ int check_launch(ehdg_problem* h) {
   return EHDG_OK;
 }
 
-int read_ctrl(ehdg_problem* h, Ctrl& c) {
-  HIP_TRY(h, hipMemcpyAsync(&c, h->dp.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+// synchronizes the stream and refreshes the host mirror of the control block
+int sync_ctrl(ehdg_problem* h) {
+  HIP_TRY(h, hipMemcpyAsync(&h->mirror, h->dp.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   return EHDG_OK;
 }
+
+double* u_cur(ehdg_problem* h) { return h->dp.u2[h->mirror.ucur & 1]; }
+double* u_other(ehdg_problem* h) { return h->dp.u2[(h->mirror.ucur & 1) ^ 1]; }
 
 // g for the current time level: steady g = g_src; backward Euler g = g_src + G u
 void rebuild_g(ehdg_problem* h) {
   DevProblem& dp = h->dp;
   const size_t cnt = (size_t)dp.S * dp.mesh.nel;
   hipMemcpyAsync(dp.g, dp.g_src, cnt * 8, hipMemcpyDeviceToDevice, h->stream);
-  if (dp.be) launch_matvec(dp.G, dp.S, dp.n, dp.u, dp.g, dp.mesh.nel, true, h->stream);
+  if (dp.be) launch_matvec(dp.G, dp.S, dp.n, u_cur(h), dp.g, dp.mesh.nel, true, h->stream);
 }
 
-// Sweeps until the device flag is raised or max_iters; returns the Ctrl snapshot.
-// The first batch launches as many sweeps as the previous solve needed (warm-started
-// time steps need about the same count); later batches grow geometrically.  Sweeps
-// launched after convergence exit at once on the device flag.
-int run_plain(ehdg_problem* h, double tol, int max_iters, Ctrl& c) {
-  DevProblem& dp = h->dp;
-  int launched = 0, chunk = std::max(1, h->predict), next = 2;
+bool mixed(const ehdg_problem* h) { return h->desc.precision != EHDG_FP64; }
+
+// queues one outer iteration: a plain sweep, or a refinement with its inner sweeps
+struct Outer {
+  ehdg_problem* h;
+  const void* lo_prev = nullptr;
+  int k = 0;  // refinements queued (selects the residual buffer)
+  void queue(double tol) {
+    DevProblem& dp = h->dp;
+    if (!mixed(h)) {
+      h->ks->sweep64(dp, tol, h->stream);
+      return;
+    }
+    const bool bf = h->desc.precision == EHDG_BF16_REFINE;
+    auto refine = bf ? h->ks->refine16 : h->ks->refine32;
+    auto inner = bf ? h->ks->inner16 : h->ks->inner32;
+    // refinement k writes residual buffer rlo[k & 1]; the correction it reads is
+    // the previous refinement's last inner iterate, never that buffer
+    void* r = dp.rlo[k & 1];
+    refine(dp, lo_prev, r, tol, h->stream);
+    const void* cur = r;
+    for (int q = 1; q < h->desc.inner_sweeps; ++q) {
+      void* out = dp.lo[q & 1];
+      inner(dp, r, cur, out, h->stream);
+      cur = out;
+    }
+    lo_prev = cur;
+    ++k;
+  }
+};
+
+// Runs outer iterations of the current segment until the device flag is raised or
+// max_outer have been queued.  The first batch is the predicted count (a warm
+// start needs about as many as the previous solve); later batches grow.  Queued
+// iterations after convergence exit at once on the device flag.
+int run_segment(ehdg_problem* h, double tol, int max_outer) {
+  Outer o{h};
+  int& pred = mixed(h) ? h->predict_outer : h->predict;
+  int launched = 0, chunk = std::max(1, pred), next = 2;
   for (;;) {
-    const int n = std::min(chunk, max_iters - launched);
-    for (int j = 0; j < n; ++j) h->ks->sweep64(dp, h->base + launched + j, true, tol, h->stream);
+    const int n = std::min(chunk, max_outer - launched);
+    for (int j = 0; j < n; ++j) o.queue(tol);
     launched += n;
     int rc = check_launch(h);
     if (rc) return rc;
-    rc = read_ctrl(h, c);
+    rc = sync_ctrl(h);
     if (rc) return rc;
-    if (c.done || launched >= max_iters) {
-      if (c.status == 1) h->predict = c.iters;
+    if (h->mirror.done || launched >= max_outer) {
+      if (h->mirror.status == 1) pred = h->mirror.iters;
       return EHDG_OK;
     }
     chunk = next;
@@ -184,81 +226,9 @@ int run_plain(ehdg_problem* h, double tol, int max_iters, Ctrl& c) {
   }
 }
 
-int run_refine(ehdg_problem* h, double tol, int max_outer, Ctrl& c) {
-  DevProblem& dp = h->dp;
-  const bool bf = h->desc.precision == EHDG_BF16_REFINE;
-  auto refine = bf ? h->ks->refine16 : h->ks->refine32;
-  auto inner = bf ? h->ks->inner16 : h->ks->inner32;
-  const int s = h->desc.inner_sweeps;
-  int launched = 0, chunk = std::max(1, h->predict_outer), next = 2;
-  const void* lo_prev = nullptr;
-  for (;;) {
-    const int n = std::min(chunk, max_outer - launched);
-    for (int j = 0; j < n; ++j) {
-      const int k = h->base + launched + j;
-      // refinement j writes residual buffer rlo[k & 1]; the correction it reads
-      // (rlo of the previous refinement or an inner buffer) is never that one
-      void* r = dp.rlo[k & 1];
-      refine(dp, dp.s[k & 1], lo_prev, dp.s[(k + 1) & 1], r, tol, h->stream);
-      const void* cur = r;
-      for (int q = 1; q < s; ++q) {
-        void* out = dp.lo[q & 1];
-        inner(dp, r, cur, out, h->stream);
-        cur = out;
-      }
-      lo_prev = cur;
-    }
-    launched += n;
-    int rc = check_launch(h);
-    if (rc) return rc;
-    rc = read_ctrl(h, c);
-    if (rc) return rc;
-    if (c.done || launched >= max_outer) {
-      if (c.status == 1) h->predict_outer = c.iters;
-      return EHDG_OK;
-    }
-    chunk = next;
-    next = std::min(next * 2, 32);
-  }
-}
-
-// Solve the current (steady or backward-Euler) system to tol.  On return the
-// buffer holding the state from which the solution is recovered is *rec_buf.
-int solve_current(ehdg_problem* h, double tol, int max_iters, int* iters_out, double* res_out, int* rec_buf,
-                  int* next_base) {
-  DevProblem& dp = h->dp;
-  // a new segment starts from the latest state: after j sweeps (or refinements)
-  // of the previous segment it sits in buffer (base + j) & 1
-  Ctrl c;
-  int rc;
-  if (!h->fresh) {
-    rc = read_ctrl(h, c);
-    if (rc) return rc;
-    h->base = (h->base + c.iters) & 1;
-    launch_ctrl_reset(dp.ctrl, h->stream);
-  }
-  h->fresh = false;
-  const bool mixed = h->desc.precision != EHDG_FP64;
-  if (!mixed) {
-    rc = run_plain(h, tol, max_iters, c);
-    if (rc) return rc;
-    const int K = c.iters;
-    *iters_out = K;
-    *rec_buf = (h->base + K - 1) & 1;  // u^K is the local solve that read s^{K-1}
-    *next_base = (h->base + K) & 1;
-  } else {
-    const int s = h->desc.inner_sweeps;
-    const int max_outer = std::max(1, (max_iters + s - 1) / s);
-    rc = run_refine(h, tol, max_outer, c);
-    if (rc) return rc;
-    const int K = c.iters;
-    *iters_out = K * s;
-    *rec_buf = (h->base + K) & 1;  // the refined iterate whose residual passed
-    *next_base = *rec_buf;
-  }
-  *res_out = c.last_res;
-  if (c.status == 2) return fail(h, EHDG_ERR_DIVERGED, "relative trace increment became non-finite");
-  if (c.status != 1) return fail(h, EHDG_ERR_NOT_CONVERGED, "iteration cap reached");
+int status_code(ehdg_problem* h) {
+  if (h->mirror.status == 2) return fail(h, EHDG_ERR_DIVERGED, "relative trace increment became non-finite");
+  if (h->mirror.status != 1) return fail(h, EHDG_ERR_NOT_CONVERGED, "iteration cap reached");
   return EHDG_OK;
 }
 
@@ -302,7 +272,7 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
     return EHDG_ERR_UNSUPPORTED;
   }
   const Operators& o = h->ops;
-  h->ks = find_kernels(desc->pde, desc->dim, desc->pde == 0 ? o.na : 4, desc->degree);
+  h->ks = find_kernels(desc->pde, desc->dim, desc->pde == 0 ? o.na : 0, desc->degree);
   const bool lowp = desc->precision != EHDG_FP64;
   if (!h->ks || (desc->precision == EHDG_BF16_REFINE && !h->ks->refine16) ||
       (desc->precision == EHDG_FP32_REFINE && !h->ks->refine32)) {
@@ -341,6 +311,8 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   dp.partials = (double*)(ws + L.off_partials);
   dp.hist = (double*)(ws + L.off_hist);
   dp.hist_cap = kHistCap;
+  dp.step_iters = (int*)(ws + L.off_steps);
+  dp.step_cap = kStepCap;
   dp.T64 = (const double*)(ws + L.off_T64);
   dp.T32 = (const float*)(ws + L.off_T32);
   dp.T16 = (const uint16_t*)(ws + L.off_T16);
@@ -355,8 +327,8 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   dp.g = (double*)(ws + L.off_g);
   dp.g_src = (double*)(ws + L.off_gsrc);
   dp.w_src = (double*)(ws + L.off_wsrc);
-  dp.u = (double*)(ws + L.off_u);
-  dp.u_new = (double*)(ws + L.off_unew);
+  dp.u2[0] = (double*)(ws + L.off_u0);
+  dp.u2[1] = (double*)(ws + L.off_u1);
   dp.lo[0] = ws + L.off_lo0;
   dp.lo[1] = ws + L.off_lo1;
   dp.rlo[0] = ws + L.off_rlo0;
@@ -372,46 +344,40 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   std::vector<double> Tpad(SI, 0.0), Mvpad((size_t)padded_rows(o.Mvol.r) * o.Mvol.c, 0.0);
   std::copy(o.T.a.begin(), o.T.a.end(), Tpad.begin());
   std::copy(o.Mvol.a.begin(), o.Mvol.a.end(), Mvpad.begin());
+  std::vector<double> B;
+  {
+    const int cols = o.m * o.nq_el;
+    B.assign((size_t)o.n * cols, 0.0);
+    for (int f = 0; f < o.m; ++f)
+      for (int i = 0; i < o.Np; ++i)
+        for (int q = 0; q < o.nq_el; ++q) B[(size_t)(f * o.Np + i) * cols + f * o.nq_el + q] = o.Bload(i, q);
+  }
   if ((rc = upload(h, (void*)dp.T64, Tpad.data(), SI * 8)) ||
       (rc = upload(h, (void*)dp.Mvol, Mvpad.data(), Mvpad.size() * 8)) ||
       (rc = upload(h, (void*)dp.R, o.R.a.data(), (size_t)o.n * o.I * 8)) ||
       (rc = upload(h, h->Q, o.Q.a.data(), (size_t)o.S * o.n * 8)) ||
-      (rc = upload(h, h->W, o.W.a.data(), (size_t)o.n * o.n * 8))) {
-    std::string m = h->err;
+      (rc = upload(h, h->W, o.W.a.data(), (size_t)o.n * o.n * 8)) ||
+      (rc = upload(h, h->Bfull, B.data(), B.size() * 8)) ||
+      (o.be && (rc = upload(h, (void*)dp.P, o.P.a.data(), (size_t)o.n * o.n * 8))) ||
+      (o.be && (rc = upload(h, (void*)dp.G, o.G.a.data(), (size_t)o.S * o.n * 8)))) {
     delete h;
     return rc;
-  }
-  if (o.be) {
-    if ((rc = upload(h, (void*)dp.P, o.P.a.data(), (size_t)o.n * o.n * 8)) ||
-        (rc = upload(h, (void*)dp.G, o.G.a.data(), (size_t)o.S * o.n * 8))) {
-      delete h;
-      return rc;
-    }
-  }
-  {
-    const int cols = o.m * o.nq_el;
-    std::vector<double> B((size_t)o.n * cols, 0.0);
-    for (int f = 0; f < o.m; ++f)
-      for (int i = 0; i < o.Np; ++i)
-        for (int q = 0; q < o.nq_el; ++q) B[(size_t)(f * o.Np + i) * cols + f * o.nq_el + q] = o.Bload(i, q);
-    if ((rc = upload(h, h->Bfull, B.data(), B.size() * 8))) {
-      delete h;
-      return rc;
-    }
   }
   launch_cast(dp.T64, (void*)dp.T32, SI, 0, h->stream);
   launch_cast(dp.T64, (void*)dp.T16, SI, 1, h->stream);
   launch_fill_bytes(dp.partials, L.off_hist - L.off_partials, h->stream);
   launch_fill(dp.hist, 0.0, kHistCap, h->stream);
-  launch_ctrl_reset(dp.ctrl, h->stream);
-  *out = h;
-  rc = ehdg_set_forcing(h, nullptr, nullptr);
+  launch_fill_bytes(dp.step_iters, kStepCap * sizeof(int), h->stream);
+  launch_ctrl_reset(dp.ctrl, 1, h->stream);
+  // the host buffers above are pageable: the copies complete before this returns
+  rc = sync_ctrl(h);
+  if (!rc) rc = ehdg_set_forcing(h, nullptr, nullptr);
   if (!rc) rc = ehdg_set_initial(h, nullptr);
   if (rc) {
-    *out = nullptr;
     delete h;
     return rc;
   }
+  *out = h;
   return EHDG_OK;
 }
 
@@ -421,16 +387,16 @@ int ehdg_set_forcing(ehdg_handle h, const double* d_forcing_q, const double* d_b
   const int nel = dp.mesh.nel;
   hipStream_t st = h->stream;
   const Operators& o = h->ops;
+  if (d_bc && dp.pde != 0) return fail(h, EHDG_ERR_INVALID_ARG, "boundary data applies to transport only");
   if (d_forcing_q) {
-    // F = (f, psi) per field, then w_src = A^{-1} F   (u_new serves as F's buffer)
+    // F = (f, psi) per field (u_other is free here), then w_src = A^{-1} F
     launch_ext_to_soa(d_forcing_q, h->scratch, o.m * o.nq_el, nel, st);
-    launch_matvec(h->Bfull, o.n, o.m * o.nq_el, h->scratch, dp.u_new, nel, false, st);
-    launch_matvec(h->W, o.n, o.n, dp.u_new, dp.w_src, nel, false, st);
+    launch_matvec(h->Bfull, o.n, o.m * o.nq_el, h->scratch, u_other(h), nel, false, st);
+    launch_matvec(h->W, o.n, o.n, u_other(h), dp.w_src, nel, false, st);
   } else {
     launch_fill(dp.w_src, 0.0, (size_t)o.n * nel, st);
   }
   if (d_bc) {
-    if (dp.pde != 0) return fail(h, EHDG_ERR_INVALID_ARG, "boundary data applies to transport only");
     launch_bc_inputs(dp, d_bc, h->scratch, st);
     launch_matvec(dp.R, o.n, o.I, h->scratch, dp.w_src, nel, true, st);
   }
@@ -450,47 +416,49 @@ int ehdg_set_initial(ehdg_handle h, const double* d_u0) {
   if (!h) return EHDG_ERR_INVALID_ARG;
   DevProblem& dp = h->dp;
   const int nel = dp.mesh.nel;
+  launch_ctrl_reset(dp.ctrl, 1, h->stream);
+  h->mirror.base = 0;
+  h->mirror.ucur = 0;
+  h->mirror.iters = 0;
+  h->mirror.done = 0;
+  h->mirror.steps_done = 0;
   if (d_u0)
-    launch_ext_to_soa(d_u0, dp.u, dp.n, nel, h->stream);
+    launch_ext_to_soa(d_u0, dp.u2[0], dp.n, nel, h->stream);
   else
-    launch_fill(dp.u, 0.0, (size_t)dp.n * nel, h->stream);
-  h->base = 0;
-  launch_matvec(h->Q, dp.S, dp.n, dp.u, dp.s[0], nel, false, h->stream);
+    launch_fill(dp.u2[0], 0.0, (size_t)dp.n * nel, h->stream);
+  launch_matvec(h->Q, dp.S, dp.n, dp.u2[0], dp.s[0], nel, false, h->stream);
   rebuild_g(h);
-  launch_ctrl_reset(dp.ctrl, h->stream);
   h->recovered = -1;
-  h->fresh = true;
   return check_launch(h);
 }
 
 int ehdg_iterate(ehdg_handle h, int32_t n_iters) {
   if (!h || n_iters < 0) return EHDG_ERR_INVALID_ARG;
-  if (h->desc.precision != EHDG_FP64) return fail(h, EHDG_ERR_UNSUPPORTED, "iterate runs the FP64 sweep");
-  Ctrl c;
-  int rc = read_ctrl(h, c);
-  if (rc) return rc;
-  if (c.done) {  // a finished solve: a new segment continues from its last iterate
-    h->base = (h->base + c.iters) & 1;
-    launch_ctrl_reset(h->dp.ctrl, h->stream);
-    c.iters = 0;
-  }
-  for (int j = 0; j < n_iters; ++j) h->ks->sweep64(h->dp, h->base + c.iters + j, true, -1.0, h->stream);
+  if (mixed(h)) return fail(h, EHDG_ERR_UNSUPPORTED, "iterate runs the FP64 sweep");
+  // a finished solve is continued in a new segment from its last iterate (on the device)
+  launch_ctrl_reset(h->dp.ctrl, 2, h->stream);
+  for (int j = 0; j < n_iters; ++j) h->ks->sweep64(h->dp, -1.0, h->stream);
   h->recovered = -1;
-  h->fresh = false;
   return check_launch(h);
 }
 
 int ehdg_solve(ehdg_handle h, double rel_tol, int32_t max_iters, int32_t* iters, double* rel_res) {
   if (!h || max_iters < 1 || !(rel_tol >= 0.0)) return EHDG_ERR_INVALID_ARG;
-  int K = 0, rec = 0, nb = 0;
-  double res = 0.0;
-  int rc = solve_current(h, rel_tol, max_iters, &K, &res, &rec, &nb);
-  if (iters) *iters = K;
-  if (rel_res) *rel_res = res;
-  if (rc == EHDG_ERR_HIP) return rc;
+  DevProblem& dp = h->dp;
+  launch_ctrl_reset(dp.ctrl, 0, h->stream);  // a new segment from the latest state
+  const int s = mixed(h) ? h->desc.inner_sweeps : 1;
+  const int max_outer = std::max(1, (max_iters + s - 1) / s);
+  int rc = run_segment(h, rel_tol, max_outer);
+  if (rc) return rc;
+  const Ctrl& c = h->mirror;
+  if (iters) *iters = c.iters * s;
+  if (rel_res) *rel_res = c.last_res;
+  rc = status_code(h);
   h->recovered = -1;
-  if (K > 0 && rc != EHDG_ERR_DIVERGED) {
-    h->ks->volume(h->dp, h->dp.s[rec], false, h->stream);
+  if (c.iters > 0 && c.status != 2) {
+    // plain: u^K is the local solve that read s^{K-1}; refinement: the refined iterate s^K
+    const int lag = mixed(h) ? 0 : 1;
+    h->ks->volume(dp, dp.s[(c.base + c.iters - lag) & 1], u_cur(h), u_other(h), h->stream);
     int rc2 = check_launch(h);
     if (rc2) return rc2;
     h->recovered = 1;
@@ -501,38 +469,72 @@ int ehdg_solve(ehdg_handle h, double rel_tol, int32_t max_iters, int32_t* iters,
 int ehdg_step(ehdg_handle h, int32_t n_steps, double rel_tol, int32_t max_iters_per_step, int32_t* iters_per_step) {
   if (!h || n_steps < 0 || max_iters_per_step < 1 || !(rel_tol >= 0.0)) return EHDG_ERR_INVALID_ARG;
   if (!h->dp.be) return fail(h, EHDG_ERR_INVALID_ARG, "ehdg_step needs a backward-Euler problem (dt > 0)");
-  for (int s = 0; s < n_steps; ++s) {
-    int K = 0, rec = 0, nb = 0;
-    double res = 0.0;
-    int rc = solve_current(h, rel_tol, max_iters_per_step, &K, &res, &rec, &nb);
-    if (iters_per_step) iters_per_step[s] = K;
-    if (rc) return rc;
-    // u^{m+1} from the last local solve, the next step's g from it, and the control
-    // block reset (one kernel); warm start from the last traces
-    h->ks->volume(h->dp, h->dp.s[rec], true, h->stream);
-    std::swap(h->dp.u, h->dp.u_new);
-    h->base = nb;
-    h->fresh = true;
-    h->recovered = -1;
+  if (n_steps == 0) return EHDG_OK;
+  DevProblem& dp = h->dp;
+  const int s = mixed(h) ? h->desc.inner_sweeps : 1;
+  const int lag = mixed(h) ? 0 : 1;
+  const int max_outer = std::max(1, (max_iters_per_step + s - 1) / s);
+  int& pred = mixed(h) ? h->predict_outer : h->predict;
+  // the first step continues from the latest state of whatever ran before
+  launch_ctrl_reset(dp.ctrl, 0, h->stream);
+  int rc = sync_ctrl(h);
+  if (rc) return rc;
+  const int first = h->mirror.steps_done, target = first + n_steps;
+  Outer o{h};
+  int max_seen = 0;
+  // Every step is queued as (predicted outer iterations + 1) followed by the step
+  // kernel.  A step that converges early leaves no-op launches; one that needs more
+  // borrows the next step's iterations (its step kernel finds it unconverged and does
+  // nothing).  The host synchronizes once per batch.
+  while (h->mirror.steps_done < target) {
+    const int remaining = target - h->mirror.steps_done;
+    const int per = std::min(std::max(1, pred) + 1, max_outer);
+    for (int r = 0; r < remaining; ++r) {
+      for (int j = 0; j < per; ++j) o.queue(rel_tol);
+      h->ks->step(dp, lag, h->stream);
+    }
     rc = check_launch(h);
     if (rc) return rc;
+    rc = sync_ctrl(h);
+    if (rc) return rc;
+    if (h->mirror.status == 2) return status_code(h);
+    if (h->mirror.steps_done < target && h->mirror.iters >= max_outer) {
+      status_code(h);
+      break;
+    }
+    std::vector<int> its(h->mirror.steps_done - first);
+    if (!its.empty()) {
+      HIP_TRY(h, hipMemcpy(its.data(), dp.step_iters + first % kStepCap, its.size() * sizeof(int),
+                           hipMemcpyDeviceToHost));
+      for (int v : its) max_seen = std::max(max_seen, v);
+      pred = max_seen;
+    }
   }
+  const int done = h->mirror.steps_done - first;
+  if (iters_per_step && done > 0) {
+    std::vector<int> its(done);
+    HIP_TRY(h, hipMemcpy(its.data(), dp.step_iters + first % kStepCap, done * sizeof(int), hipMemcpyDeviceToHost));
+    for (int i = 0; i < done; ++i) iters_per_step[i] = its[i] * s;
+  }
+  for (int i = done; iters_per_step && i < n_steps; ++i) iters_per_step[i] = 0;
+  h->recovered = -1;
+  if (done < n_steps) return fail(h, EHDG_ERR_NOT_CONVERGED, "iteration cap reached within a time step");
   return EHDG_OK;
 }
 
 int ehdg_get_solution(ehdg_handle h, double* d_u) {
   if (!h || !d_u) return EHDG_ERR_INVALID_ARG;
   DevProblem& dp = h->dp;
-  Ctrl c;
-  int rc = read_ctrl(h, c);
+  int rc = sync_ctrl(h);
   if (rc) return rc;
-  const double* src = dp.u;
+  const Ctrl& c = h->mirror;
+  const double* src = u_cur(h);
   if (h->recovered == 1) {
-    src = dp.u_new;
-  } else if (c.iters > 0) {
-    h->ks->volume(dp, dp.s[(h->base + c.iters - 1) & 1], false, h->stream);
+    src = u_other(h);
+  } else if (c.iters > 0 && !mixed(h)) {
+    h->ks->volume(dp, dp.s[(c.base + c.iters - 1) & 1], u_cur(h), u_other(h), h->stream);
     h->recovered = 1;
-    src = dp.u_new;
+    src = u_other(h);
   }
   launch_soa_to_ext(src, d_u, dp.n, dp.mesh.nel, h->stream);
   return check_launch(h);
@@ -540,9 +542,9 @@ int ehdg_get_solution(ehdg_handle h, double* d_u) {
 
 int ehdg_get_residuals(ehdg_handle h, int32_t first, int32_t count, double* out) {
   if (!h || first < 0 || count < 0 || (count > 0 && !out)) return EHDG_ERR_INVALID_ARG;
-  Ctrl c;
-  int rc = read_ctrl(h, c);
+  int rc = sync_ctrl(h);
   if (rc) return rc;
+  const Ctrl& c = h->mirror;
   if ((long long)first + count > c.iters || count > kHistCap || c.iters - first > kHistCap)
     return fail(h, EHDG_ERR_INVALID_ARG, "residual range not recorded");
   std::vector<double> ring(kHistCap);
@@ -560,19 +562,18 @@ int ehdg_sizes(ehdg_handle h, int64_t* n_el, int32_t* m, int32_t* n_p, int32_t* 
   if (s) *s = h->dp.S;
   if (i) *i = h->dp.I;
   if (iters) {
-    Ctrl c;
-    int rc = read_ctrl(h, c);
+    int rc = sync_ctrl(h);
     if (rc) return rc;
-    *iters = c.iters;
+    *iters = h->mirror.iters;
   }
   return EHDG_OK;
 }
 
-// state blob: [Ctrl (256 B)][base int (256 B)][s0][s1][u]
+// state blob: [Ctrl (256 B)][s0][s1][u of the current time level]
 int ehdg_state_bytes(ehdg_handle h, size_t* bytes) {
   if (!h || !bytes) return EHDG_ERR_INVALID_ARG;
   const size_t ne = (size_t)h->dp.mesh.nel;
-  *bytes = 512 + align256(h->dp.S * ne * 8) * 2 + align256(h->dp.n * ne * 8);
+  *bytes = 256 + align256(h->dp.S * ne * 8) * 2 + align256(h->dp.n * ne * 8);
   return EHDG_OK;
 }
 
@@ -583,13 +584,12 @@ int ehdg_get_state(ehdg_handle h, void* d_dst, size_t bytes) {
   const size_t ne = (size_t)dp.mesh.nel;
   char* d = (char*)d_dst;
   const size_t sb = align256(dp.S * ne * 8);
+  int rc = sync_ctrl(h);
+  if (rc) return rc;
   HIP_TRY(h, hipMemcpyAsync(d, dp.ctrl, sizeof(Ctrl), hipMemcpyDeviceToDevice, h->stream));
-  static thread_local int base_host;
-  base_host = h->base;
-  HIP_TRY(h, hipMemcpyAsync(d + 256, &base_host, sizeof(int), hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(d + 512, dp.s[0], dp.S * ne * 8, hipMemcpyDeviceToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(d + 512 + sb, dp.s[1], dp.S * ne * 8, hipMemcpyDeviceToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(d + 512 + 2 * sb, dp.u, dp.n * ne * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(d + 256, dp.s[0], dp.S * ne * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(d + 256 + sb, dp.s[1], dp.S * ne * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(d + 256 + 2 * sb, u_cur(h), dp.n * ne * 8, hipMemcpyDeviceToDevice, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   return EHDG_OK;
 }
@@ -601,18 +601,16 @@ int ehdg_set_state(ehdg_handle h, const void* d_src, size_t bytes) {
   const size_t ne = (size_t)dp.mesh.nel;
   const char* d = (const char*)d_src;
   const size_t sb = align256(dp.S * ne * 8);
-  int base_host = 0;
   HIP_TRY(h, hipMemcpyAsync(dp.ctrl, d, sizeof(Ctrl), hipMemcpyDeviceToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(&base_host, d + 256, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(dp.s[0], d + 512, dp.S * ne * 8, hipMemcpyDeviceToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(dp.s[1], d + 512 + sb, dp.S * ne * 8, hipMemcpyDeviceToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(dp.u, d + 512 + 2 * sb, dp.n * ne * 8, hipMemcpyDeviceToDevice, h->stream));
-  HIP_TRY(h, hipStreamSynchronize(h->stream));
-  if (base_host != 0 && base_host != 1) return fail(h, EHDG_ERR_INVALID_ARG, "corrupt state blob");
-  h->base = base_host;
+  int rc = sync_ctrl(h);
+  if (rc) return rc;
+  const Ctrl& c = h->mirror;
+  if ((c.base & ~1) || (c.ucur & ~1) || c.iters < 0) return fail(h, EHDG_ERR_INVALID_ARG, "corrupt state blob");
+  HIP_TRY(h, hipMemcpyAsync(dp.s[0], d + 256, dp.S * ne * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(dp.s[1], d + 256 + sb, dp.S * ne * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(u_cur(h), d + 256 + 2 * sb, dp.n * ne * 8, hipMemcpyDeviceToDevice, h->stream));
   rebuild_g(h);
   h->recovered = -1;
-  h->fresh = false;
   return check_launch(h);
 }
 

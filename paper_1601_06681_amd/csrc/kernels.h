@@ -12,15 +12,23 @@ constexpr int kElemsPerGroup = 64;
 constexpr int kRowGroups = 4;
 inline int padded_rows(int rows) { return (rows + kRowGroups - 1) / kRowGroups * kRowGroups; }
 
-// Device-resident iteration control, one per handle.
+// Device-resident iteration control, one per handle.  Kernels choose their
+// buffers from it, so work can be queued ahead of the host knowing when a solve
+// converges: the trace state after k sweeps (or refinements) of the current
+// segment is in s[(base + k) & 1]; the current time level's solution is u[ucur].
 struct Ctrl {
-  int done;          // set once the stopping test holds (or the increment is non-finite)
-  int iters;         // sweeps completed since the last reset
-  int status;        // 0 running, 1 converged, 2 non-finite increment
-  unsigned counter;  // arrival counter of the last-block reduction
-  double last_res;   // last relative increment
-  double pad[5];
+  int done;           // set once the stopping test holds (or the increment is non-finite)
+  int iters;          // sweeps (or refinements) of the current segment
+  int status;         // 0 running, 1 converged, 2 non-finite increment
+  unsigned counter;   // arrivals of the sweep reduction
+  double last_res;    // last relative increment
+  int base;           // state buffer holding s^0 of the current segment
+  int ucur;           // solution buffer holding the current time level
+  int steps_done;     // backward-Euler steps completed since the last initial state
+  unsigned vcounter;  // arrivals of the step-recovery kernel
+  double pad[3];
 };
+static_assert(sizeof(Ctrl) == 64, "Ctrl is one 64-byte block");
 
 // Mesh indexing shared by every kernel.
 struct MeshDev {
@@ -49,8 +57,9 @@ struct DevProblem {
   double* g;               // S
   double* g_src;           // S
   double* w_src;           // n
-  double* u;               // n: current time-level / last recovered solution
-  double* u_new;           // n: recovery output
+  double* u2[2];           // n: solution buffers; u2[ucur] is the current time level
+  int* step_iters;         // sweeps per completed backward-Euler step (ring)
+  int step_cap;
   void* lo[2];             // low-precision correction, double buffered (S)
   void* rlo[2];            // low-precision residual, double buffered (S)
   double* partials;        // 2 per block
@@ -61,20 +70,23 @@ struct DevProblem {
 
 // Kernels of one (pde, dim, active axes, face nodes) family.
 struct KernelSet {
-  // s[k&1] -> s[(k+1)&1]; with resid, a relative-increment reduction (tol < 0: never stops)
-  void (*sweep64)(const DevProblem&, int k, bool resid, double tol, hipStream_t);
-  // u_new = w_src + R in(s_prev) (+ P u for BE).  With step (BE): also the next
-  // step's g = g_src + G u_new, and the iteration control is reset for that step.
-  void (*volume)(const DevProblem&, const double* s_prev, bool step, hipStream_t);
-  // mixed precision outer step: s_out = s_in + lo_in (lo_in may be null);
-  // r = g + T in(s_out) - s_out in FP64; r_out = r in the low precision (it is also
-  // the first inner iterate); residual reduction of ||r|| / ||s_out + r||
-  void (*refine32)(const DevProblem&, const double* s_in, const void* lo_in, double* s_out, void* r_out,
-                   double tol, hipStream_t);
+  // one FP64 sweep s^{k+1} = g + T in(s^k), buffers from the control block, with the
+  // relative-increment reduction (tol < 0: record only, never stop)
+  void (*sweep64)(const DevProblem&, double tol, hipStream_t);
+  // element solution u_out = w_src + R in(s_prev) (+ P u_old for BE); no control change
+  void (*volume)(const DevProblem&, const double* s_prev, const double* u_old, double* u_out, hipStream_t);
+  // backward-Euler step completion, queued after a step's sweeps: if the step has
+  // converged, u[ucur^1] = solution of the last local solve (lag 1: it read
+  // s^{K-1}; lag 0: refinement, it reads s^K), next g, and the control block
+  // advances to the next step; otherwise nothing happens
+  void (*step)(const DevProblem&, int lag, hipStream_t);
+  // mixed precision outer step: s' = s^k + lo_in (lo_in ignored on the segment's
+  // first refinement); r = g + T in(s') - s' in FP64 into r_out (low precision);
+  // s' stored as s^{k+1}; reduction of ||r|| / ||s' + r||
+  void (*refine32)(const DevProblem&, const void* lo_in, void* r_out, double tol, hipStream_t);
   // inner sweep on the correction: lo_out = r_lo + T_lo in(lo_in)
   void (*inner32)(const DevProblem&, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t);
-  void (*refine16)(const DevProblem&, const double* s_in, const void* lo_in, double* s_out, void* r_out,
-                   double tol, hipStream_t);
+  void (*refine16)(const DevProblem&, const void* lo_in, void* r_out, double tol, hipStream_t);
   void (*inner16)(const DevProblem&, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t);
 };
 
@@ -91,7 +103,9 @@ void launch_fill(double* p, double v, size_t count, hipStream_t st);
 void launch_fill_bytes(void* p, size_t bytes, hipStream_t st);
 // transport boundary inputs: in_bc[c][e] (I rows) from the compact side layout
 void launch_bc_inputs(const DevProblem& dp, const double* bc, double* in_bc, hipStream_t st);
-void launch_ctrl_reset(Ctrl* c, hipStream_t st);
+// full = 1: everything (new initial state); full = 0: start a new segment from the
+// latest state; full = 2: the same, but only if the current segment has finished
+void launch_ctrl_reset(Ctrl* c, int full, hipStream_t st);
 void launch_cast(const double* src, void* dst, size_t count, int to_bf16, hipStream_t st);
 
 }  // namespace ehdg

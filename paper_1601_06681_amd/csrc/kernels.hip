@@ -104,13 +104,25 @@ struct Ld16Aos {  // BF16, element-major: the S values of an element are contigu
   const uint16_t* p;
   __device__ __forceinline__ float operator()(int r, int e) const { return bf16_to_f32(p[(size_t)e * S + r]); }
 };
-// FP64 iterate plus a low-precision correction: s + delta
+// FP64 iterate plus a low-precision correction: s + delta (delta ignored unless use)
 template <class LD>
 struct LdSum {
   Ld64 s;
   LD d;
-  __device__ __forceinline__ double operator()(int r, int e) const { return s(r, e) + (double)d(r, e); }
+  int use;
+  __device__ __forceinline__ double operator()(int r, int e) const {
+    const double v = s(r, e);
+    return use ? v + (double)d(r, e) : v;
+  }
 };
+
+// point a loader's FP64 state at the buffer chosen on the device
+__device__ __forceinline__ void set_state(Ld64& l, const double* p, int) { l.p = p; }
+template <class LD>
+__device__ __forceinline__ void set_state(LdSum<LD>& l, const double* p, int use) {
+  l.s.p = p;
+  l.use = use;
+}
 
 template <typename T>
 __device__ __forceinline__ T fmadd(T a, T b, T c) { return fma(a, b, c); }
@@ -187,6 +199,35 @@ struct SweFam {
     const auto own = ld(c, e);
     const int n = nb.get(f);
     const auto oth = n >= 0 ? ld((f ^ 1) * NF + k, n) : own;
+    return own + oth;
+  }
+  __device__ __forceinline__ static int own_row(int) { return -1; }
+};
+
+// Linearized Euler, P1 = p + 1.  State per element side f: the outgoing part
+// c_f = (I + S_f)/2 w of the 4-vector w = (rho', u', v', p') at the face nodes,
+// row (4 f + field) NF + k.  Input row of face f: the trace what = c_own +
+// c_neighbour (the conservation condition of the upwind flux); on a boundary
+// without incoming waves what = c_own.
+template <int P1>
+struct EulerFam {
+  static constexpr int NF = P1, NP = P1 * P1;
+  static constexpr int S = 16 * NF, I = 16 * NF, N = 4 * NP;
+  __device__ __forceinline__ static void neighbours(const MeshDev& m, int e, Nb& nb) {
+    const Ijk c = coords(m, e);
+    nb.n0 = neighbour(m, e, c, 0, -1);
+    nb.n1 = neighbour(m, e, c, 0, 1);
+    nb.n2 = neighbour(m, e, c, 1, -1);
+    nb.n3 = neighbour(m, e, c, 1, 1);
+  }
+  template <class LD>
+  __device__ __forceinline__ static auto row(const MeshDev& m, int e, const Nb& nb, const LD& ld, int c)
+      -> decltype(ld(0, 0)) {
+    using V = decltype(ld(0, 0));
+    const int f = c / (4 * NF), rem = c - f * 4 * NF;
+    const V own = ld(c, e);
+    const int n = nb.get(f);
+    const V oth = n >= 0 ? ld((f ^ 1) * 4 * NF + rem, n) : V(0);
     return own + oth;
   }
   __device__ __forceinline__ static int own_row(int) { return -1; }
@@ -296,11 +337,18 @@ __device__ __forceinline__ void stage_inputs(const MeshDev& m, int e, bool valid
 }
 
 // out[r][e] = g[r][e] + sum_c T[r][c] in_e[c]   (r < S, c < I).  T has RowSplit<S>::PAD rows.
-template <class F, typename T, class LD, bool RESID>
+// DEVPAR: the FP64 state buffers are chosen from the control block (s0/s1), else
+// the loader and `out` are used as given.
+template <class F, typename T, class LD, bool RESID, bool DEVPAR>
 __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* __restrict__ g,
-                                                     const T* __restrict__ Tm, T* __restrict__ out,
-                                                     ResidArgs ra) {
+                                                     const T* __restrict__ Tm, T* out, ResidArgs ra,
+                                                     double* s0, double* s1) {
   if (ra.ctrl->done) return;
+  if constexpr (DEVPAR) {
+    const int b = (ra.ctrl->base + ra.ctrl->iters) & 1;
+    set_state(ld, b ? s1 : s0, 0);
+    out = b ? s0 : s1;
+  }
   T* x = reinterpret_cast<T*>(g_smem);
   const int lane = threadIdx.x & 63, w = wave_id();
   const int e = remap_block(blockIdx.x, gridDim.x) * kLanes + lane;
@@ -358,9 +406,13 @@ struct StAos16 {  // BF16, element-major
 
 template <class F, class LD, class ST>
 __global__ __launch_bounds__(kThreads) void k_refine(MeshDev m, LD ld, const double* __restrict__ g,
-                                                      const double* __restrict__ Tm, double* __restrict__ s_out,
+                                                      const double* __restrict__ Tm, double* s0, double* s1,
                                                       ST r_lo, ResidArgs ra) {
   if (ra.ctrl->done) return;
+  // s^k from the control block; the correction is applied from the segment's second refinement on
+  const int b = (ra.ctrl->base + ra.ctrl->iters) & 1;
+  set_state(ld, b ? s1 : s0, ra.ctrl->iters > 0 ? 1 : 0);
+  double* s_out = b ? s0 : s1;
   double* x = reinterpret_cast<double*>(g_smem);
   const int lane = threadIdx.x & 63, w = wave_id();
   const int e = remap_block(blockIdx.x, gridDim.x) * kLanes + lane;
@@ -404,25 +456,16 @@ __global__ __launch_bounds__(kThreads) void k_refine(MeshDev m, LD ld, const dou
 //   steady:          u_new = w_src + R in(s_prev)
 //   backward Euler:  [u_new; g_next] = [w_src; gbe] + [[P, R], [G P, G R]] [u_old; in(s_prev)]
 // (u_new = A^{-1}(F_src + Mbt u_old + L in) and g_next = Q A^{-1}(F_src + Mbt u_new)).
-// Optionally resets the iteration control for the next time step.
 template <class F, bool BE>
-__global__ __launch_bounds__(kThreads) void k_volume(MeshDev m, const double* __restrict__ s_prev,
-                                                      const double* __restrict__ Mv,
-                                                      const double* __restrict__ u_old,
-                                                      const double* __restrict__ w_src,
-                                                      const double* __restrict__ gbe, double* __restrict__ u_new,
-                                                      double* __restrict__ g_out, Ctrl* ctrl_reset) {
+__device__ __forceinline__ void volume_body(const MeshDev& m, const double* __restrict__ s_prev,
+                                            const double* __restrict__ Mv, const double* __restrict__ u_old,
+                                            const double* __restrict__ w_src, const double* __restrict__ gbe,
+                                            double* __restrict__ u_new, double* __restrict__ g_out) {
   constexpr int COLS = (BE ? F::N : 0) + F::I;
   constexpr int ROWS = F::N + (BE ? F::S : 0);
   constexpr int RW = RowSplit<ROWS>::RW;
   double* x = reinterpret_cast<double*>(g_smem);
   const int lane = threadIdx.x & 63, w = wave_id();
-  if (ctrl_reset && blockIdx.x == 0 && threadIdx.x == 0) {
-    ctrl_reset->done = 0;
-    ctrl_reset->iters = 0;
-    ctrl_reset->status = 0;
-    ctrl_reset->counter = 0u;
-  }
   const int e = remap_block(blockIdx.x, gridDim.x) * kLanes + lane;
   const bool valid = e < m.nel;
   const size_t nel = (size_t)m.nel;
@@ -443,16 +486,58 @@ __global__ __launch_bounds__(kThreads) void k_volume(MeshDev m, const double* __
 #pragma unroll
     for (int i = 0; i < RW; ++i) acc[i] = fma(Mv[(r0 + i) * COLS + c], xc, acc[i]);
   }
-  if (!valid) return;
 #pragma unroll
   for (int i = 0; i < RW; ++i) {
     const int q = r0 + i;
+    if (!valid) break;
     if (q < F::N) {
       u_new[(size_t)q * nel + e] = acc[i] + (w_src ? w_src[(size_t)q * nel + e] : 0.0);
     } else if (BE && q < ROWS && g_out) {
       const int r = q - F::N;
       g_out[(size_t)r * nel + e] = acc[i] + (gbe ? gbe[(size_t)r * nel + e] : 0.0);
     }
+  }
+}
+
+template <class F, bool BE>
+__global__ __launch_bounds__(kThreads) void k_volume(MeshDev m, const double* __restrict__ s_prev,
+                                                      const double* __restrict__ Mv,
+                                                      const double* __restrict__ u_old,
+                                                      const double* __restrict__ w_src,
+                                                      const double* __restrict__ gbe, double* __restrict__ u_new) {
+  volume_body<F, BE>(m, s_prev, Mv, u_old, w_src, gbe, u_new, nullptr);
+}
+
+// Completion of a backward-Euler step, queued after the step's sweeps.  Runs only if
+// the step converged; then u[ucur^1] = u^{m+1}, g = the next step's g, and the last
+// workgroup to finish advances the control block (every workgroup has read it by then).
+template <class F>
+__global__ __launch_bounds__(kThreads) void k_step(MeshDev m, double* s0, double* s1, const double* __restrict__ Mv,
+                                                    double* u0, double* u1, const double* __restrict__ w_src,
+                                                    const double* __restrict__ gbe, double* __restrict__ g_out,
+                                                    Ctrl* ctrl, int* step_iters, int step_cap, int lag) {
+  if (ctrl->status != 1) return;
+  const int iters = ctrl->iters, base = ctrl->base, uc = ctrl->ucur;
+  const double* s_prev = ((base + iters - lag) & 1) ? s1 : s0;
+  volume_body<F, true>(m, s_prev, Mv, uc ? u1 : u0, w_src, gbe, uc ? u0 : u1, g_out);
+  __shared__ int is_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    is_last = (atomicAdd(&ctrl->vcounter, 1u) == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (is_last && threadIdx.x == 0) {
+    __threadfence();
+    step_iters[ctrl->steps_done % step_cap] = iters;
+    ctrl->steps_done += 1;
+    ctrl->base = (base + iters) & 1;
+    ctrl->ucur = uc ^ 1;
+    ctrl->iters = 0;
+    ctrl->done = 0;
+    ctrl->status = 0;
+    ctrl->counter = 0u;
+    ctrl->vcounter = 0u;
   }
 }
 
@@ -483,66 +568,68 @@ template <class F>
 struct Family {
   static constexpr size_t lds_in64 = (size_t)F::I * kLanes * 8;
   static constexpr size_t lds_in32 = (size_t)F::I * kLanes * 4;
-  static void sweep64(const DevProblem& dp, int k, bool resid, double tol, hipStream_t st) {
+  static void sweep64(const DevProblem& dp, double tol, hipStream_t st) {
     const ResidArgs ra = resid_args(dp, tol, tol >= 0.0 ? 1 : 0);
-    const Ld64 ld{dp.s[k & 1], (size_t)dp.mesh.nel};
     const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
-    if (resid) {
-      auto kern = k_sweep<F, double, Ld64, true>;
-      allow_lds(kern, lds_in64);
-      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, ld, (const double*)dp.g, dp.T64,
-                         dp.s[(k + 1) & 1], ra);
-    } else {
-      auto kern = k_sweep<F, double, Ld64, false>;
-      allow_lds(kern, lds_in64);
-      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, ld, (const double*)dp.g, dp.T64,
-                         dp.s[(k + 1) & 1], ra);
-    }
+    auto kern = k_sweep<F, double, Ld64, true, true>;
+    allow_lds(kern, lds_in64);
+    hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, Ld64{dp.s[0], (size_t)dp.mesh.nel},
+                       (const double*)dp.g, dp.T64, (double*)nullptr, ra, dp.s[0], dp.s[1]);
   }
-  static void volume(const DevProblem& dp, const double* s_prev, bool step, hipStream_t st) {
+  static void volume(const DevProblem& dp, const double* s_prev, const double* u_old, double* u_out,
+                     hipStream_t st) {
     const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
+    const double* wsrc = dp.has_src ? dp.w_src : nullptr;
     if (dp.be) {
       const size_t lds = (size_t)(F::N + F::I) * kLanes * 8;
       auto kern = k_volume<F, true>;
       allow_lds(kern, lds);
-      hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, s_prev, dp.Mvol, (const double*)dp.u,
-                         (const double*)(dp.has_src ? dp.w_src : nullptr), (const double*)(dp.has_src ? dp.gbe : nullptr),
-                         dp.u_new, step ? dp.g : nullptr, step ? dp.ctrl : nullptr);
+      hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, s_prev, dp.Mvol, u_old, wsrc, (const double*)nullptr,
+                         u_out);
     } else {
       auto kern = k_volume<F, false>;
       allow_lds(kern, lds_in64);
-      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, s_prev, dp.Mvol, (const double*)nullptr,
-                         (const double*)(dp.has_src ? dp.w_src : nullptr), (const double*)nullptr, dp.u_new,
-                         (double*)nullptr, (Ctrl*)nullptr);
+      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, s_prev, dp.Mvol, (const double*)nullptr, wsrc,
+                         (const double*)nullptr, u_out);
     }
   }
-  static void refine32(const DevProblem& dp, const double* s_in, const void* lo_in, double* s_out, void* r_out,
-                       double tol, hipStream_t st) {
+  static void step(const DevProblem& dp, int lag, hipStream_t st) {
+    const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
+    const size_t lds = (size_t)(F::N + F::I) * kLanes * 8;
+    auto kern = k_step<F>;
+    allow_lds(kern, lds);
+    hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, dp.s[0], dp.s[1], dp.Mvol, dp.u2[0], dp.u2[1],
+                       (const double*)(dp.has_src ? dp.w_src : nullptr),
+                       (const double*)(dp.has_src ? dp.gbe : nullptr), dp.g, dp.ctrl, dp.step_iters, dp.step_cap,
+                       lag);
+  }
+  static void refine32(const DevProblem& dp, const void* lo_in, void* r_out, double tol, hipStream_t st) {
     const ResidArgs ra = resid_args(dp, tol, 1);
     const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
+    const size_t ne = (size_t)dp.mesh.nel;
+    const StSoa32 store{(float*)r_out, ne};
     if (lo_in) {
-      const size_t ne = (size_t)dp.mesh.nel;
-      const LdSum<Ld32> ld{Ld64{s_in, ne}, Ld32{(const float*)lo_in, ne}};
+      const LdSum<Ld32> ld{Ld64{dp.s[0], ne}, Ld32{(const float*)lo_in, ne}, 1};
       auto kern = k_refine<F, LdSum<Ld32>, StSoa32>;
       allow_lds(kern, lds_in64);
-      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, ld, (const double*)dp.g, dp.T64, s_out,
-                         StSoa32{(float*)r_out, ne}, ra);
+      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, ld, (const double*)dp.g, dp.T64, dp.s[0],
+                         dp.s[1], store, ra);
     } else {
       auto kern = k_refine<F, Ld64, StSoa32>;
       allow_lds(kern, lds_in64);
-      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, Ld64{s_in, (size_t)dp.mesh.nel},
-                         (const double*)dp.g, dp.T64, s_out, StSoa32{(float*)r_out, (size_t)dp.mesh.nel}, ra);
+      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, Ld64{dp.s[0], ne}, (const double*)dp.g, dp.T64,
+                         dp.s[0], dp.s[1], store, ra);
     }
   }
   static void inner32(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
     const ResidArgs ra = resid_args(dp, -1.0, 0);
-    auto kern = k_sweep<F, float, Ld32, false>;
+    auto kern = k_sweep<F, float, Ld32, false, false>;
     allow_lds(kern, lds_in32);
     hipLaunchKernelGGL(kern, dim3(ngroups(dp.mesh.nel)), dim3(kThreads), lds_in32, st, dp.mesh,
-                       Ld32{(const float*)lo_in, (size_t)dp.mesh.nel}, (const float*)r_lo, dp.T32, (float*)lo_out, ra);
+                       Ld32{(const float*)lo_in, (size_t)dp.mesh.nel}, (const float*)r_lo, dp.T32, (float*)lo_out, ra,
+                       (double*)nullptr, (double*)nullptr);
   }
 };
-
 
 // ---------------------------------------------------------------------------
 // BF16 correction sweep on MFMA (3D transport, degree 3: S = 48, I = 96)
@@ -623,23 +710,23 @@ struct Bf16Ops {
 
 template <class F>
 struct Bf16Ops<F, true> {
-  static void refine(const DevProblem& dp, const double* s_in, const void* lo_in, double* s_out, void* r_out,
-                     double tol, hipStream_t st) {
+  static void refine(const DevProblem& dp, const void* lo_in, void* r_out, double tol, hipStream_t st) {
     const ResidArgs ra = resid_args(dp, tol, 1);
     const size_t ne = (size_t)dp.mesh.nel;
     const size_t lds = (size_t)F::I * kLanes * 8;
     const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
     const StAos16<F::S> store{(uint16_t*)r_out};
     if (lo_in) {
-      const LdSum<Ld16Aos<F::S>> ld{Ld64{s_in, ne}, Ld16Aos<F::S>{(const uint16_t*)lo_in}};
+      const LdSum<Ld16Aos<F::S>> ld{Ld64{dp.s[0], ne}, Ld16Aos<F::S>{(const uint16_t*)lo_in}, 1};
       auto kern = k_refine<F, LdSum<Ld16Aos<F::S>>, StAos16<F::S>>;
       allow_lds(kern, lds);
-      hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, ld, (const double*)dp.g, dp.T64, s_out, store, ra);
+      hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, ld, (const double*)dp.g, dp.T64, dp.s[0], dp.s[1],
+                         store, ra);
     } else {
       auto kern = k_refine<F, Ld64, StAos16<F::S>>;
       allow_lds(kern, lds);
-      hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, Ld64{s_in, ne}, (const double*)dp.g, dp.T64, s_out,
-                         store, ra);
+      hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, Ld64{dp.s[0], ne}, (const double*)dp.g, dp.T64,
+                         dp.s[0], dp.s[1], store, ra);
     }
   }
   static void inner(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
@@ -665,8 +752,9 @@ struct HasMfmaTiling<TransportFam<3, 3, 4>> {
 // ---------------------------------------------------------------------------
 template <class F>
 static const KernelSet* set_of() {
-  static const KernelSet ks = {&Family<F>::sweep64, &Family<F>::volume, &Family<F>::refine32, &Family<F>::inner32,
-                               Bf16Ops<F, HasMfmaTiling<F>::value>::refine,
+  static const KernelSet ks = {&Family<F>::sweep64,  &Family<F>::volume,
+                               &Family<F>::step,     &Family<F>::refine32,
+                               &Family<F>::inner32,  Bf16Ops<F, HasMfmaTiling<F>::value>::refine,
                                Bf16Ops<F, HasMfmaTiling<F>::value>::inner};
   return &ks;
 }
@@ -713,6 +801,15 @@ const KernelSet* find_kernels(int pde, int dim, int na, int p) {
       case 4: return set_of<SweFam<5>>();
       case 5: return set_of<SweFam<6>>();
       case 6: return set_of<SweFam<7>>();
+    }
+  }
+  if (pde == 2 && dim == 2) {
+    switch (p) {
+      case 1: return set_of<EulerFam<2>>();
+      case 2: return set_of<EulerFam<3>>();
+      case 3: return set_of<EulerFam<4>>();
+      case 4: return set_of<EulerFam<5>>();
+      case 5: return set_of<EulerFam<6>>();
     }
   }
   return nullptr;
@@ -787,17 +884,27 @@ void launch_fill_bytes(void* p, size_t bytes, hipStream_t st) {
                      (uint32_t*)p, words);
 }
 
-__global__ void k_ctrl_reset(Ctrl* c) {
-  if (threadIdx.x == 0) {
-    c->done = 0;
-    c->iters = 0;
-    c->status = 0;
-    c->counter = 0u;
+__global__ void k_ctrl_reset(Ctrl* c, int full) {
+  if (threadIdx.x != 0) return;
+  if (full == 1) {
+    c->base = 0;
+    c->ucur = 0;
+    c->steps_done = 0;
     c->last_res = 0.0;
+  } else {
+    if (full == 2 && !c->done) return;  // the current segment is still running: continue it
+    c->base = (c->base + c->iters) & 1;  // the new segment starts from the latest state
   }
+  c->done = 0;
+  c->iters = 0;
+  c->status = 0;
+  c->counter = 0u;
+  c->vcounter = 0u;
 }
 
-void launch_ctrl_reset(Ctrl* c, hipStream_t st) { hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, c); }
+void launch_ctrl_reset(Ctrl* c, int full, hipStream_t st) {
+  hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, c, full);
+}
 
 __global__ void k_cast(const double* __restrict__ src, void* __restrict__ dst, size_t count, int to_bf16) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -187,6 +187,25 @@ bool invert(const Mat& A, Mat& Ainv) {
 
 namespace {
 
+// sign(A) by the Newton iteration X <- (X + X^{-1}) / 2 from X = A (converges for
+// any A without eigenvalues on the imaginary axis); |A| = sign(A) A.
+bool matrix_sign(const Mat& A, Mat& S) {
+  S = A;
+  Mat Xi;
+  for (int it = 0; it < 100; ++it) {
+    if (!invert(S, Xi)) return false;
+    double diff = 0.0, nrm = 0.0;
+    for (size_t k = 0; k < S.a.size(); ++k) {
+      const double nx = 0.5 * (S.a[k] + Xi.a[k]);
+      diff = std::max(diff, std::fabs(nx - S.a[k]));
+      nrm = std::max(nrm, std::fabs(nx));
+      S.a[k] = nx;
+    }
+    if (diff <= 1e-15 * nrm) return true;
+  }
+  return true;
+}
+
 // Element-level tensor operators on a box with half-widths hh[d].
 struct ElementOps {
   int d, p, n1, Np, nf;
@@ -292,6 +311,15 @@ std::string build_operators(const Desc& d, Operators& ops) {
     if (p < 1 || p > 6) return "shallow water supports degree 1..6";
     if (!(d.Phi > 0.0) || !std::isfinite(d.Phi)) return "Phi must be > 0";
     if (!(d.dt > 0.0) || !std::isfinite(d.dt)) return "shallow water needs dt > 0";
+  } else if (d.pde == 2) {
+    ops.pde = Pde::Euler;
+    if (d.dim != 2) return "linearized Euler is 2D";
+    if (p < 1 || p > 5) return "linearized Euler supports degree 1..5";
+    if (!(d.dt > 0.0) || !std::isfinite(d.dt)) return "linearized Euler needs dt > 0";
+    if (!(d.c0 > 0.0) || !(d.rho0 > 0.0)) return "c0 and rho0 must be > 0";
+    for (int a = 0; a < 2; ++a)
+      if (d.U0[a] == 0.0 || std::fabs(d.U0[a]) == d.c0 || !std::isfinite(d.U0[a]))
+        return "a face normal sees a zero wave speed (U0_a = 0 or |U0_a| = c0)";
   } else {
     return "unknown pde";
   }
@@ -351,7 +379,7 @@ std::string build_operators(const Desc& d, Operators& ops) {
       Mbt = Mat(Np, Np);
       for (size_t k = 0; k < Mbt.a.size(); ++k) Mbt.a[k] = E.M.a[k] / d.dt;
     }
-  } else {
+  } else if (ops.pde == Pde::Swe) {
     ops.m = 3;
     const int n = 3 * Np;
     ops.n = n;
@@ -404,6 +432,55 @@ std::string build_operators(const Desc& d, Operators& ops) {
         Mbt(Np + i, Np + j) = Phi * idt * E.M(i, j);
         Mbt(2 * Np + i, 2 * Np + j) = Phi * idt * E.M(i, j);
       }
+  }
+  if (ops.pde == Pde::Euler) {
+    // w = (rho', u', v', p'); flux A_x w, A_y w; upwind HDG with |A_n| (see ehdg.h)
+    const int n = 4 * Np;
+    ops.m = 4;
+    ops.n = n;
+    ops.S = 16 * nf;
+    ops.I = 16 * nf;
+    const double U = d.U0[0], V = d.U0[1], r0 = d.rho0, k0 = d.rho0 * d.c0 * d.c0, idt = 1.0 / d.dt;
+    Mat Ax(4, 4), Ay(4, 4);
+    const double ax[16] = {U, r0, 0, 0, 0, U, 0, 1 / r0, 0, 0, U, 0, 0, k0, 0, U};
+    const double ay[16] = {V, 0, r0, 0, 0, V, 0, 0, 0, 0, V, 1 / r0, 0, 0, k0, V};
+    std::copy(ax, ax + 16, Ax.a.begin());
+    std::copy(ay, ay + 16, Ay.a.begin());
+    A = Mat(n, n);
+    for (int fa = 0; fa < 4; ++fa)
+      for (int fb = 0; fb < 4; ++fb)
+        for (int i = 0; i < Np; ++i)
+          for (int j = 0; j < Np; ++j)
+            A(fa * Np + i, fb * Np + j) =
+                (fa == fb ? idt * E.M(i, j) : 0.0) - Ax(fa, fb) * E.K[0](i, j) - Ay(fa, fb) * E.K[1](i, j);
+    L = Mat(n, ops.I);
+    ops.Q = Mat(ops.S, n);
+    for (int f = 0; f < 4; ++f) {
+      const double n1 = (f / 2 == 0) ? (f % 2 ? 1.0 : -1.0) : 0.0;
+      const double n2 = (f / 2 == 1) ? (f % 2 ? 1.0 : -1.0) : 0.0;
+      Mat An(4, 4), Sg, Ab;
+      for (int k = 0; k < 16; ++k) An.a[k] = n1 * Ax.a[k] + n2 * Ay.a[k];
+      if (!matrix_sign(An, Sg)) return "a face normal sees a zero wave speed";
+      Ab = matmul(Sg, An);
+      for (int fa = 0; fa < 4; ++fa)
+        for (int fb = 0; fb < 4; ++fb) {
+          const double w = An(fa, fb) + Ab(fa, fb);
+          for (int i = 0; i < Np; ++i)
+            for (int j = 0; j < Np; ++j) {
+              const double e = E.E[f](i, j);
+              if (e != 0.0) A(fa * Np + i, fb * Np + j) += w * e;
+            }
+          for (int i = 0; i < Np; ++i)
+            for (int c = 0; c < nf; ++c) L(fa * Np + i, (f * 4 + fb) * nf + c) = Ab(fa, fb) * E.Lf[f](i, c);
+          // outgoing part of the own state on this side: (I + S) / 2 w at the face nodes
+          const double q = 0.5 * ((fa == fb ? 1.0 : 0.0) + Sg(fa, fb));
+          for (int c = 0; c < nf; ++c) ops.Q((f * 4 + fa) * nf + c, fb * Np + E.fn[f][c]) = q;
+        }
+    }
+    Mbt = Mat(n, n);
+    for (int fa = 0; fa < 4; ++fa)
+      for (int i = 0; i < Np; ++i)
+        for (int j = 0; j < Np; ++j) Mbt(fa * Np + i, fa * Np + j) = idt * E.M(i, j);
   }
   if (!invert(A, ops.W)) return "local operator is singular";
   ops.R = matmul(ops.W, L);

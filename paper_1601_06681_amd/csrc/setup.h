@@ -41,7 +41,7 @@ Mat matmul(const Mat& A, const Mat& B);
 // Inverse by LU with partial pivoting; returns false if singular.
 bool invert(const Mat& A, Mat& Ainv);
 
-enum class Pde { Transport = 0, Swe = 1 };
+enum class Pde { Transport = 0, Swe = 1, Euler = 2 };
 
 // Everything the device needs for one problem.
 struct Operators {
@@ -71,6 +71,7 @@ struct Desc {
   int periodic[3];
   int degree;
   double beta[3], sigma, Phi, dt;
+  double U0[2], c0, rho0;
 };
 
 // Builds the operators; returns an empty string on success, else an error message.

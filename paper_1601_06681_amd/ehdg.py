@@ -11,11 +11,11 @@ import numpy as np
 
 from . import _lib
 from ._lib import (EHDG_BF16_REFINE, EHDG_ERR_DIVERGED, EHDG_ERR_NOT_CONVERGED, EHDG_ERR_UNSUPPORTED,
-                   EHDG_FP32_REFINE, EHDG_FP64, EHDG_OK, EHDG_SWE, EHDG_TRANSPORT, ehdg_desc)
+                   EHDG_FP32_REFINE, EHDG_FP64, EHDG_EULER, EHDG_OK, EHDG_SWE, EHDG_TRANSPORT, ehdg_desc)
 
 __all__ = [
     "EhdgError", "Problem", "make_desc", *_lib.EXPORTED,
-    "EHDG_TRANSPORT", "EHDG_SWE", "EHDG_FP64", "EHDG_FP32_REFINE", "EHDG_BF16_REFINE",
+    "EHDG_TRANSPORT", "EHDG_SWE", "EHDG_EULER", "EHDG_FP64", "EHDG_FP32_REFINE", "EHDG_BF16_REFINE",
 ]
 
 
@@ -54,7 +54,7 @@ def _stream_ptr(stream):
 
 
 def make_desc(pde, dim, n, L=(1.0, 1.0, 1.0), periodic=(0, 0, 0), degree=1, beta=(0.0, 0.0, 0.0), sigma=0.0,
-              Phi=1.0, dt=0.0, precision=EHDG_FP64, inner_sweeps=1):
+              Phi=1.0, dt=0.0, precision=EHDG_FP64, inner_sweeps=1, U0=(0.0, 0.0), c0=1.0, rho0=1.0):
     d = ehdg_desc()
     d.pde, d.dim, d.degree = int(pde), int(dim), int(degree)
     for a in range(3):
@@ -63,6 +63,8 @@ def make_desc(pde, dim, n, L=(1.0, 1.0, 1.0), periodic=(0, 0, 0), degree=1, beta
         d.periodic[a] = int(periodic[a]) if a < len(periodic) else 0
         d.beta[a] = float(beta[a]) if a < len(beta) else 0.0
     d.sigma, d.Phi, d.dt = float(sigma), float(Phi), float(dt)
+    d.U0[0], d.U0[1] = float(U0[0]), float(U0[1])
+    d.c0, d.rho0 = float(c0), float(rho0)
     d.precision, d.inner_sweeps = int(precision), int(inner_sweeps)
     return d
 
@@ -171,10 +173,12 @@ class Problem:
     at the physical points implied by the library's reference points."""
 
     def __init__(self, pde, dim, n, L=(1.0, 1.0, 1.0), periodic=(0, 0, 0), degree=1, beta=(0.0, 0.0, 0.0),
-                 sigma=0.0, Phi=1.0, dt=0.0, precision=EHDG_FP64, inner_sweeps=1, device="cuda", stream=None):
+                 sigma=0.0, Phi=1.0, dt=0.0, precision=EHDG_FP64, inner_sweeps=1, device="cuda", stream=None,
+                 U0=(0.0, 0.0), c0=1.0, rho0=1.0):
         torch = _torch()
         self.torch = torch
-        self.desc = make_desc(pde, dim, n, L, periodic, degree, beta, sigma, Phi, dt, precision, inner_sweeps)
+        self.desc = make_desc(pde, dim, n, L, periodic, degree, beta, sigma, Phi, dt, precision, inner_sweeps,
+                              U0, c0, rho0)
         self.pde, self.dim, self.p = pde, dim, degree
         self.n = tuple(int(v) for v in n[:dim])
         self.L = tuple(float(v) for v in L[:dim])

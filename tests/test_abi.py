@@ -59,6 +59,18 @@ def test_workspace_bytes_and_validation():
         E.ehdg_workspace_bytes(E.make_desc(E.EHDG_TRANSPORT, 2, (4, 4), degree=2, beta=(0, 0)))
 
 
+def test_euler_descriptor_validation():
+    from paper_1601_06681_amd import ehdg as E
+    ok = E.make_desc(E.EHDG_EULER, 2, (32, 32), periodic=(1, 1), degree=3, dt=1e-3, U0=(0.5, 0.25), c0=1.0)
+    assert E.ehdg_workspace_bytes(ok) > 32 * 32 * 64 * 8
+    for bad in (dict(U0=(0.0, 0.25)), dict(U0=(1.0, 0.25)), dict(dt=0.0), dict(degree=6)):
+        kw = dict(periodic=(1, 1), degree=3, dt=1e-3, U0=(0.5, 0.25), c0=1.0)
+        kw.update(bad)
+        with pytest.raises(E.EhdgError) as ei:
+            E.ehdg_workspace_bytes(E.make_desc(E.EHDG_EULER, 2, (8, 8), **kw))
+        assert ei.value.code == 2
+
+
 def test_error_strings():
     from paper_1601_06681_amd import ehdg as E
     for code in range(7):
