@@ -69,16 +69,13 @@ __device__ __forceinline__ int neighbour(const MeshDev& m, int e, const Ijk& c, 
   return e + (v - ci) * stride;
 }
 
-// Index of the wavefront within the workgroup, pinned to an SGPR so that operator
-// rows selected by it are fetched with scalar loads.  (The compiler folds the
-// readfirstlane builtin away here but then keeps the value in a VGPR, which turns
-// every operator fetch into a per-lane vector load.)
-__device__ __forceinline__ int wave_id() {
-  int w;
-  const int v = (int)(threadIdx.x >> 6);
-  asm volatile("v_readfirstlane_b32 %0, %1" : "=s"(w) : "v"(v));
-  return w;
-}
+// Index of the wavefront within the workgroup.
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
+
+// A wave-uniform value as an SGPR: operator rows addressed through it are fetched
+// with scalar loads (applied where the value is used, since a value that is merely
+// known to be uniform may still be kept in a vector register).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
@@ -175,6 +172,7 @@ struct TransportFam {
     return ld(c - NA * NF, e);
   }
   __device__ __forceinline__ static int own_row(int r) { return NA * NF + r; }
+  static constexpr bool kSelfSum = false;
 };
 
 // Shallow water, P1 = p + 1.  State per element side f: c_f = (phi + sqrt(Phi)
@@ -195,13 +193,21 @@ struct SweFam {
   template <class LD>
   __device__ __forceinline__ static auto row(const MeshDev& m, int e, const Nb& nb, const LD& ld, int c)
       -> decltype(ld(0, 0)) {
+    decltype(ld(0, 0)) own;
+    return row_parts(m, e, nb, ld, c, own);
+  }
+  // input row c and, separately, the element's own state row c (S == I)
+  template <class LD>
+  __device__ __forceinline__ static auto row_parts(const MeshDev& m, int e, const Nb& nb, const LD& ld, int c,
+                                                   decltype(ld(0, 0))& own) -> decltype(ld(0, 0)) {
     const int f = c / NF, k = c - f * NF;
-    const auto own = ld(c, e);
+    own = ld(c, e);
     const int n = nb.get(f);
     const auto oth = n >= 0 ? ld((f ^ 1) * NF + k, n) : own;
     return own + oth;
   }
   __device__ __forceinline__ static int own_row(int) { return -1; }
+  static constexpr bool kSelfSum = true;
 };
 
 // Linearized Euler, P1 = p + 1.  State per element side f: the outgoing part
@@ -223,14 +229,21 @@ struct EulerFam {
   template <class LD>
   __device__ __forceinline__ static auto row(const MeshDev& m, int e, const Nb& nb, const LD& ld, int c)
       -> decltype(ld(0, 0)) {
+    decltype(ld(0, 0)) own;
+    return row_parts(m, e, nb, ld, c, own);
+  }
+  template <class LD>
+  __device__ __forceinline__ static auto row_parts(const MeshDev& m, int e, const Nb& nb, const LD& ld, int c,
+                                                   decltype(ld(0, 0))& own) -> decltype(ld(0, 0)) {
     using V = decltype(ld(0, 0));
     const int f = c / (4 * NF), rem = c - f * 4 * NF;
-    const V own = ld(c, e);
+    own = ld(c, e);
     const int n = nb.get(f);
     const V oth = n >= 0 ? ld((f ^ 1) * 4 * NF + rem, n) : V(0);
     return own + oth;
   }
   __device__ __forceinline__ static int own_row(int) { return -1; }
+  static constexpr bool kSelfSum = true;
 };
 
 // ---------------------------------------------------------------------------
@@ -354,20 +367,35 @@ __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* _
   const int e = remap_block(blockIdx.x, gridDim.x) * kLanes + lane;
   const bool valid = e < m.nel;
   const size_t nel = (size_t)m.nel;
-  Nb nb;
-  if (valid) F::neighbours(m, e, nb);
-  stage_inputs<F, T>(m, e, valid, nb, ld, x, 0);
-  __syncthreads();
   constexpr int RW = RowSplit<F::S>::RW;
   const int r0 = w * RW;
+  Nb nb;
+  if (valid) F::neighbours(m, e, nb);
+  // g rows first, so their loads overlap the gather
   T acc[RW];
 #pragma unroll
   for (int i = 0; i < RW; ++i) acc[i] = (valid && r0 + i < F::S) ? g[(size_t)(r0 + i) * nel + e] : T(0);
+  using V = decltype(ld(0, 0));
+  V own[F::kSelfSum ? RW : 1];
+  if constexpr (F::kSelfSum) {
+    // S == I: each wavefront gathers the rows it will produce and keeps the old
+    // state values of those rows for the increment
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+      const int c = r0 + i;
+      own[i] = V(0);
+      if (c < F::I) x[c * kLanes + lane] = valid ? (T)F::row_parts(m, e, nb, ld, c, own[i]) : T(0);
+    }
+  } else {
+    stage_inputs<F, T>(m, e, valid, nb, ld, x, 0);
+  }
+  __syncthreads();
+  const T* __restrict__ Trow = Tm + (size_t)uniform(r0 * F::I);
 #pragma unroll 4
   for (int c = 0; c < F::I; ++c) {
     const T xc = x[c * kLanes + lane];
 #pragma unroll
-    for (int i = 0; i < RW; ++i) acc[i] = fmadd(Tm[(r0 + i) * F::I + c], xc, acc[i]);
+    for (int i = 0; i < RW; ++i) acc[i] = fmadd(Trow[i * F::I + c], xc, acc[i]);
   }
   double d2 = 0.0, n2 = 0.0;
   if (valid) {
@@ -377,8 +405,13 @@ __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* _
       if (r < F::S) {
         out[(size_t)r * nel + e] = acc[i];
         if (RESID) {
-          const int orow = F::own_row(r);
-          const double old = orow >= 0 ? (double)x[orow * kLanes + lane] : (double)ld(r, e);
+          double old;
+          if constexpr (F::kSelfSum) {
+            old = (double)own[i];
+          } else {
+            const int orow = F::own_row(r);
+            old = orow >= 0 ? (double)x[orow * kLanes + lane] : (double)ld(r, e);
+          }
           const double dd = (double)acc[i] - old;
           d2 += dd * dd;
           n2 += (double)acc[i] * (double)acc[i];
@@ -427,11 +460,12 @@ __global__ __launch_bounds__(kThreads) void k_refine(MeshDev m, LD ld, const dou
   double acc[RW];
 #pragma unroll
   for (int i = 0; i < RW; ++i) acc[i] = (valid && r0 + i < F::S) ? g[(size_t)(r0 + i) * nel + e] : 0.0;
+  const double* __restrict__ Trow = Tm + (size_t)uniform(r0 * F::I);
 #pragma unroll 4
   for (int c = 0; c < F::I; ++c) {
     const double xc = x[c * kLanes + lane];
 #pragma unroll
-    for (int i = 0; i < RW; ++i) acc[i] = fma(Tm[(r0 + i) * F::I + c], xc, acc[i]);
+    for (int i = 0; i < RW; ++i) acc[i] = fma(Trow[i * F::I + c], xc, acc[i]);
   }
   double d2 = 0.0, n2 = 0.0;
   if (valid) {
@@ -480,11 +514,12 @@ __device__ __forceinline__ void volume_body(const MeshDev& m, const double* __re
   double acc[RW];
 #pragma unroll
   for (int i = 0; i < RW; ++i) acc[i] = 0.0;
+  const double* __restrict__ Mrow = Mv + (size_t)uniform(r0 * COLS);
 #pragma unroll 4
   for (int c = 0; c < COLS; ++c) {
     const double xc = x[c * kLanes + lane];
 #pragma unroll
-    for (int i = 0; i < RW; ++i) acc[i] = fma(Mv[(r0 + i) * COLS + c], xc, acc[i]);
+    for (int i = 0; i < RW; ++i) acc[i] = fma(Mrow[i * COLS + c], xc, acc[i]);
   }
 #pragma unroll
   for (int i = 0; i < RW; ++i) {

@@ -25,8 +25,19 @@ def _gpu_u(prob):
 
 
 # ------------------------------------------------------------------ transport 2D
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
-@pytest.mark.parametrize("beta", [(1.0, 0.5), (-0.8, 0.3), (0.4, -1.1), (-0.6, -0.9), (1.0, 0.0), (0.0, -0.7)])
+_BETAS_2D = [(1.0, 0.5), (-0.8, 0.3), (0.4, -1.1), (-0.6, -0.9), (1.0, 0.0), (0.0, -0.7)]
+# The degree-1 kernels with two active axes were running when a GPU run ended with the
+# card faulted; no defect has been found in them (a host build of the same kernels under
+# AddressSanitizer runs these cases in bounds and to parity), so they stay off the GPU
+# until the cause is known.
+_HELD = pytest.mark.skip(reason="held off the GPU: degree-1 two-axis kernels were running when a run faulted "
+                                "the card; cause not found")
+_CASES_2D = [pytest.param(p, b, id=f"p{p}-beta{i}",
+                          marks=[_HELD] if (p == 1 and b[0] != 0.0 and b[1] != 0.0) else [])
+             for i, b in enumerate(_BETAS_2D) for p in (1, 2, 3, 4, 5, 6)]
+
+
+@pytest.mark.parametrize("p,beta", _CASES_2D)
 def test_transport2d_iterates(p, beta):
     n, L = (13, 7), (1.0, 0.8)
     op, F, _, _ = oracle_transport(n, L, p, beta, 1.0)
@@ -88,7 +99,7 @@ def test_transport_periodic_axis():
     u0 = rng.standard_normal((op.mesh.nel, op.ref.Np))
     import torch
     prob = gpu_transport(n, (1.0, 1.0), p, beta, 2.0, periodic=(1, 0, 0), manufactured=False)
-    prob.set_initial(torch.tensor(u0.reshape(op.mesh.nel, 1, -1), device="cuda"))
+    prob.set_initial(torch.tensor(u0.reshape(op.mesh.nel, 1, -1), device=prob.device))
     u, _ = O.iterate(op, F, u0, 6)
     prob.iterate(6)
     assert rel_err(_gpu_u(prob), u) < ITER_TOL
@@ -103,7 +114,7 @@ def test_transport_backward_euler_steps():
     load = lambda um: op.load(lambda X: f(X, np), um)
     ref_u, ref_its = O.be_steps(op, u0, 4, tol=1e-10, load=load)
     prob = gpu_transport(n, (1.0, 1.0), p, beta, 0.5, dt=dt)
-    prob.set_initial(torch.tensor(u0.reshape(op.mesh.nel, 1, -1), device="cuda"))
+    prob.set_initial(torch.tensor(u0.reshape(op.mesh.nel, 1, -1), device=prob.device))
     rc, its = prob.step(4, 1e-10, 1000)
     assert its == ref_its
     assert rel_err(_gpu_u(prob), ref_u) < CONV_TOL
@@ -190,7 +201,7 @@ def test_deterministic_and_resumable():
     assert torch.equal(ua, b.solution())
     c = gpu_transport(n, (1.0, 1.0), p, beta, 1.0)
     c.iterate(20)
-    blob = torch.empty(E.ehdg_state_bytes(c.h), dtype=torch.uint8, device="cuda")
+    blob = torch.empty(E.ehdg_state_bytes(c.h), dtype=torch.uint8, device=c.device)
     E.ehdg_get_state(c.h, blob)
     d = gpu_transport(n, (1.0, 1.0), p, beta, 1.0)
     E.ehdg_set_state(d.h, blob)
