@@ -161,15 +161,18 @@ struct TransportFam {
     if (NA > 1) nb.n1 = neighbour(m, e, c, m.ax[1], -m.dir[1]);
     if (NA > 2) nb.n2 = neighbour(m, e, c, m.ax[2], -m.dir[2]);
   }
+  // e must be a valid element index (callers pass a stand-in for idle lanes): the
+  // load is unconditional, so the loads of all rows of a wavefront can be in flight
+  // together, and only the value is selected
   template <class LD>
   __device__ __forceinline__ static auto row(const MeshDev& m, int e, const Nb& nb, const LD& ld, int c)
       -> decltype(ld(0, 0)) {
     using V = decltype(ld(0, 0));
-    if (c < NA * NF) {
-      const int n = nb.get(c / NF);
-      return n >= 0 ? ld(c, n) : V(0);
-    }
-    return ld(c - NA * NF, e);
+    const bool up = c < NA * NF;
+    const int n = nb.get(c / NF);
+    const bool inflow_bc = up && n < 0;
+    const V v = ld(up ? c : c - NA * NF, (up && n >= 0) ? n : e);
+    return inflow_bc ? V(0) : v;
   }
   __device__ __forceinline__ static int own_row(int r) { return NA * NF + r; }
   static constexpr bool kSelfSum = false;
@@ -201,10 +204,10 @@ struct SweFam {
   __device__ __forceinline__ static auto row_parts(const MeshDev& m, int e, const Nb& nb, const LD& ld, int c,
                                                    decltype(ld(0, 0))& own) -> decltype(ld(0, 0)) {
     const int f = c / NF, k = c - f * NF;
-    own = ld(c, e);
     const int n = nb.get(f);
-    const auto oth = n >= 0 ? ld((f ^ 1) * NF + k, n) : own;
-    return own + oth;
+    own = ld(c, e);
+    const auto other = ld((f ^ 1) * NF + k, n >= 0 ? n : e);  // unconditional, in bounds
+    return own + (n >= 0 ? other : own);
   }
   __device__ __forceinline__ static int own_row(int) { return -1; }
   static constexpr bool kSelfSum = true;
@@ -237,10 +240,10 @@ struct EulerFam {
                                                    decltype(ld(0, 0))& own) -> decltype(ld(0, 0)) {
     using V = decltype(ld(0, 0));
     const int f = c / (4 * NF), rem = c - f * 4 * NF;
-    own = ld(c, e);
     const int n = nb.get(f);
-    const V oth = n >= 0 ? ld((f ^ 1) * 4 * NF + rem, n) : V(0);
-    return own + oth;
+    own = ld(c, e);
+    const V other = ld((f ^ 1) * 4 * NF + rem, n >= 0 ? n : e);  // unconditional, in bounds
+    return own + (n >= 0 ? other : V(0));
   }
   __device__ __forceinline__ static int own_row(int) { return -1; }
   static constexpr bool kSelfSum = true;
@@ -281,15 +284,20 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
       a += sd[i][0];
       b += sd[i][1];
     }
+    // The partials are agent-scope atomic stores (written through to the level where
+    // all XCDs see them).  Waiting for their completion before the arrival is counted
+    // orders them before it, without a device-wide release fence: such a fence writes
+    // back this XCD's whole L2 and, once per workgroup, costs more than the sweep.
     __hip_atomic_store(&ra.partials[2 * blockIdx.x], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&ra.partials[2 * blockIdx.x + 1], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned prev = atomicAdd(&ra.ctrl->counter, 1u);
+    __builtin_amdgcn_s_waitcnt(0);
+    const unsigned prev = __hip_atomic_fetch_add(&ra.ctrl->counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     is_last = (prev == gridDim.x - 1) ? 1 : 0;
   }
   __syncthreads();
   if (!is_last) return;
-  __threadfence();
+  // every partial has arrived; the agent-scope atomic loads below read them where
+  // they were written
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads) {
     a += __hip_atomic_load(&ra.partials[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -323,7 +331,7 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
       c->status = 1;
       c->done = 1;
     }
-    c->counter = 0u;
+    __hip_atomic_store(&c->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -341,12 +349,26 @@ extern __shared__ __align__(16) unsigned char g_smem[];
 
 // Gathers input rows [c_begin, c_end) of the workgroup's elements into LDS rows
 // starting at lds_row (wavefront w takes rows w, w + kWaves, ...).
+// es is the lane's element, or element 0 for a lane past the end (valid = false).
 template <class F, typename T, class LD>
-__device__ __forceinline__ void stage_inputs(const MeshDev& m, int e, bool valid, const Nb& nb, const LD& ld,
+__device__ __forceinline__ void stage_inputs(const MeshDev& m, int es, bool valid, const Nb& nb, const LD& ld,
                                              T* x, int lds_row) {
   const int lane = threadIdx.x & 63, w = wave_id();
-  for (int c = w; c < F::I; c += kWaves)
-    x[(lds_row + c) * kLanes + lane] = valid ? (T)F::row(m, e, nb, ld, c) : T(0);
+  // unrolled with a compile-time trip count and unconditional loads, so every load
+  // is in flight before the first LDS write waits for one
+  constexpr int J = (F::I + kWaves - 1) / kWaves;
+  T v[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int c = w + j * kWaves;
+    const T r = (T)F::row(m, es, nb, ld, c < F::I ? c : F::I - 1);
+    v[j] = valid ? r : T(0);
+  }
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int c = w + j * kWaves;
+    if (c < F::I) x[(lds_row + c) * kLanes + lane] = v[j];
+  }
 }
 
 // out[r][e] = g[r][e] + sum_c T[r][c] in_e[c]   (r < S, c < I).  T has RowSplit<S>::PAD rows.
@@ -366,15 +388,20 @@ __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* _
   const int lane = threadIdx.x & 63, w = wave_id();
   const int e = remap_block(blockIdx.x, gridDim.x) * kLanes + lane;
   const bool valid = e < m.nel;
+  const int es = valid ? e : 0;  // stand-in element for lanes past the end: loads stay in bounds
   const size_t nel = (size_t)m.nel;
   constexpr int RW = RowSplit<F::S>::RW;
   const int r0 = w * RW;
   Nb nb;
-  if (valid) F::neighbours(m, e, nb);
+  F::neighbours(m, es, nb);
   // g rows first, so their loads overlap the gather
   T acc[RW];
 #pragma unroll
-  for (int i = 0; i < RW; ++i) acc[i] = (valid && r0 + i < F::S) ? g[(size_t)(r0 + i) * nel + e] : T(0);
+  for (int i = 0; i < RW; ++i) {
+    const int r = r0 + i;
+    const T gv = g[(size_t)(r < F::S ? r : F::S - 1) * nel + es];
+    acc[i] = (valid && r < F::S) ? gv : T(0);
+  }
   using V = decltype(ld(0, 0));
   V own[F::kSelfSum ? RW : 1];
   if constexpr (F::kSelfSum) {
@@ -383,11 +410,13 @@ __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* _
 #pragma unroll
     for (int i = 0; i < RW; ++i) {
       const int c = r0 + i;
-      own[i] = V(0);
-      if (c < F::I) x[c * kLanes + lane] = valid ? (T)F::row_parts(m, e, nb, ld, c, own[i]) : T(0);
+      V o;
+      const T v = (T)F::row_parts(m, es, nb, ld, c < F::I ? c : F::I - 1, o);
+      own[i] = o;
+      if (c < F::I) x[c * kLanes + lane] = valid ? v : T(0);
     }
   } else {
-    stage_inputs<F, T>(m, e, valid, nb, ld, x, 0);
+    stage_inputs<F, T>(m, es, valid, nb, ld, x, 0);
   }
   __syncthreads();
   const T* __restrict__ Trow = Tm + (size_t)uniform(r0 * F::I);
@@ -406,12 +435,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* _
         out[(size_t)r * nel + e] = acc[i];
         if (RESID) {
           double old;
-          if constexpr (F::kSelfSum) {
+          if constexpr (F::kSelfSum)
             old = (double)own[i];
-          } else {
-            const int orow = F::own_row(r);
-            old = orow >= 0 ? (double)x[orow * kLanes + lane] : (double)ld(r, e);
-          }
+          else
+            old = (double)x[F::own_row(r) * kLanes + lane];
           const double dd = (double)acc[i] - old;
           d2 += dd * dd;
           n2 += (double)acc[i] * (double)acc[i];
@@ -450,16 +477,37 @@ __global__ __launch_bounds__(kThreads) void k_refine(MeshDev m, LD ld, const dou
   const int lane = threadIdx.x & 63, w = wave_id();
   const int e = remap_block(blockIdx.x, gridDim.x) * kLanes + lane;
   const bool valid = e < m.nel;
+  const int es = valid ? e : 0;
   const size_t nel = (size_t)m.nel;
-  Nb nb;
-  if (valid) F::neighbours(m, e, nb);
-  stage_inputs<F, double>(m, e, valid, nb, ld, x, 0);
-  __syncthreads();
   constexpr int RW = RowSplit<F::S>::RW;
   const int r0 = w * RW;
+  Nb nb;
+  F::neighbours(m, es, nb);
   double acc[RW];
 #pragma unroll
-  for (int i = 0; i < RW; ++i) acc[i] = (valid && r0 + i < F::S) ? g[(size_t)(r0 + i) * nel + e] : 0.0;
+  for (int i = 0; i < RW; ++i) {
+    const int r = r0 + i;
+    const double gv = g[(size_t)(r < F::S ? r : F::S - 1) * nel + es];
+    acc[i] = (valid && r < F::S) ? gv : 0.0;
+  }
+  // s' (the refined iterate) of the rows this wavefront produces
+  double own[RW];
+  if constexpr (F::kSelfSum) {
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+      const int c = r0 + i;
+      double o;
+      const double v = F::row_parts(m, es, nb, ld, c < F::I ? c : F::I - 1, o);
+      own[i] = o;
+      if (c < F::I) x[c * kLanes + lane] = valid ? v : 0.0;
+    }
+    __syncthreads();
+  } else {
+    stage_inputs<F, double>(m, es, valid, nb, ld, x, 0);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RW; ++i) own[i] = r0 + i < F::S ? x[F::own_row(r0 + i) * kLanes + lane] : 0.0;
+  }
   const double* __restrict__ Trow = Tm + (size_t)uniform(r0 * F::I);
 #pragma unroll 4
   for (int c = 0; c < F::I; ++c) {
@@ -473,10 +521,8 @@ __global__ __launch_bounds__(kThreads) void k_refine(MeshDev m, LD ld, const dou
     for (int i = 0; i < RW; ++i) {
       const int r = r0 + i;
       if (r < F::S) {
-        const int orow = F::own_row(r);
-        const double s1 = orow >= 0 ? x[orow * kLanes + lane] : ld(r, e);
-        const double res = acc[i] - s1;
-        s_out[(size_t)r * nel + e] = s1;
+        const double res = acc[i] - own[i];
+        s_out[(size_t)r * nel + e] = own[i];
         r_lo(r, e, res);
         d2 += res * res;
         n2 += acc[i] * acc[i];
@@ -503,12 +549,25 @@ __device__ __forceinline__ void volume_body(const MeshDev& m, const double* __re
   const int e = remap_block(blockIdx.x, gridDim.x) * kLanes + lane;
   const bool valid = e < m.nel;
   const size_t nel = (size_t)m.nel;
+  const int es = valid ? e : 0;
   Nb nb;
-  if (valid) F::neighbours(m, e, nb);
+  F::neighbours(m, es, nb);
   if constexpr (BE) {
-    for (int c = w; c < F::N; c += kWaves) x[c * kLanes + lane] = valid ? u_old[(size_t)c * nel + e] : 0.0;
+    constexpr int J = (F::N + kWaves - 1) / kWaves;
+    double v[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int c = w + j * kWaves;
+      const double u = u_old[(size_t)(c < F::N ? c : F::N - 1) * nel + es];
+      v[j] = valid ? u : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int c = w + j * kWaves;
+      if (c < F::N) x[c * kLanes + lane] = v[j];
+    }
   }
-  stage_inputs<F, double>(m, e, valid, nb, Ld64{s_prev, nel}, x, BE ? F::N : 0);
+  stage_inputs<F, double>(m, es, valid, nb, Ld64{s_prev, nel}, x, BE ? F::N : 0);
   __syncthreads();
   const int r0 = w * RW;
   double acc[RW];
@@ -557,13 +616,13 @@ __global__ __launch_bounds__(kThreads) void k_step(MeshDev m, double* s0, double
   volume_body<F, true>(m, s_prev, Mv, uc ? u1 : u0, w_src, gbe, uc ? u0 : u1, g_out);
   __shared__ int is_last;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    is_last = (atomicAdd(&ctrl->vcounter, 1u) == gridDim.x - 1) ? 1 : 0;
-  }
+  // the control block was read by every workgroup before it arrives here, and nothing
+  // this kernel writes is read by the last workgroup: no fence is needed
+  if (threadIdx.x == 0)
+    is_last = (__hip_atomic_fetch_add(&ctrl->vcounter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+               gridDim.x - 1) ? 1 : 0;
   __syncthreads();
   if (is_last && threadIdx.x == 0) {
-    __threadfence();
     step_iters[ctrl->steps_done % step_cap] = iters;
     ctrl->steps_done += 1;
     ctrl->base = (base + iters) & 1;
@@ -571,8 +630,8 @@ __global__ __launch_bounds__(kThreads) void k_step(MeshDev m, double* s0, double
     ctrl->iters = 0;
     ctrl->done = 0;
     ctrl->status = 0;
-    ctrl->counter = 0u;
-    ctrl->vcounter = 0u;
+    __hip_atomic_store(&ctrl->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctrl->vcounter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -701,8 +760,9 @@ __global__ __launch_bounds__(kThreads) void k_inner_mfma(MeshDev m, const uint16
   for (int t = 0; t < kMfmaTilesPerWave; ++t) {
     const int e = (tile0 + t) * 16 + j;
     const bool valid = e < m.nel;
+    const int es = valid ? e : 0;
     Nb nb;
-    if (valid) F::neighbours(m, e, nb);
+    F::neighbours(m, es, nb);
     floatx4_t acc[3];
 #pragma unroll
     for (int mt = 0; mt < 3; ++mt) acc[mt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
@@ -711,13 +771,12 @@ __global__ __launch_bounds__(kThreads) void k_inner_mfma(MeshDev m, const uint16
       // inputs 8q .. 8q+7, q = 4 kt + kg: q < 6 -> upwind neighbour of face q/2, its
       // state rows 8q..; q >= 6 -> own state rows 8q - 48 ..
       const int q = 4 * kt + kg;
-      const int src = q < 6 ? nb.get(q >> 1) : e;
+      const int src = q < 6 ? nb.get(q >> 1) : es;
       const int row = q < 6 ? 8 * q : 8 * q - 48;
-      bf16x8_t b;
-      if (valid && src >= 0)
-        b = *reinterpret_cast<const bf16x8_t*>(lo_in + (size_t)src * 48 + row);
-      else
-        b = bf16x8_t{};
+      // unconditional load at an in-bounds element, then the zero for an inflow
+      // boundary or an idle lane is selected
+      const bf16x8_t ld = *reinterpret_cast<const bf16x8_t*>(lo_in + (size_t)(src >= 0 ? src : es) * 48 + row);
+      const bf16x8_t b = (valid && src >= 0) ? ld : bf16x8_t{};
 #pragma unroll
       for (int mt = 0; mt < 3; ++mt) acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][kt], b, acc[mt], 0, 0, 0);
     }
