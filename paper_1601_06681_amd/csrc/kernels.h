@@ -17,15 +17,16 @@ inline int padded_rows(int rows) { return (rows + kRowGroups - 1) / kRowGroups *
 // converges: the trace state after k sweeps (or refinements) of the current
 // segment is in s[(base + k) & 1]; the current time level's solution is u[ucur].
 struct Ctrl {
+  // the first four fields are read together by every sweep (one 16-byte load)
   int done;           // set once the stopping test holds (or the increment is non-finite)
   int iters;          // sweeps (or refinements) of the current segment
+  int base;           // state buffer holding s^0 of the current segment
   int status;         // 0 running, 1 converged, 2 non-finite increment
   unsigned counter;   // arrivals of the sweep reduction
-  double last_res;    // last relative increment
-  int base;           // state buffer holding s^0 of the current segment
   int ucur;           // solution buffer holding the current time level
   int steps_done;     // backward-Euler steps completed since the last initial state
   unsigned vcounter;  // arrivals of the step-recovery kernel
+  double last_res;    // last relative increment
   double pad[3];
 };
 static_assert(sizeof(Ctrl) == 64, "Ctrl is one 64-byte block");

@@ -61,12 +61,11 @@ __device__ __forceinline__ int neighbour(const MeshDev& m, int e, const Ijk& c, 
   const int ni = sel3(m.n[0], m.n[1], m.n[2], axis);
   const int per = sel3(m.periodic[0], m.periodic[1], m.periodic[2], axis);
   const int stride = sel3(1, m.n[0], m.n[0] * m.n[1], axis);
-  int v = ci + step;
-  if (v < 0 || v >= ni) {
-    if (!per) return -1;
-    v = v < 0 ? v + ni : v - ni;
-  }
-  return e + (v - ci) * stride;
+  const int v = ci + step;
+  const bool out = v < 0 || v >= ni;
+  const int vw = v < 0 ? v + ni : (v >= ni ? v - ni : v);  // wrapped on a periodic axis
+  const int n = e + (vw - ci) * stride;
+  return (out && !per) ? -1 : n;
 }
 
 // Index of the wavefront within the workgroup.
@@ -76,6 +75,15 @@ __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
 // with scalar loads (applied where the value is used, since a value that is merely
 // known to be uniform may still be kept in a vector register).
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// done, iters, base and status of the control block in one 16-byte load
+struct CtrlHead {
+  int done, iters, base, status;
+};
+__device__ __forceinline__ CtrlHead ctrl_head(const Ctrl* c) {
+  const int4 v = *reinterpret_cast<const int4*>(c);
+  return {v.x, v.y, v.z, v.w};
+}
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
@@ -298,10 +306,26 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
   if (!is_last) return;
   // every partial has arrived; the agent-scope atomic loads below read them where
   // they were written
+  // kU partials per thread are loaded together (unconditional loads at clamped
+  // indices, so all are in flight at once), then summed in a fixed order
+  constexpr int kU = 8;
+  const int nb = (int)gridDim.x;
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads) {
-    a += __hip_atomic_load(&ra.partials[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    b += __hip_atomic_load(&ra.partials[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int i0 = threadIdx.x; i0 < nb; i0 += kThreads * kU) {
+    double pa[kU], pb[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * kThreads;
+      const int ic = i < nb ? i : nb - 1;
+      pa[u] = __hip_atomic_load(&ra.partials[2 * ic], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      pb[u] = __hip_atomic_load(&ra.partials[2 * ic + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const bool in = i0 + u * kThreads < nb;
+      a += in ? pa[u] : 0.0;
+      b += in ? pb[u] : 0.0;
+    }
   }
   a = wave_sum(a);
   b = wave_sum(b);
@@ -378,12 +402,11 @@ template <class F, typename T, class LD, bool RESID, bool DEVPAR>
 __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* __restrict__ g,
                                                      const T* __restrict__ Tm, T* out, ResidArgs ra,
                                                      double* s0, double* s1) {
-  if (ra.ctrl->done) return;
-  if constexpr (DEVPAR) {
-    const int b = (ra.ctrl->base + ra.ctrl->iters) & 1;
-    set_state(ld, b ? s1 : s0, 0);
-    out = b ? s0 : s1;
-  }
+  // the control block is read first; the index arithmetic and the g loads, which do
+  // not depend on it, overlap its latency
+  const CtrlHead ch = ctrl_head(ra.ctrl);
+  const int done = ch.done;
+  const int parity = (ch.base + ch.iters) & 1;
   T* x = reinterpret_cast<T*>(g_smem);
   const int lane = threadIdx.x & 63, w = wave_id();
   const int e = remap_block(blockIdx.x, gridDim.x) * kLanes + lane;
@@ -394,13 +417,17 @@ __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* _
   const int r0 = w * RW;
   Nb nb;
   F::neighbours(m, es, nb);
-  // g rows first, so their loads overlap the gather
   T acc[RW];
 #pragma unroll
   for (int i = 0; i < RW; ++i) {
     const int r = r0 + i;
     const T gv = g[(size_t)(r < F::S ? r : F::S - 1) * nel + es];
     acc[i] = (valid && r < F::S) ? gv : T(0);
+  }
+  if (done) return;
+  if constexpr (DEVPAR) {
+    set_state(ld, parity ? s1 : s0, 0);
+    out = parity ? s0 : s1;
   }
   using V = decltype(ld(0, 0));
   V own[F::kSelfSum ? RW : 1];
@@ -468,10 +495,11 @@ template <class F, class LD, class ST>
 __global__ __launch_bounds__(kThreads) void k_refine(MeshDev m, LD ld, const double* __restrict__ g,
                                                       const double* __restrict__ Tm, double* s0, double* s1,
                                                       ST r_lo, ResidArgs ra) {
-  if (ra.ctrl->done) return;
+  const CtrlHead ch = ctrl_head(ra.ctrl);
+  if (ch.done) return;
   // s^k from the control block; the correction is applied from the segment's second refinement on
-  const int b = (ra.ctrl->base + ra.ctrl->iters) & 1;
-  set_state(ld, b ? s1 : s0, ra.ctrl->iters > 0 ? 1 : 0);
+  const int b = (ch.base + ch.iters) & 1;
+  set_state(ld, b ? s1 : s0, ch.iters > 0 ? 1 : 0);
   double* s_out = b ? s0 : s1;
   double* x = reinterpret_cast<double*>(g_smem);
   const int lane = threadIdx.x & 63, w = wave_id();
