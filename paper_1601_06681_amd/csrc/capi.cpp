@@ -75,7 +75,8 @@ Desc to_desc(const ehdg_desc* d) {
 }
 
 struct Layout {
-  size_t off_ctrl, off_partials, off_hist, off_steps, off_T64, off_T32, off_T16, off_R, off_Q, off_W, off_P, off_G,
+  size_t off_ctrl, off_partials, off_hist, off_steps, off_T64, off_Tf64, off_T32, off_T16, off_R, off_Q, off_W, off_P,
+      off_G,
       off_B, off_Mv, off_gbe;
   size_t off_s0, off_s1, off_g, off_gsrc, off_wsrc, off_u0, off_u1, off_lo0, off_lo1, off_rlo0, off_rlo1, off_scratch;
   size_t total;
@@ -89,7 +90,8 @@ Layout layout_for(const Operators& o, long long nel, bool lowp) {
     off += align256(bytes);
     return at;
   };
-  const size_t nb = (size_t)((nel + kElemsPerGroup - 1) / kElemsPerGroup);
+  // one partial pair per workgroup: at most one workgroup per 16-element tile
+  const size_t nb = (size_t)((nel + kMfmaTileElems - 1) / kMfmaTileElems);
   const size_t S = o.S, I = o.I, n = o.n, ne = (size_t)nel;
   const size_t Sp = (size_t)padded_rows(o.S);
   L.off_ctrl = take(sizeof(Ctrl));
@@ -97,6 +99,7 @@ Layout layout_for(const Operators& o, long long nel, bool lowp) {
   L.off_hist = take(kHistCap * sizeof(double));
   L.off_steps = take(kStepCap * sizeof(int));
   L.off_T64 = take(Sp * I * 8);
+  L.off_Tf64 = take((size_t)mfma_row_tiles(o.S) * mfma_k_tiles(o.I) * 64 * 8);
   L.off_T32 = take(Sp * I * 4);
   L.off_T16 = take(Sp * I * 2);
   L.off_Mv = take((size_t)padded_rows(o.Mvol.r) * o.Mvol.c * 8);
@@ -314,6 +317,7 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   dp.step_iters = (int*)(ws + L.off_steps);
   dp.step_cap = kStepCap;
   dp.T64 = (const double*)(ws + L.off_T64);
+  dp.Tf64 = (const double*)(ws + L.off_Tf64);
   dp.T32 = (const float*)(ws + L.off_T32);
   dp.T16 = (const uint16_t*)(ws + L.off_T16);
   dp.R = (const double*)(ws + L.off_R);
@@ -344,6 +348,15 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   std::vector<double> Tpad(SI, 0.0), Mvpad((size_t)padded_rows(o.Mvol.r) * o.Mvol.c, 0.0);
   std::copy(o.T.a.begin(), o.T.a.end(), Tpad.begin());
   std::copy(o.Mvol.a.begin(), o.Mvol.a.end(), Mvpad.begin());
+  // fragment-major copy of T for the matrix-core sweep
+  const int MT = mfma_row_tiles(o.S), KT = mfma_k_tiles(o.I);
+  std::vector<double> Tf((size_t)MT * KT * 64, 0.0);
+  for (int mt = 0; mt < MT; ++mt)
+    for (int kt = 0; kt < KT; ++kt)
+      for (int l = 0; l < 64; ++l) {
+        const int r = 16 * mt + l % 16, c = 4 * kt + l / 16;
+        if (r < o.S && c < o.I) Tf[((size_t)mt * KT + kt) * 64 + l] = o.T(r, c);
+      }
   std::vector<double> B;
   {
     const int cols = o.m * o.nq_el;
@@ -353,6 +366,7 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
         for (int q = 0; q < o.nq_el; ++q) B[(size_t)(f * o.Np + i) * cols + f * o.nq_el + q] = o.Bload(i, q);
   }
   if ((rc = upload(h, (void*)dp.T64, Tpad.data(), SI * 8)) ||
+      (rc = upload(h, (void*)dp.Tf64, Tf.data(), Tf.size() * 8)) ||
       (rc = upload(h, (void*)dp.Mvol, Mvpad.data(), Mvpad.size() * 8)) ||
       (rc = upload(h, (void*)dp.R, o.R.a.data(), (size_t)o.n * o.I * 8)) ||
       (rc = upload(h, h->Q, o.Q.a.data(), (size_t)o.S * o.n * 8)) ||

@@ -12,6 +12,15 @@ constexpr int kElemsPerGroup = 64;
 constexpr int kRowGroups = 4;
 inline int padded_rows(int rows) { return (rows + kRowGroups - 1) / kRowGroups * kRowGroups; }
 
+// FP64 sweeps run on the matrix cores (v_mfma_f64_16x16x4f64): the S x I operator is
+// cut into 16 x 4 fragments held in registers, stored fragment-major so that a
+// wavefront loads fragment (mt, kt) as one contiguous 512-byte run:
+//   Tf[(mt * KT + kt) * 64 + lane] = T[16 mt + lane % 16][4 kt + lane / 16]  (0 outside S x I).
+// Elements are processed in tiles of 16 (one per matrix column).
+constexpr int kMfmaTileElems = 16;
+inline int mfma_row_tiles(int rows) { return (rows + 15) / 16; }
+inline int mfma_k_tiles(int cols) { return (cols + 3) / 4; }
+
 // Device-resident iteration control, one per handle.  Kernels choose their
 // buffers from it, so work can be queued ahead of the host knowing when a solve
 // converges: the trace state after k sweeps (or refinements) of the current
@@ -46,6 +55,7 @@ struct DevProblem {
   int pde, dim, nf, S, I, n, m, Np, na;
   bool be;
   const double* T64;       // S x I
+  const double* Tf64;      // fragment-major T for the matrix-core sweep
   const float* T32;        // S x I
   const uint16_t* T16;     // S x I (bf16 bits)
   const double* R;         // n x I

@@ -19,6 +19,7 @@
 //     also raises a device-side "done" flag that makes later sweeps exit at once.
 #include "kernels.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace ehdg {
@@ -275,8 +276,11 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// NW: wavefronts per workgroup
+template <int NW = kWaves>
 __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
-  __shared__ double sd[kWaves][2];
+  constexpr int NT = 64 * NW;
+  __shared__ double sd[NW][2];
   __shared__ int is_last;
   const int lane = threadIdx.x & 63, w = wave_id();
   d2 = wave_sum(d2);
@@ -288,7 +292,7 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
   __syncthreads();
   if (threadIdx.x == 0) {
     double a = 0.0, b = 0.0;
-    for (int i = 0; i < kWaves; ++i) {
+    for (int i = 0; i < NW; ++i) {
       a += sd[i][0];
       b += sd[i][1];
     }
@@ -311,18 +315,18 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
   constexpr int kU = 8;
   const int nb = (int)gridDim.x;
   double a = 0.0, b = 0.0;
-  for (int i0 = threadIdx.x; i0 < nb; i0 += kThreads * kU) {
+  for (int i0 = threadIdx.x; i0 < nb; i0 += NT * kU) {
     double pa[kU], pb[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int i = i0 + u * kThreads;
+      const int i = i0 + u * NT;
       const int ic = i < nb ? i : nb - 1;
       pa[u] = __hip_atomic_load(&ra.partials[2 * ic], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       pb[u] = __hip_atomic_load(&ra.partials[2 * ic + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const bool in = i0 + u * kThreads < nb;
+      const bool in = i0 + u * NT < nb;
       a += in ? pa[u] : 0.0;
       b += in ? pb[u] : 0.0;
     }
@@ -338,7 +342,7 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
   if (threadIdx.x == 0) {
     a = 0.0;
     b = 0.0;
-    for (int i = 0; i < kWaves; ++i) {
+    for (int i = 0; i < NW; ++i) {
       a += sd[i][0];
       b += sd[i][1];
     }
@@ -474,6 +478,105 @@ __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* _
     }
   }
   if (RESID) finish_residual(d2, n2, ra);
+}
+
+// ---------------------------------------------------------------------------
+// the FP64 sweep on the matrix cores
+// ---------------------------------------------------------------------------
+// out = g + T in(s) for tiles of 16 elements as D(S x 16) = T(S x I) B(I x 16) + G with
+// v_mfma_f64_16x16x4f64.  Lane l of a wavefront holds A[l % 16][l / 16] of each 16 x 4
+// operator fragment (kept in registers for the whole launch), B[l / 16][l % 16] = input
+// row 4 kt + l / 16 of element 16 t + l % 16 (gathered straight from the component-
+// major state: 16 lanes read 128 contiguous bytes), and D[l / 16 + 4 r][l % 16] (rows
+// interleaved by 4 in the FP64 variant; checked on gfx950 with a one-wavefront probe).
+// A workgroup of WPG wavefronts shares each element tile, wavefront w applying row
+// tiles [w MTW, (w + 1) MTW); it sweeps a contiguous range of tiles.
+typedef double doublex4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaMaxA = 48;  // operator doubles per lane a wavefront keeps in registers
+
+template <int ROWS, int COLS>
+struct Tiling64 {
+  static constexpr int MT = (ROWS + 15) / 16, KT = (COLS + 3) / 4;
+  static constexpr int pick(int d) { return d <= 1 ? 1 : ((MT % d == 0 && d * KT <= kMfmaMaxA) ? d : pick(d - 1)); }
+  static constexpr int MTW = pick(MT);  // row tiles per wavefront
+  static constexpr int WPG = MT / MTW;  // wavefronts per element tile
+};
+
+template <class F>
+struct SweepWaves {  // wavefronts per workgroup of the matrix-core sweep
+  static constexpr int value = Tiling64<F::S, F::I>::WPG;
+};
+
+template <class F, bool DEVPAR>
+__global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma(
+    MeshDev m, Ld64 ld, const double* __restrict__ g, const double* __restrict__ Tf, double* out, ResidArgs ra,
+    double* s0, double* s1, int tiles_per_group) {
+  using TL = Tiling64<F::S, F::I>;
+  constexpr int MTW = TL::MTW, KT = TL::KT;
+  const CtrlHead ch = ctrl_head(ra.ctrl);
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int j = lane & 15, kq = lane >> 4;
+  // this wavefront's operator fragments (loaded while the control block read is in flight)
+  double a[MTW][KT];
+#pragma unroll
+  for (int u = 0; u < MTW; ++u)
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) a[u][kt] = Tf[((w * MTW + u) * KT + kt) * 64 + lane];
+  if (ch.done) return;
+  if constexpr (DEVPAR) {
+    const int parity = (ch.base + ch.iters) & 1;
+    ld.p = parity ? s1 : s0;
+    out = parity ? s0 : s1;
+  }
+  const size_t nel = (size_t)m.nel;
+  const int ntiles = (m.nel + 15) >> 4;
+  const int t0 = remap_block(blockIdx.x, gridDim.x) * tiles_per_group;
+  const int t1 = min(t0 + tiles_per_group, ntiles);
+  double d2 = 0.0, n2 = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int e = t * 16 + j;
+    const bool valid = e < m.nel;
+    const int es = valid ? e : 0;
+    Nb nb;
+    F::neighbours(m, es, nb);
+    double b[KT];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      const int c = 4 * kt + kq;
+      const double v = F::row(m, es, nb, ld, c < F::I ? c : F::I - 1);
+      b[kt] = (valid && c < F::I) ? v : 0.0;
+    }
+    doublex4_t acc[MTW];
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (w * MTW + u) + kq + 4 * r;
+        const double gv = g[(size_t)(row < F::S ? row : F::S - 1) * nel + es];
+        acc[u][r] = (valid && row < F::S) ? gv : 0.0;
+      }
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+      for (int u = 0; u < MTW; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][kt], b[kt], acc[u], 0, 0, 0);
+    // the previous value of each output row (the element's own state) for the increment
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (w * MTW + u) + kq + 4 * r;
+        const double old = ld(row < F::S ? row : F::S - 1, es);
+        if (valid && row < F::S) {
+          const double v = acc[u][r];
+          out[(size_t)row * nel + e] = v;
+          const double dd = v - old;
+          d2 += dd * dd;
+          n2 += v * v;
+        }
+      }
+  }
+  finish_residual<TL::WPG>(d2, n2, ra);
 }
 
 // mixed precision outer step: s_out = s_in (+ lo_in); r = g + T in(s_out) - s_out (FP64);
@@ -669,6 +772,15 @@ __global__ __launch_bounds__(kThreads) void k_step(MeshDev m, double* s0, double
 static inline int nblocks(int nel) { return (nel + kBlock - 1) / kBlock; }
 static inline int ngroups(int nel) { return (nel + kLanes - 1) / kLanes; }
 
+// Matrix-core launches: about 8192 wavefronts, each workgroup (wpg wavefronts) taking a
+// contiguous range of 16-element tiles.  groups <= number of tiles.
+static inline void mfma_groups(int nel, int wpg, int& tiles_per_group, int& groups) {
+  const int ntiles = (nel + kMfmaTileElems - 1) / kMfmaTileElems;
+  const int target = std::max(1, 8192 / wpg);
+  tiles_per_group = std::max(1, (ntiles + target - 1) / target);
+  groups = (ntiles + tiles_per_group - 1) / tiles_per_group;
+}
+
 static inline ResidArgs resid_args(const DevProblem& dp, double tol, int stop) {
   ResidArgs ra;
   ra.ctrl = dp.ctrl;
@@ -691,12 +803,13 @@ struct Family {
   static constexpr size_t lds_in64 = (size_t)F::I * kLanes * 8;
   static constexpr size_t lds_in32 = (size_t)F::I * kLanes * 4;
   static void sweep64(const DevProblem& dp, double tol, hipStream_t st) {
+    using TL = Tiling64<F::S, F::I>;
     const ResidArgs ra = resid_args(dp, tol, tol >= 0.0 ? 1 : 0);
-    const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
-    auto kern = k_sweep<F, double, Ld64, true, true>;
-    allow_lds(kern, lds_in64);
-    hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, Ld64{dp.s[0], (size_t)dp.mesh.nel},
-                       (const double*)dp.g, dp.T64, (double*)nullptr, ra, dp.s[0], dp.s[1]);
+    int tpg, groups;
+    mfma_groups(dp.mesh.nel, TL::WPG, tpg, groups);
+    hipLaunchKernelGGL((k_sweep_mfma<F, true>), dim3(groups), dim3(64 * TL::WPG), 0, st, dp.mesh,
+                       Ld64{dp.s[0], (size_t)dp.mesh.nel}, (const double*)dp.g, dp.Tf64, (double*)nullptr, ra,
+                       dp.s[0], dp.s[1], tpg);
   }
   static void volume(const DevProblem& dp, const double* s_prev, const double* u_old, double* u_out,
                      hipStream_t st) {
