@@ -21,6 +21,13 @@ constexpr int kMfmaTileElems = 16;
 inline int mfma_row_tiles(int rows) { return (rows + 15) / 16; }
 inline int mfma_k_tiles(int cols) { return (cols + 3) / 4; }
 
+// Arrival counters of the last-workgroup reductions: two sets (sweep reduction, step
+// completion) of 8 group counters plus one counter of finished groups, each on its
+// own 4 KB so that concurrent arrivals do not queue on one address.
+constexpr int kCounterStride = 1024;  // unsigned ints
+constexpr int kCounterSet = 9 * kCounterStride;
+constexpr size_t kCounterBytes = 2 * (size_t)kCounterSet * sizeof(unsigned);
+
 // Device-resident iteration control, one per handle.  Kernels choose their
 // buffers from it, so work can be queued ahead of the host knowing when a solve
 // converges: the trace state after k sweeps (or refinements) of the current
@@ -31,10 +38,10 @@ struct Ctrl {
   int iters;          // sweeps (or refinements) of the current segment
   int base;           // state buffer holding s^0 of the current segment
   int status;         // 0 running, 1 converged, 2 non-finite increment
-  unsigned counter;   // arrivals of the sweep reduction
+  unsigned unused0;
   int ucur;           // solution buffer holding the current time level
   int steps_done;     // backward-Euler steps completed since the last initial state
-  unsigned vcounter;  // arrivals of the step-recovery kernel
+  unsigned unused1;
   double last_res;    // last relative increment
   double pad[3];
 };
@@ -75,6 +82,7 @@ struct DevProblem {
   void* rlo[2];            // low-precision residual, double buffered (S)
   double* partials;        // 2 per block
   Ctrl* ctrl;
+  unsigned* counters;      // kCounterBytes: arrival counters (zero between launches)
   double* hist;            // residual ring
   int hist_cap;
 };
@@ -117,6 +125,7 @@ void launch_bc_inputs(const DevProblem& dp, const double* bc, double* in_bc, hip
 // full = 1: everything (new initial state); full = 0: start a new segment from the
 // latest state; full = 2: the same, but only if the current segment has finished
 void launch_ctrl_reset(Ctrl* c, int full, hipStream_t st);
+void launch_counters_reset(unsigned* counters, hipStream_t st);
 void launch_cast(const double* src, void* dst, size_t count, int to_bf16, hipStream_t st);
 
 }  // namespace ehdg

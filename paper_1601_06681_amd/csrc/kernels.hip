@@ -263,12 +263,32 @@ struct EulerFam {
 // ---------------------------------------------------------------------------
 struct ResidArgs {
   Ctrl* ctrl;
+  unsigned* cnt;  // arrival counter set
   double* partials;
   double* hist;
   int hist_cap;
   double tol;
   int stop;  // 1: set done on tol or non-finite; 0: record only
 };
+
+// Two-level arrival count of workgroup b of nb: the workgroups are split into 8
+// groups (b & 7) counting on their own counter; the last arrival of each group then
+// counts on the counter of finished groups.  Returns true for the last workgroup
+// overall, which resets the counters.  The caller completes (waits for) every store
+// the last workgroup must see before arriving.
+__device__ bool arrive_last(unsigned* cnt, int b, int nb) {
+  const int grp = b & 7;
+  const int size = (nb >> 3) + (grp < (nb & 7) ? 1 : 0);
+  const unsigned prev =
+      __hip_atomic_fetch_add(cnt + grp * kCounterStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (prev != (unsigned)(size - 1)) return false;
+  const unsigned groups = nb < 8 ? (unsigned)nb : 8u;
+  const unsigned done =
+      __hip_atomic_fetch_add(cnt + 8 * kCounterStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (done != groups - 1) return false;
+  for (int i = 0; i < 9; ++i) __hip_atomic_store(cnt + i * kCounterStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -303,8 +323,7 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
     __hip_atomic_store(&ra.partials[2 * blockIdx.x], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&ra.partials[2 * blockIdx.x + 1], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_s_waitcnt(0);
-    const unsigned prev = __hip_atomic_fetch_add(&ra.ctrl->counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == gridDim.x - 1) ? 1 : 0;
+    is_last = arrive_last(ra.cnt, blockIdx.x, gridDim.x) ? 1 : 0;
   }
   __syncthreads();
   if (!is_last) return;
@@ -359,7 +378,6 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
       c->status = 1;
       c->done = 1;
     }
-    __hip_atomic_store(&c->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -499,13 +517,15 @@ template <int ROWS, int COLS>
 struct Tiling64 {
   static constexpr int MT = (ROWS + 15) / 16, KT = (COLS + 3) / 4;
   static constexpr int pick(int d) { return d <= 1 ? 1 : ((MT % d == 0 && d * KT <= kMfmaMaxA) ? d : pick(d - 1)); }
-  static constexpr int MTW = pick(MT);  // row tiles per wavefront
-  static constexpr int WPG = MT / MTW;  // wavefronts per element tile
+  static constexpr int MTW = pick(MT);              // row tiles per wavefront
+  static constexpr int WPG = MT / MTW;              // wavefronts per element tile
+  static constexpr int TS = WPG >= 4 ? 1 : 4 / WPG;  // element tiles in flight per workgroup
+  static constexpr int NW = WPG * TS;               // wavefronts per workgroup
 };
 
 template <class F>
 struct SweepWaves {  // wavefronts per workgroup of the matrix-core sweep
-  static constexpr int value = Tiling64<F::S, F::I>::WPG;
+  static constexpr int value = Tiling64<F::S, F::I>::NW;
 };
 
 template <class F, bool DEVPAR>
@@ -515,7 +535,8 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma(
   using TL = Tiling64<F::S, F::I>;
   constexpr int MTW = TL::MTW, KT = TL::KT;
   const CtrlHead ch = ctrl_head(ra.ctrl);
-  const int lane = threadIdx.x & 63, w = wave_id();
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  const int w = wave % TL::WPG, slot = wave / TL::WPG;  // row-tile group, tile slot
   const int j = lane & 15, kq = lane >> 4;
   // this wavefront's operator fragments (loaded while the control block read is in flight)
   double a[MTW][KT];
@@ -534,7 +555,7 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma(
   const int t0 = remap_block(blockIdx.x, gridDim.x) * tiles_per_group;
   const int t1 = min(t0 + tiles_per_group, ntiles);
   double d2 = 0.0, n2 = 0.0;
-  for (int t = t0; t < t1; ++t) {
+  for (int t = t0 + slot; t < t1; t += TL::TS) {
     const int e = t * 16 + j;
     const bool valid = e < m.nel;
     const int es = valid ? e : 0;
@@ -576,7 +597,7 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma(
         }
       }
   }
-  finish_residual<TL::WPG>(d2, n2, ra);
+  finish_residual<TL::NW>(d2, n2, ra);
 }
 
 // mixed precision outer step: s_out = s_in (+ lo_in); r = g + T in(s_out) - s_out (FP64);
@@ -740,7 +761,8 @@ template <class F>
 __global__ __launch_bounds__(kThreads) void k_step(MeshDev m, double* s0, double* s1, const double* __restrict__ Mv,
                                                     double* u0, double* u1, const double* __restrict__ w_src,
                                                     const double* __restrict__ gbe, double* __restrict__ g_out,
-                                                    Ctrl* ctrl, int* step_iters, int step_cap, int lag) {
+                                                    Ctrl* ctrl, unsigned* cnt, int* step_iters, int step_cap,
+                                                    int lag) {
   if (ctrl->status != 1) return;
   const int iters = ctrl->iters, base = ctrl->base, uc = ctrl->ucur;
   const double* s_prev = ((base + iters - lag) & 1) ? s1 : s0;
@@ -749,9 +771,7 @@ __global__ __launch_bounds__(kThreads) void k_step(MeshDev m, double* s0, double
   __syncthreads();
   // the control block was read by every workgroup before it arrives here, and nothing
   // this kernel writes is read by the last workgroup: no fence is needed
-  if (threadIdx.x == 0)
-    is_last = (__hip_atomic_fetch_add(&ctrl->vcounter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-               gridDim.x - 1) ? 1 : 0;
+  if (threadIdx.x == 0) is_last = arrive_last(cnt, blockIdx.x, gridDim.x) ? 1 : 0;
   __syncthreads();
   if (is_last && threadIdx.x == 0) {
     step_iters[ctrl->steps_done % step_cap] = iters;
@@ -761,8 +781,6 @@ __global__ __launch_bounds__(kThreads) void k_step(MeshDev m, double* s0, double
     ctrl->iters = 0;
     ctrl->done = 0;
     ctrl->status = 0;
-    __hip_atomic_store(&ctrl->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&ctrl->vcounter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -772,18 +790,21 @@ __global__ __launch_bounds__(kThreads) void k_step(MeshDev m, double* s0, double
 static inline int nblocks(int nel) { return (nel + kBlock - 1) / kBlock; }
 static inline int ngroups(int nel) { return (nel + kLanes - 1) / kLanes; }
 
-// Matrix-core launches: about 8192 wavefronts, each workgroup (wpg wavefronts) taking a
-// contiguous range of 16-element tiles.  groups <= number of tiles.
-static inline void mfma_groups(int nel, int wpg, int& tiles_per_group, int& groups) {
+// Matrix-core launches: about 4096 wavefronts (4 per SIMD), each workgroup (nw
+// wavefronts, ts element tiles in flight) taking a contiguous range of 16-element
+// tiles.  groups <= number of tiles.
+static inline void mfma_groups(int nel, int nw, int ts, int& tiles_per_group, int& groups) {
   const int ntiles = (nel + kMfmaTileElems - 1) / kMfmaTileElems;
-  const int target = std::max(1, 8192 / wpg);
-  tiles_per_group = std::max(1, (ntiles + target - 1) / target);
+  const int target = std::max(1, 4096 / nw);
+  tiles_per_group = std::max(ts, (ntiles + target - 1) / target);
+  tiles_per_group = (tiles_per_group + ts - 1) / ts * ts;
   groups = (ntiles + tiles_per_group - 1) / tiles_per_group;
 }
 
 static inline ResidArgs resid_args(const DevProblem& dp, double tol, int stop) {
   ResidArgs ra;
   ra.ctrl = dp.ctrl;
+  ra.cnt = dp.counters;
   ra.partials = dp.partials;
   ra.hist = dp.hist;
   ra.hist_cap = dp.hist_cap;
@@ -806,8 +827,8 @@ struct Family {
     using TL = Tiling64<F::S, F::I>;
     const ResidArgs ra = resid_args(dp, tol, tol >= 0.0 ? 1 : 0);
     int tpg, groups;
-    mfma_groups(dp.mesh.nel, TL::WPG, tpg, groups);
-    hipLaunchKernelGGL((k_sweep_mfma<F, true>), dim3(groups), dim3(64 * TL::WPG), 0, st, dp.mesh,
+    mfma_groups(dp.mesh.nel, TL::NW, TL::TS, tpg, groups);
+    hipLaunchKernelGGL((k_sweep_mfma<F, true>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh,
                        Ld64{dp.s[0], (size_t)dp.mesh.nel}, (const double*)dp.g, dp.Tf64, (double*)nullptr, ra,
                        dp.s[0], dp.s[1], tpg);
   }
@@ -835,8 +856,8 @@ struct Family {
     allow_lds(kern, lds);
     hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, dp.s[0], dp.s[1], dp.Mvol, dp.u2[0], dp.u2[1],
                        (const double*)(dp.has_src ? dp.w_src : nullptr),
-                       (const double*)(dp.has_src ? dp.gbe : nullptr), dp.g, dp.ctrl, dp.step_iters, dp.step_cap,
-                       lag);
+                       (const double*)(dp.has_src ? dp.gbe : nullptr), dp.g, dp.ctrl, dp.counters + kCounterSet,
+                       dp.step_iters, dp.step_cap, lag);
   }
   static void refine32(const DevProblem& dp, const void* lo_in, void* r_out, double tol, hipStream_t st) {
     const ResidArgs ra = resid_args(dp, tol, 1);
@@ -1133,8 +1154,15 @@ __global__ void k_ctrl_reset(Ctrl* c, int full) {
   c->done = 0;
   c->iters = 0;
   c->status = 0;
-  c->counter = 0u;
-  c->vcounter = 0u;
+}
+
+__global__ void k_counters_reset(unsigned* cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 18) cnt[i * kCounterStride] = 0u;
+}
+
+void launch_counters_reset(unsigned* counters, hipStream_t st) {
+  hipLaunchKernelGGL(k_counters_reset, dim3(1), dim3(64), 0, st, counters);
 }
 
 void launch_ctrl_reset(Ctrl* c, int full, hipStream_t st) {
