@@ -75,7 +75,7 @@ Desc to_desc(const ehdg_desc* d) {
 }
 
 struct Layout {
-  size_t off_ctrl, off_counters, off_partials, off_hist, off_steps, off_T64, off_Tf64, off_T32, off_T16, off_R, off_Q, off_W, off_P,
+  size_t off_ctrl, off_counters, off_Mf64, off_Tf32, off_partials, off_hist, off_steps, off_T64, off_Tf64, off_T32, off_T16, off_R, off_Q, off_W, off_P,
       off_G,
       off_B, off_Mv, off_gbe;
   size_t off_s0, off_s1, off_g, off_gsrc, off_wsrc, off_u0, off_u1, off_lo0, off_lo1, off_rlo0, off_rlo1, off_scratch;
@@ -101,6 +101,8 @@ Layout layout_for(const Operators& o, long long nel, bool lowp) {
   L.off_steps = take(kStepCap * sizeof(int));
   L.off_T64 = take(Sp * I * 8);
   L.off_Tf64 = take((size_t)mfma_row_tiles(o.S) * mfma_k_tiles(o.I) * 64 * 8);
+  L.off_Mf64 = take((size_t)mfma_row_tiles(o.Mvol.r) * mfma_k_tiles(o.Mvol.c) * 64 * 8);
+  L.off_Tf32 = take((size_t)mfma_row_tiles(o.S) * mfma_k_tiles(o.I) * 64 * 4);
   L.off_T32 = take(Sp * I * 4);
   L.off_T16 = take(Sp * I * 2);
   L.off_Mv = take((size_t)padded_rows(o.Mvol.r) * o.Mvol.c * 8);
@@ -143,6 +145,20 @@ std::string validate(const ehdg_desc* d) {
   if (d->precision < EHDG_FP64 || d->precision > EHDG_BF16_REFINE) return "unknown precision";
   if (d->precision != EHDG_FP64 && d->inner_sweeps < 1) return "inner_sweeps must be >= 1";
   return "";
+}
+
+// Operator A (rows x cols) cut into the 16 x 4 fragments of the FP64 matrix-core
+// instruction: F[(mt * KT + kt) * 64 + l] = A[16 mt + l % 16][4 kt + l / 16], zero outside A.
+std::vector<double> fragments(const Mat& A) {
+  const int MT = mfma_row_tiles(A.r), KT = mfma_k_tiles(A.c);
+  std::vector<double> F((size_t)MT * KT * 64, 0.0);
+  for (int mt = 0; mt < MT; ++mt)
+    for (int kt = 0; kt < KT; ++kt)
+      for (int l = 0; l < 64; ++l) {
+        const int r = 16 * mt + l % 16, c = 4 * kt + l / 16;
+        if (r < A.r && c < A.c) F[((size_t)mt * KT + kt) * 64 + l] = A(r, c);
+      }
+  return F;
 }
 
 int upload(ehdg_problem* h, void* dst, const void* src, size_t bytes) {
@@ -320,6 +336,8 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   dp.step_cap = kStepCap;
   dp.T64 = (const double*)(ws + L.off_T64);
   dp.Tf64 = (const double*)(ws + L.off_Tf64);
+  dp.Mf64 = (const double*)(ws + L.off_Mf64);
+  dp.Tf32 = (const float*)(ws + L.off_Tf32);
   dp.T32 = (const float*)(ws + L.off_T32);
   dp.T16 = (const uint16_t*)(ws + L.off_T16);
   dp.R = (const double*)(ws + L.off_R);
@@ -350,15 +368,8 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   std::vector<double> Tpad(SI, 0.0), Mvpad((size_t)padded_rows(o.Mvol.r) * o.Mvol.c, 0.0);
   std::copy(o.T.a.begin(), o.T.a.end(), Tpad.begin());
   std::copy(o.Mvol.a.begin(), o.Mvol.a.end(), Mvpad.begin());
-  // fragment-major copy of T for the matrix-core sweep
-  const int MT = mfma_row_tiles(o.S), KT = mfma_k_tiles(o.I);
-  std::vector<double> Tf((size_t)MT * KT * 64, 0.0);
-  for (int mt = 0; mt < MT; ++mt)
-    for (int kt = 0; kt < KT; ++kt)
-      for (int l = 0; l < 64; ++l) {
-        const int r = 16 * mt + l % 16, c = 4 * kt + l / 16;
-        if (r < o.S && c < o.I) Tf[((size_t)mt * KT + kt) * 64 + l] = o.T(r, c);
-      }
+  // fragment-major copies of T and of the recovery operator for the matrix-core kernels
+  const std::vector<double> Tf = fragments(o.T), Mf = fragments(o.Mvol);
   std::vector<double> B;
   {
     const int cols = o.m * o.nq_el;
@@ -369,6 +380,7 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   }
   if ((rc = upload(h, (void*)dp.T64, Tpad.data(), SI * 8)) ||
       (rc = upload(h, (void*)dp.Tf64, Tf.data(), Tf.size() * 8)) ||
+      (rc = upload(h, (void*)dp.Mf64, Mf.data(), Mf.size() * 8)) ||
       (rc = upload(h, (void*)dp.Mvol, Mvpad.data(), Mvpad.size() * 8)) ||
       (rc = upload(h, (void*)dp.R, o.R.a.data(), (size_t)o.n * o.I * 8)) ||
       (rc = upload(h, h->Q, o.Q.a.data(), (size_t)o.S * o.n * 8)) ||
@@ -381,6 +393,7 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   }
   launch_cast(dp.T64, (void*)dp.T32, SI, 0, h->stream);
   launch_cast(dp.T64, (void*)dp.T16, SI, 1, h->stream);
+  launch_cast(dp.Tf64, (void*)dp.Tf32, Tf.size(), 0, h->stream);
   launch_fill_bytes(dp.counters, kCounterBytes, h->stream);
   launch_fill_bytes(dp.partials, L.off_hist - L.off_partials, h->stream);
   launch_fill(dp.hist, 0.0, kHistCap, h->stream);

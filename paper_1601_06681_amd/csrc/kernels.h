@@ -63,12 +63,14 @@ struct DevProblem {
   bool be;
   const double* T64;       // S x I
   const double* Tf64;      // fragment-major T for the matrix-core sweep
+  const float* Tf32;       // the same in FP32
   const float* T32;        // S x I
   const uint16_t* T16;     // S x I (bf16 bits)
   const double* R;         // n x I
   const double* P;         // n x n (BE)
   const double* G;         // S x n (BE)
   const double* Mvol;      // recovery: steady R (n x I); BE [[P, R], [G P, G R]]; rows padded
+  const double* Mf64;      // fragment-major Mvol for the matrix-core step completion
   double* gbe;             // BE source part of the next g: g_src + G w_src  (S)
   bool has_src;            // forcing or boundary data present (w_src, g_src nonzero)
   double* s[2];            // trace state, double buffered

@@ -510,6 +510,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* _
 // A workgroup of WPG wavefronts shares each element tile, wavefront w applying row
 // tiles [w MTW, (w + 1) MTW); it sweeps a contiguous range of tiles.
 typedef double doublex4_t __attribute__((ext_vector_type(4)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaMaxA = 48;  // operator doubles per lane a wavefront keeps in registers
 
@@ -784,6 +785,245 @@ __global__ __launch_bounds__(kThreads) void k_step(MeshDev m, double* s0, double
   }
 }
 
+// Mixed-precision refinement on the matrix cores (the k_refine contract): s' = s^k (+ the
+// low-precision correction from the segment's second refinement on); r = g + T in(s') - s'
+// in FP64, stored in the low precision; s' stored as s^{k+1}; reduction of ||r|| and
+// ||s' + r||.
+template <class F, class LD, class ST>
+__global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
+    MeshDev m, LD ld, const double* __restrict__ g, const double* __restrict__ Tf, double* s0, double* s1, ST r_lo,
+    ResidArgs ra, int tiles_per_group) {
+  using TL = Tiling64<F::S, F::I>;
+  constexpr int MTW = TL::MTW, KT = TL::KT;
+  const CtrlHead ch = ctrl_head(ra.ctrl);
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  const int w = wave % TL::WPG, slot = wave / TL::WPG;
+  const int j = lane & 15, kq = lane >> 4;
+  double a[MTW][KT];
+#pragma unroll
+  for (int u = 0; u < MTW; ++u)
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) a[u][kt] = Tf[((w * MTW + u) * KT + kt) * 64 + lane];
+  if (ch.done) return;
+  const int parity = (ch.base + ch.iters) & 1;
+  set_state(ld, parity ? s1 : s0, ch.iters > 0 ? 1 : 0);
+  double* s_out = parity ? s0 : s1;
+  const size_t nel = (size_t)m.nel;
+  const int ntiles = (m.nel + 15) >> 4;
+  const int t0 = remap_block(blockIdx.x, gridDim.x) * tiles_per_group;
+  const int t1 = min(t0 + tiles_per_group, ntiles);
+  double d2 = 0.0, n2 = 0.0;
+  for (int t = t0 + slot; t < t1; t += TL::TS) {
+    const int e = t * 16 + j;
+    const bool valid = e < m.nel;
+    const int es = valid ? e : 0;
+    Nb nb;
+    F::neighbours(m, es, nb);
+    double b[KT];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      const int c = 4 * kt + kq;
+      const double v = F::row(m, es, nb, ld, c < F::I ? c : F::I - 1);
+      b[kt] = (valid && c < F::I) ? v : 0.0;
+    }
+    doublex4_t acc[MTW];
+    double own[MTW][4];
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (w * MTW + u) + kq + 4 * r;
+        const int rc = row < F::S ? row : F::S - 1;
+        const double gv = g[(size_t)rc * nel + es];
+        own[u][r] = ld(rc, es);
+        acc[u][r] = (valid && row < F::S) ? gv : 0.0;
+      }
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+      for (int u = 0; u < MTW; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][kt], b[kt], acc[u], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (w * MTW + u) + kq + 4 * r;
+        if (valid && row < F::S) {
+          const double v = acc[u][r], res = v - own[u][r];
+          s_out[(size_t)row * nel + e] = own[u][r];
+          r_lo(row, e, res);
+          d2 += res * res;
+          n2 += v * v;
+        }
+      }
+  }
+  finish_residual<TL::NW>(d2, n2, ra);
+}
+
+// FP32 correction sweep on the matrix cores: lo_out = r_lo + T in(lo_in) with
+// v_mfma_f32_16x16x4f32 (same fragments as the FP64 sweep, in FP32; the FP32 result
+// fragment holds D[4 (l / 16) + r][l % 16]).
+template <class F>
+__global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_inner32_mfma(
+    MeshDev m, Ld32 ld, const float* __restrict__ r_lo, const float* __restrict__ Tf, float* __restrict__ out,
+    const Ctrl* ctrl, int tiles_per_group) {
+  using TL = Tiling64<F::S, F::I>;
+  constexpr int MTW = TL::MTW, KT = TL::KT;
+  const int done = ctrl->done;
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  const int w = wave % TL::WPG, slot = wave / TL::WPG;
+  const int j = lane & 15, kq = lane >> 4;
+  float a[MTW][KT];
+#pragma unroll
+  for (int u = 0; u < MTW; ++u)
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) a[u][kt] = Tf[((w * MTW + u) * KT + kt) * 64 + lane];
+  if (done) return;
+  const size_t nel = (size_t)m.nel;
+  const int ntiles = (m.nel + 15) >> 4;
+  const int t0 = remap_block(blockIdx.x, gridDim.x) * tiles_per_group;
+  const int t1 = min(t0 + tiles_per_group, ntiles);
+  for (int t = t0 + slot; t < t1; t += TL::TS) {
+    const int e = t * 16 + j;
+    const bool valid = e < m.nel;
+    const int es = valid ? e : 0;
+    Nb nb;
+    F::neighbours(m, es, nb);
+    float b[KT];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      const int c = 4 * kt + kq;
+      const float v = F::row(m, es, nb, ld, c < F::I ? c : F::I - 1);
+      b[kt] = (valid && c < F::I) ? v : 0.0f;
+    }
+    floatx4_t acc[MTW];
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (w * MTW + u) + 4 * kq + r;
+        const float rv = r_lo[(size_t)(row < F::S ? row : F::S - 1) * nel + es];
+        acc[u][r] = (valid && row < F::S) ? rv : 0.0f;
+      }
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+      for (int u = 0; u < MTW; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][kt], b[kt], acc[u], 0, 0, 0);
+    if (valid) {
+#pragma unroll
+      for (int u = 0; u < MTW; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (w * MTW + u) + 4 * kq + r;
+          if (row < F::S) out[(size_t)row * nel + e] = acc[u][r];
+        }
+    }
+  }
+}
+
+// The same step completion on the matrix cores: [u_new; g_next] = [w_src; gbe] + M
+// [u_old; in(s_prev)] with the stacked operator M of (N + S) x (N + I) held as
+// fragments (fragment-major copy Mf, laid out like the sweep operator's).
+template <class F>
+struct StepTiling {
+  using TL = Tiling64<F::N + F::S, F::N + F::I>;
+  static constexpr int value = TL::NW;
+};
+
+template <class F>
+__global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
+    MeshDev m, double* s0, double* s1, const double* __restrict__ Mf, double* u0, double* u1,
+    const double* __restrict__ w_src, const double* __restrict__ gbe, double* __restrict__ g_out, Ctrl* ctrl,
+    unsigned* cnt, int* step_iters, int step_cap, int lag, int tiles_per_group) {
+  using TL = typename StepTiling<F>::TL;
+  constexpr int MTW = TL::MTW, KT = TL::KT, N = F::N, ROWS = F::N + F::S, COLS = F::N + F::I;
+  const CtrlHead ch = ctrl_head(ctrl);
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  const int w = wave % TL::WPG, slot = wave / TL::WPG;
+  const int j = lane & 15, kq = lane >> 4;
+  double a[MTW][KT];
+#pragma unroll
+  for (int u = 0; u < MTW; ++u)
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) a[u][kt] = Mf[((w * MTW + u) * KT + kt) * 64 + lane];
+  if (ch.status != 1) return;
+  const int iters = ch.iters, base = ch.base, uc = ctrl->ucur;
+  const size_t nel = (size_t)m.nel;
+  const Ld64 ld{((base + iters - lag) & 1) ? s1 : s0, nel};
+  const double* __restrict__ u_old = uc ? u1 : u0;
+  double* __restrict__ u_new = uc ? u0 : u1;
+  const int ntiles = (m.nel + 15) >> 4;
+  const int t0 = remap_block(blockIdx.x, gridDim.x) * tiles_per_group;
+  const int t1 = min(t0 + tiles_per_group, ntiles);
+  for (int t = t0 + slot; t < t1; t += TL::TS) {
+    const int e = t * 16 + j;
+    const bool valid = e < m.nel;
+    const int es = valid ? e : 0;
+    Nb nb;
+    F::neighbours(m, es, nb);
+    double b[KT];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      const int c = 4 * kt + kq;
+      double v;
+      if (4 * kt + 3 < N) {
+        v = u_old[(size_t)c * nel + es];
+      } else if (4 * kt >= N) {
+        const int ci = c - N;
+        v = F::row(m, es, nb, ld, ci < F::I ? ci : F::I - 1);
+      } else {  // the k tile that straddles the two blocks of inputs
+        const double vu = u_old[(size_t)(c < N ? c : N - 1) * nel + es];
+        const double vs = F::row(m, es, nb, ld, c >= N ? c - N : 0);
+        v = c < N ? vu : vs;
+      }
+      b[kt] = (valid && c < COLS) ? v : 0.0;
+    }
+    doublex4_t acc[MTW];
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = 16 * (w * MTW + u) + kq + 4 * r;
+        double c0 = 0.0;
+        if (q < N) {
+          if (w_src) c0 = w_src[(size_t)q * nel + es];
+        } else if (q < ROWS) {
+          if (gbe) c0 = gbe[(size_t)(q - N) * nel + es];
+        }
+        acc[u][r] = valid ? c0 : 0.0;
+      }
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+      for (int u = 0; u < MTW; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][kt], b[kt], acc[u], 0, 0, 0);
+    if (valid) {
+#pragma unroll
+      for (int u = 0; u < MTW; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = 16 * (w * MTW + u) + kq + 4 * r;
+          if (q < N)
+            u_new[(size_t)q * nel + e] = acc[u][r];
+          else if (q < ROWS && g_out)
+            g_out[(size_t)(q - N) * nel + e] = acc[u][r];
+        }
+    }
+  }
+  __shared__ int is_last;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = arrive_last(cnt, blockIdx.x, gridDim.x) ? 1 : 0;
+  __syncthreads();
+  if (is_last && threadIdx.x == 0) {
+    step_iters[ctrl->steps_done % step_cap] = iters;
+    ctrl->steps_done += 1;
+    ctrl->base = (base + iters) & 1;
+    ctrl->ucur = uc ^ 1;
+    ctrl->iters = 0;
+    ctrl->done = 0;
+    ctrl->status = 0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host launchers of one family
 // ---------------------------------------------------------------------------
@@ -850,40 +1090,38 @@ struct Family {
     }
   }
   static void step(const DevProblem& dp, int lag, hipStream_t st) {
-    const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
-    const size_t lds = (size_t)(F::N + F::I) * kLanes * 8;
-    auto kern = k_step<F>;
-    allow_lds(kern, lds);
-    hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, dp.s[0], dp.s[1], dp.Mvol, dp.u2[0], dp.u2[1],
-                       (const double*)(dp.has_src ? dp.w_src : nullptr),
+    using TL = typename StepTiling<F>::TL;
+    int tpg, groups;
+    mfma_groups(dp.mesh.nel, TL::NW, TL::TS, tpg, groups);
+    hipLaunchKernelGGL((k_step_mfma<F>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, dp.s[0], dp.s[1],
+                       dp.Mf64, dp.u2[0], dp.u2[1], (const double*)(dp.has_src ? dp.w_src : nullptr),
                        (const double*)(dp.has_src ? dp.gbe : nullptr), dp.g, dp.ctrl, dp.counters + kCounterSet,
-                       dp.step_iters, dp.step_cap, lag);
+                       dp.step_iters, dp.step_cap, lag, tpg);
   }
   static void refine32(const DevProblem& dp, const void* lo_in, void* r_out, double tol, hipStream_t st) {
-    const ResidArgs ra = resid_args(dp, tol, 1);
-    const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
     const size_t ne = (size_t)dp.mesh.nel;
     const StSoa32 store{(float*)r_out, ne};
-    if (lo_in) {
-      const LdSum<Ld32> ld{Ld64{dp.s[0], ne}, Ld32{(const float*)lo_in, ne}, 1};
-      auto kern = k_refine<F, LdSum<Ld32>, StSoa32>;
-      allow_lds(kern, lds_in64);
-      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, ld, (const double*)dp.g, dp.T64, dp.s[0],
-                         dp.s[1], store, ra);
-    } else {
-      auto kern = k_refine<F, Ld64, StSoa32>;
-      allow_lds(kern, lds_in64);
-      hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, Ld64{dp.s[0], ne}, (const double*)dp.g, dp.T64,
-                         dp.s[0], dp.s[1], store, ra);
-    }
+    if (lo_in)
+      refine_mfma(dp, LdSum<Ld32>{Ld64{dp.s[0], ne}, Ld32{(const float*)lo_in, ne}, 1}, store, tol, st);
+    else
+      refine_mfma(dp, Ld64{dp.s[0], ne}, store, tol, st);
+  }
+  template <class LD, class ST>
+  static void refine_mfma(const DevProblem& dp, const LD& ld, const ST& store, double tol, hipStream_t st) {
+    using TL = Tiling64<F::S, F::I>;
+    const ResidArgs ra = resid_args(dp, tol, 1);
+    int tpg, groups;
+    mfma_groups(dp.mesh.nel, TL::NW, TL::TS, tpg, groups);
+    hipLaunchKernelGGL((k_refine_mfma<F, LD, ST>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, ld,
+                       (const double*)dp.g, dp.Tf64, dp.s[0], dp.s[1], store, ra, tpg);
   }
   static void inner32(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
-    const ResidArgs ra = resid_args(dp, -1.0, 0);
-    auto kern = k_sweep<F, float, Ld32, false, false>;
-    allow_lds(kern, lds_in32);
-    hipLaunchKernelGGL(kern, dim3(ngroups(dp.mesh.nel)), dim3(kThreads), lds_in32, st, dp.mesh,
-                       Ld32{(const float*)lo_in, (size_t)dp.mesh.nel}, (const float*)r_lo, dp.T32, (float*)lo_out, ra,
-                       (double*)nullptr, (double*)nullptr);
+    using TL = Tiling64<F::S, F::I>;
+    int tpg, groups;
+    mfma_groups(dp.mesh.nel, TL::NW, TL::TS, tpg, groups);
+    hipLaunchKernelGGL((k_inner32_mfma<F>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh,
+                       Ld32{(const float*)lo_in, (size_t)dp.mesh.nel}, (const float*)r_lo, dp.Tf32,
+                       (float*)lo_out, (const Ctrl*)dp.ctrl, tpg);
   }
 };
 
@@ -897,7 +1135,6 @@ struct Family {
 // (48 BF16 per element), so each B fragment is one 16-byte load: 8 consecutive
 // state rows of the lane's element or of its upwind neighbour.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef float floatx4_t __attribute__((ext_vector_type(4)));
 typedef unsigned short ushort4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaTilesPerWave = 8;
@@ -967,23 +1204,13 @@ struct Bf16Ops {
 template <class F>
 struct Bf16Ops<F, true> {
   static void refine(const DevProblem& dp, const void* lo_in, void* r_out, double tol, hipStream_t st) {
-    const ResidArgs ra = resid_args(dp, tol, 1);
     const size_t ne = (size_t)dp.mesh.nel;
-    const size_t lds = (size_t)F::I * kLanes * 8;
-    const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
     const StAos16<F::S> store{(uint16_t*)r_out};
-    if (lo_in) {
-      const LdSum<Ld16Aos<F::S>> ld{Ld64{dp.s[0], ne}, Ld16Aos<F::S>{(const uint16_t*)lo_in}, 1};
-      auto kern = k_refine<F, LdSum<Ld16Aos<F::S>>, StAos16<F::S>>;
-      allow_lds(kern, lds);
-      hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, ld, (const double*)dp.g, dp.T64, dp.s[0], dp.s[1],
-                         store, ra);
-    } else {
-      auto kern = k_refine<F, Ld64, StAos16<F::S>>;
-      allow_lds(kern, lds);
-      hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, Ld64{dp.s[0], ne}, (const double*)dp.g, dp.T64,
-                         dp.s[0], dp.s[1], store, ra);
-    }
+    if (lo_in)
+      Family<F>::refine_mfma(dp, LdSum<Ld16Aos<F::S>>{Ld64{dp.s[0], ne}, Ld16Aos<F::S>{(const uint16_t*)lo_in}, 1},
+                             store, tol, st);
+    else
+      Family<F>::refine_mfma(dp, Ld64{dp.s[0], ne}, store, tol, st);
   }
   static void inner(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
     const int tiles = (dp.mesh.nel + 15) / 16;
