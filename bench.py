@@ -226,8 +226,8 @@ def run_transport3d(torch, args):
 def run_counter_sample(torch, args):
     """For rocprofv3 --pmc runs: a plain device-to-device copy of 256 MiB (the
     calibration kernel: it must fetch and write exactly 256 MiB each), then 20 FP64
-    sweeps of the shallow-water workload and, unless --no-3d, 5 sweeps of the 64^3
-    transport workload.  Nothing else is launched."""
+    sweeps and 2 backward-Euler steps of the shallow-water workload and, unless --no-3d,
+    5 sweeps of the 64^3 transport workload."""
     from paper_1601_06681_amd import workloads as W
     n = 256 * 1024 * 1024 // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -241,6 +241,9 @@ def run_counter_sample(torch, args):
     prob.set_initial(W.gaussian_hump(W.hump_centre(cfg["seed"])))
     torch.cuda.synchronize()
     prob.iterate(20)
+    torch.cuda.synchronize()
+    prob.set_initial(W.gaussian_hump(W.hump_centre(cfg["seed"])))
+    prob.step(2, cfg["tol"], 1000)
     torch.cuda.synchronize()
     prob.close()
     if not args.no_3d:

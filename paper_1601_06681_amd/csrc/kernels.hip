@@ -520,9 +520,88 @@ struct Tiling64 {
   static constexpr int pick(int d) { return d <= 1 ? 1 : ((MT % d == 0 && d * KT <= kMfmaMaxA) ? d : pick(d - 1)); }
   static constexpr int MTW = pick(MT);              // row tiles per wavefront
   static constexpr int WPG = MT / MTW;              // wavefronts per element tile
-  static constexpr int TS = WPG >= 4 ? 1 : 4 / WPG;  // element tiles in flight per workgroup
+  static constexpr int TS = WPG > 1 ? 1 : 4;          // element tiles in flight per workgroup
   static constexpr int NW = WPG * TS;               // wavefronts per workgroup
 };
+
+// Matrix-core engine for a workgroup of WPG (> 1) wavefronts that share every element
+// tile: the B tile (COLS x 16 elements) is gathered once per workgroup into LDS (wave-
+// front w loads k tiles w, w + WPG, ...), double-buffered, with the next tile's loads
+// in flight while the current tile's MFMAs run; wavefront w then applies row tiles
+// [w MTW, (w + 1) MTW) with its register-resident operator fragments a.
+//   colval(c, es, nb): input column c (< COLS) of element es (a valid element index)
+//   init(row, es, aux): C entry of output row (< ROWS); may also set aux (a value the
+//                      epilogue needs, loaded together with the C entries)
+//   epi(row, e, v, aux): result of output row for element e (valid lanes only)
+template <class F, int ROWS, int COLS, int MTW, int WPG, class ColVal, class Init, class Epi>
+__device__ __forceinline__ void mfma64_shared_b(const MeshDev& m, const double (&a)[MTW][(COLS + 3) / 4], int t0,
+                                                int t1, double* lds, ColVal colval, Init init, Epi epi) {
+  constexpr int KT = (COLS + 3) / 4, KTW = (KT + WPG - 1) / WPG, BT = KT * 4 * 16;
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int j = lane & 15, kq = lane >> 4;
+  double v[KTW];
+  auto gather = [&](int t) {
+    const int e = t * 16 + j;
+    const bool valid = e < m.nel;
+    const int es = valid ? e : 0;
+    Nb nb;
+    F::neighbours(m, es, nb);
+#pragma unroll
+    for (int i = 0; i < KTW; ++i) {
+      const int kt = w + i * WPG, c = 4 * kt + kq;
+      const double x = colval(c < COLS ? c : COLS - 1, es, nb);
+      v[i] = (valid && c < COLS) ? x : 0.0;
+    }
+  };
+  auto stage = [&](double* buf) {
+#pragma unroll
+    for (int i = 0; i < KTW; ++i) {
+      const int kt = w + i * WPG;
+      if (kt < KT) buf[(4 * kt + kq) * 16 + j] = v[i];
+    }
+  };
+  if (t0 < t1) {
+    gather(t0);
+    stage(lds);
+  }
+  __syncthreads();
+  for (int t = t0; t < t1; ++t) {
+    const int cur = (t - t0) & 1;
+    const double* bcur = lds + cur * BT;
+    const int e = t * 16 + j;
+    const bool valid = e < m.nel;
+    const int es = valid ? e : 0;
+    // C entries of this tile first (their loads are waited for before the prefetch's)
+    doublex4_t acc[MTW];
+    double aux[MTW][4];
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (w * MTW + u) + kq + 4 * r;
+        const double c0 = init(row < ROWS ? row : ROWS - 1, es, aux[u][r]);
+        acc[u][r] = (valid && row < ROWS) ? c0 : 0.0;
+      }
+    if (t + 1 < t1) gather(t + 1);
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      const double b = bcur[(4 * kt + kq) * 16 + j];
+#pragma unroll
+      for (int u = 0; u < MTW; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][kt], b, acc[u], 0, 0, 0);
+    }
+    if (valid) {
+#pragma unroll
+      for (int u = 0; u < MTW; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (w * MTW + u) + kq + 4 * r;
+          if (row < ROWS) epi(row, e, (double)acc[u][r], aux[u][r]);
+        }
+    }
+    if (t + 1 < t1) stage(lds + (cur ^ 1) * BT);
+    __syncthreads();
+  }
+}
 
 template <class F>
 struct SweepWaves {  // wavefronts per workgroup of the matrix-core sweep
@@ -556,6 +635,23 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma(
   const int t0 = remap_block(blockIdx.x, gridDim.x) * tiles_per_group;
   const int t1 = min(t0 + tiles_per_group, ntiles);
   double d2 = 0.0, n2 = 0.0;
+  if constexpr (TL::WPG > 1) {
+    __shared__ double bt[2 * KT * 4 * 16];
+    mfma64_shared_b<F, F::S, F::I, MTW, TL::WPG>(
+        m, a, t0, t1, bt, [&](int c, int es, const Nb& nb) { return F::row(m, es, nb, ld, c); },
+        [&](int row, int es, double& old) {
+          old = ld(row, es);
+          return g[(size_t)row * nel + es];
+        },
+        [&](int row, int e, double v, double old) {
+          out[(size_t)row * nel + e] = v;
+          const double dd = v - old;
+          d2 += dd * dd;
+          n2 += v * v;
+        });
+    finish_residual<TL::NW>(d2, n2, ra);
+    return;
+  }
   for (int t = t0 + slot; t < t1; t += TL::TS) {
     const int e = t * 16 + j;
     const bool valid = e < m.nel;
@@ -813,6 +909,24 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
   const int t0 = remap_block(blockIdx.x, gridDim.x) * tiles_per_group;
   const int t1 = min(t0 + tiles_per_group, ntiles);
   double d2 = 0.0, n2 = 0.0;
+  if constexpr (TL::WPG > 1) {
+    __shared__ double bt[2 * KT * 4 * 16];
+    mfma64_shared_b<F, F::S, F::I, MTW, TL::WPG>(
+        m, a, t0, t1, bt, [&](int c, int es, const Nb& nb) { return (double)F::row(m, es, nb, ld, c); },
+        [&](int row, int es, double& own) {
+          own = ld(row, es);
+          return g[(size_t)row * nel + es];
+        },
+        [&](int row, int e, double v, double own) {
+          const double res = v - own;
+          s_out[(size_t)row * nel + e] = own;
+          r_lo(row, e, res);
+          d2 += res * res;
+          n2 += v * v;
+        });
+    finish_residual<TL::NW>(d2, n2, ra);
+    return;
+  }
   for (int t = t0 + slot; t < t1; t += TL::TS) {
     const int e = t * 16 + j;
     const bool valid = e < m.nel;
@@ -954,58 +1068,67 @@ __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
   const int ntiles = (m.nel + 15) >> 4;
   const int t0 = remap_block(blockIdx.x, gridDim.x) * tiles_per_group;
   const int t1 = min(t0 + tiles_per_group, ntiles);
-  for (int t = t0 + slot; t < t1; t += TL::TS) {
-    const int e = t * 16 + j;
-    const bool valid = e < m.nel;
-    const int es = valid ? e : 0;
-    Nb nb;
-    F::neighbours(m, es, nb);
-    double b[KT];
-#pragma unroll
-    for (int kt = 0; kt < KT; ++kt) {
-      const int c = 4 * kt + kq;
-      double v;
-      if (4 * kt + 3 < N) {
-        v = u_old[(size_t)c * nel + es];
-      } else if (4 * kt >= N) {
-        const int ci = c - N;
-        v = F::row(m, es, nb, ld, ci < F::I ? ci : F::I - 1);
-      } else {  // the k tile that straddles the two blocks of inputs
-        const double vu = u_old[(size_t)(c < N ? c : N - 1) * nel + es];
-        const double vs = F::row(m, es, nb, ld, c >= N ? c - N : 0);
-        v = c < N ? vu : vs;
-      }
-      b[kt] = (valid && c < COLS) ? v : 0.0;
+  auto colval = [&](int c, int es, const Nb& nb) {
+    // inputs: u_old rows, then the gathered trace rows (both loads in bounds; one is kept)
+    const double vu = u_old[(size_t)(c < N ? c : N - 1) * nel + es];
+    const double vs = F::row(m, es, nb, ld, c >= N ? c - N : 0);
+    return c < N ? vu : vs;
+  };
+  auto init = [&](int q, int es, double&) {
+    double c0 = 0.0;
+    if (q < N) {
+      if (w_src) c0 = w_src[(size_t)q * nel + es];
+    } else if (gbe) {
+      c0 = gbe[(size_t)(q - N) * nel + es];
     }
-    doublex4_t acc[MTW];
+    return c0;
+  };
+  auto epi = [&](int q, int e, double v, double) {
+    if (q < N)
+      u_new[(size_t)q * nel + e] = v;
+    else if (g_out)
+      g_out[(size_t)(q - N) * nel + e] = v;
+  };
+  if constexpr (TL::WPG > 1) {
+    __shared__ double bt[2 * KT * 4 * 16];
+    mfma64_shared_b<F, ROWS, COLS, MTW, TL::WPG>(m, a, t0, t1, bt, colval, init, epi);
+  } else {
+    for (int t = t0 + slot; t < t1; t += TL::TS) {
+      const int e = t * 16 + j;
+      const bool valid = e < m.nel;
+      const int es = valid ? e : 0;
+      Nb nb;
+      F::neighbours(m, es, nb);
+      double b[KT];
 #pragma unroll
-    for (int u = 0; u < MTW; ++u)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = 16 * (w * MTW + u) + kq + 4 * r;
-        double c0 = 0.0;
-        if (q < N) {
-          if (w_src) c0 = w_src[(size_t)q * nel + es];
-        } else if (q < ROWS) {
-          if (gbe) c0 = gbe[(size_t)(q - N) * nel + es];
-        }
-        acc[u][r] = valid ? c0 : 0.0;
+      for (int kt = 0; kt < KT; ++kt) {
+        const int c = 4 * kt + kq;
+        const double v = colval(c < COLS ? c : COLS - 1, es, nb);
+        b[kt] = (valid && c < COLS) ? v : 0.0;
       }
-#pragma unroll
-    for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-      for (int u = 0; u < MTW; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][kt], b[kt], acc[u], 0, 0, 0);
-    if (valid) {
+      doublex4_t acc[MTW];
+      double unused;
 #pragma unroll
       for (int u = 0; u < MTW; ++u)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int q = 16 * (w * MTW + u) + kq + 4 * r;
-          if (q < N)
-            u_new[(size_t)q * nel + e] = acc[u][r];
-          else if (q < ROWS && g_out)
-            g_out[(size_t)(q - N) * nel + e] = acc[u][r];
+          const double c0 = init(q < ROWS ? q : ROWS - 1, es, unused);
+          acc[u][r] = (valid && q < ROWS) ? c0 : 0.0;
         }
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int u = 0; u < MTW; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][kt], b[kt], acc[u], 0, 0, 0);
+      if (valid) {
+#pragma unroll
+        for (int u = 0; u < MTW; ++u)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int q = 16 * (w * MTW + u) + kq + 4 * r;
+            if (q < ROWS) epi(q, e, (double)acc[u][r], 0.0);
+          }
+      }
     }
   }
   __shared__ int is_last;
