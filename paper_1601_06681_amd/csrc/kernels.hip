@@ -1069,10 +1069,14 @@ __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
   const int t0 = remap_block(blockIdx.x, gridDim.x) * tiles_per_group;
   const int t1 = min(t0 + tiles_per_group, ntiles);
   auto colval = [&](int c, int es, const Nb& nb) {
-    // inputs: u_old rows, then the gathered trace rows (both loads in bounds; one is kept)
-    const double vu = u_old[(size_t)(c < N ? c : N - 1) * nel + es];
-    const double vs = F::row(m, es, nb, ld, c >= N ? c - N : 0);
-    return c < N ? vu : vs;
+    // inputs: u_old rows, then the gathered trace rows (the branch is uniform across a
+    // wavefront except in the one k tile that straddles the two blocks)
+    double v;
+    if (c < N)
+      v = u_old[(size_t)c * nel + es];
+    else
+      v = F::row(m, es, nb, ld, c - N);
+    return v;
   };
   auto init = [&](int q, int es, double&) {
     double c0 = 0.0;
