@@ -127,7 +127,7 @@ def run_swe(args, torch):
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK,
                 "traffic": traffic_from_profiles("swe_sweep_p4_256x256", alg_bytes),
-                "kernel": "k_sweep<SweFam<5>, double> (FP64 sweep, residual fused)",
+                "kernel": "k_sweep_mfma<SweFam<5>> (FP64 matrix-core sweep, residual fused)",
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_us": t_sweep * 1e6}
     log(f"[bench] sweep {t_sweep * 1e6:.2f} us/launch, {achieved / 1e9:.0f} GB/s algorithmic")
 
@@ -256,6 +256,56 @@ def run_counter_sample(torch, args):
     log("[bench] counter sample done")
 
 
+PMC_KERNELS = {  # summary tag -> kernel name prefix (as rocprofv3 prints it)
+    "swe_sweep_p4_256x256": "void ehdg::k_sweep_mfma<ehdg::SweFam<5>, true>",
+    "swe_step_p4_256x256": "void ehdg::k_step_mfma<ehdg::SweFam<5> >",
+    "transport3d_sweep_p3_64x64x64": "void ehdg::k_sweep_mfma<ehdg::TransportFam<3, 3, 4>, true>",
+}
+
+
+def summarize_pmc(fetch_dir, write_dir):
+    """Writes profiles/<tag>_pmc.json from two rocprofv3 --pmc runs of --counter-sample
+    (FETCH_SIZE, then WRITE_SIZE).  Each counter is scaled by what it reads for the
+    256 MiB device-to-device copy in the same run (which moves exactly 256 MiB each way)."""
+    import csv
+    import statistics
+
+    def load(d, counter):
+        rows = list(csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))))
+        out = {}
+        for r in rows:
+            if r["Counter_Name"] == counter:
+                out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy_kib = 256 * 1024.0
+    f_copy = max(v for k, vs in fetch.items() if k.startswith("__amd_rocclr_copyBuffer") for v in vs)
+    w_copy = max(v for k, vs in write.items() if k.startswith("__amd_rocclr_copyBuffer") for v in vs)
+    ff, fw = copy_kib / f_copy, copy_kib / w_copy
+    sha = kernel_src_sha()
+    for tag, prefix in PMC_KERNELS.items():
+        fk = [v for k, vs in fetch.items() if k.startswith(prefix) for v in vs]
+        wk = [v for k, vs in write.items() if k.startswith(prefix) for v in vs]
+        if not fk or not wk:
+            continue
+        fm, wm = statistics.median(fk), statistics.median(wk)
+        d = {"kernel": prefix, "kernel_src_sha": sha, "dispatches": [len(fk), len(wk)],
+             "fetch_kib_per_dispatch_raw": fm, "write_kib_per_dispatch_raw": wm,
+             "copy_calibration": {"copy_bytes": 256 * 1024 * 1024, "fetch_kib_raw": f_copy, "write_kib_raw": w_copy,
+                                  "fetch_factor": ff, "write_factor": fw},
+             "hbm_bytes_per_dispatch": (fm * ff + wm * fw) * 1024.0,
+             "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch_dir> -o run -- "
+                          "python3 bench.py --counter-sample",
+                          "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <write_dir> -o run -- "
+                          "python3 bench.py --counter-sample",
+                          "python bench.py --summarize-pmc <fetch_dir> <write_dir>"]}
+        path = os.path.join(ROOT, "profiles", f"{tag}_pmc.json")
+        with open(path, "w") as fh:
+            json.dump(d, fh, indent=1)
+        log(f"[pmc] {tag}: {d['hbm_bytes_per_dispatch'] / 1e6:.2f} MB per dispatch -> {path}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,7 +317,12 @@ def main():
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--counter-sample", action="store_true",
                     help="only the copy-calibration kernel and a few sweeps, for rocprofv3 --pmc")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/*_pmc.json from two --pmc runs of --counter-sample (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the eHDG sweep of one mesh is measured "
                                    "on a single MI355X (multi-GPU sharding is a design, not a measured path)"}))
