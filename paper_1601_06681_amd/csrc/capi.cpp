@@ -75,7 +75,7 @@ Desc to_desc(const ehdg_desc* d) {
 }
 
 struct Layout {
-  size_t off_ctrl, off_counters, off_zero, off_Mf64, off_Tf32, off_partials, off_hist, off_steps, off_T64, off_Tf64, off_T32, off_T16, off_R, off_Q, off_W, off_P,
+  size_t off_ctrl, off_counters, off_Mf64, off_Tf32, off_partials, off_hist, off_steps, off_T64, off_Tf64, off_T32, off_T16, off_R, off_Q, off_W, off_P,
       off_G,
       off_B, off_Mv, off_gbe;
   size_t off_s0, off_s1, off_g, off_gsrc, off_wsrc, off_u0, off_u1, off_lo0, off_lo1, off_rlo0, off_rlo1, off_scratch;
@@ -96,7 +96,6 @@ Layout layout_for(const Operators& o, long long nel, bool lowp) {
   const size_t Sp = (size_t)padded_rows(o.S);
   L.off_ctrl = take(sizeof(Ctrl));
   L.off_counters = take(kCounterBytes);
-  L.off_zero = take(256);
   L.off_partials = take(2 * nb * sizeof(double));
   L.off_hist = take(kHistCap * sizeof(double));
   L.off_steps = take(kStepCap * sizeof(int));
@@ -330,7 +329,6 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   dp.be = o.be;
   dp.ctrl = (Ctrl*)(ws + L.off_ctrl);
   dp.counters = (unsigned*)(ws + L.off_counters);
-  dp.zero = (const double*)(ws + L.off_zero);
   dp.partials = (double*)(ws + L.off_partials);
   dp.hist = (double*)(ws + L.off_hist);
   dp.hist_cap = kHistCap;
@@ -397,7 +395,6 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   launch_cast(dp.T64, (void*)dp.T16, SI, 1, h->stream);
   launch_cast(dp.Tf64, (void*)dp.Tf32, Tf.size(), 0, h->stream);
   launch_fill_bytes(dp.counters, kCounterBytes, h->stream);
-  launch_fill_bytes((void*)dp.zero, 256, h->stream);
   launch_fill_bytes(dp.partials, L.off_hist - L.off_partials, h->stream);
   launch_fill(dp.hist, 0.0, kHistCap, h->stream);
   launch_fill_bytes(dp.step_iters, kStepCap * sizeof(int), h->stream);

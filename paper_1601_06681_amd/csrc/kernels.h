@@ -85,7 +85,6 @@ struct DevProblem {
   double* partials;        // 2 per block
   Ctrl* ctrl;
   unsigned* counters;      // kCounterBytes: arrival counters (zero between launches)
-  const double* zero;      // a zero slot that masked gathers read
   double* hist;            // residual ring
   int hist_cap;
 };

@@ -184,16 +184,6 @@ struct TransportFam {
     return inflow_bc ? V(0) : v;
   }
   __device__ __forceinline__ static int own_row(int r) { return NA * NF + r; }
-  // the state values whose sum is input row c of element es (p2 = zero: a single value);
-  // masked values point at a zero, so a prefetch is nothing but loads
-  __device__ __forceinline__ static void row_ptrs(const Nb& nb, const double* st, size_t nel, int es, int c,
-                                                  const double* zero, const double*& p1, const double*& p2) {
-    const bool up = c < NA * NF;
-    const int n = nb.get(c / NF);
-    p1 = up ? (n >= 0 ? st + (size_t)c * nel + n : zero) : st + (size_t)(c - NA * NF) * nel + es;
-    p2 = zero;
-  }
-  static constexpr bool kPairs = false;  // an input is one state value
   static constexpr bool kSelfSum = false;
 };
 
@@ -229,14 +219,6 @@ struct SweFam {
     return own + (n >= 0 ? other : own);
   }
   __device__ __forceinline__ static int own_row(int) { return -1; }
-  __device__ __forceinline__ static void row_ptrs(const Nb& nb, const double* st, size_t nel, int es, int c,
-                                                  const double*, const double*& p1, const double*& p2) {
-    const int f = c / NF, k = c - f * NF;
-    const int n = nb.get(f);
-    p1 = st + (size_t)c * nel + es;
-    p2 = n >= 0 ? st + (size_t)((f ^ 1) * NF + k) * nel + n : p1;  // wall: 2 c_own
-  }
-  static constexpr bool kPairs = true;  // an input is the sum of two state values
   static constexpr bool kSelfSum = true;
 };
 
@@ -273,14 +255,6 @@ struct EulerFam {
     return own + (n >= 0 ? other : V(0));
   }
   __device__ __forceinline__ static int own_row(int) { return -1; }
-  __device__ __forceinline__ static void row_ptrs(const Nb& nb, const double* st, size_t nel, int es, int c,
-                                                  const double* zero, const double*& p1, const double*& p2) {
-    const int f = c / (4 * NF), rem = c - f * 4 * NF;
-    const int n = nb.get(f);
-    p1 = st + (size_t)c * nel + es;
-    p2 = n >= 0 ? st + (size_t)((f ^ 1) * 4 * NF + rem) * nel + n : zero;
-  }
-  static constexpr bool kPairs = true;
   static constexpr bool kSelfSum = true;
 };
 
@@ -538,7 +512,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* _
 typedef double doublex4_t __attribute__((ext_vector_type(4)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmaMaxA = 32;  // operator doubles per lane a wavefront keeps in registers
+constexpr int kMfmaMaxA = 48;  // operator doubles per lane a wavefront keeps in registers
 
 template <int ROWS, int COLS>
 struct Tiling64 {
@@ -629,88 +603,6 @@ __device__ __forceinline__ void mfma64_shared_b(const MeshDev& m, const double (
   }
 }
 
-// The same engine with the gather given as addresses: colptrs(c, es, nb, p1, p2) names the
-// (at most two) FP64 values whose sum is input column c of element es, a zero slot
-// standing for a masked one.  The prefetch of the next tile is then nothing but loads;
-// the sums and the LDS stores come after the current tile's MFMAs, so the loads stay in
-// flight across them (a select or an add on the loaded values next to the loads would
-// make the wavefront wait for them first).
-template <class F, int ROWS, int COLS, int MTW, int WPG, bool PAIRS, class ColPtrs, class Init, class Epi>
-__device__ __forceinline__ void mfma64_shared_b_ptr(const MeshDev& m, const double (&a)[MTW][(COLS + 3) / 4], int t0,
-                                                    int t1, double* lds, const double* zero, ColPtrs colptrs,
-                                                    Init init, Epi epi) {
-  constexpr int KT = (COLS + 3) / 4, KTW = (KT + WPG - 1) / WPG, BT = KT * 4 * 16;
-  const int lane = threadIdx.x & 63, w = wave_id();
-  const int j = lane & 15, kq = lane >> 4;
-  double va[KTW], vb[PAIRS ? KTW : 1];
-  auto gather = [&](int t) {
-    const int e = t * 16 + j;
-    const bool valid = e < m.nel;
-    const int es = valid ? e : 0;
-    Nb nb;
-    F::neighbours(m, es, nb);
-#pragma unroll
-    for (int i = 0; i < KTW; ++i) {
-      const int kt = w + i * WPG, c = 4 * kt + kq;
-      const double *p1, *p2;
-      colptrs(c < COLS ? c : COLS - 1, es, nb, p1, p2);
-      const bool ok = valid && c < COLS;
-      va[i] = *(ok ? p1 : zero);
-      if constexpr (PAIRS) vb[i] = *(ok ? p2 : zero);
-    }
-  };
-  auto stage = [&](double* buf) {
-#pragma unroll
-    for (int i = 0; i < KTW; ++i) {
-      const int kt = w + i * WPG;
-      double x = va[i];
-      if constexpr (PAIRS) x += vb[i];
-      if (kt < KT) buf[(4 * kt + kq) * 16 + j] = x;
-    }
-  };
-  if (t0 < t1) {
-    gather(t0);
-    stage(lds);
-  }
-  __syncthreads();
-  for (int t = t0; t < t1; ++t) {
-    const int cur = (t - t0) & 1;
-    const double* bcur = lds + cur * BT;
-    const int e = t * 16 + j;
-    const bool valid = e < m.nel;
-    const int es = valid ? e : 0;
-    doublex4_t acc[MTW];
-    double aux[MTW][4];
-#pragma unroll
-    for (int u = 0; u < MTW; ++u)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * (w * MTW + u) + kq + 4 * r;
-        const double c0 = init(row < ROWS ? row : ROWS - 1, es, aux[u][r]);
-        acc[u][r] = (valid && row < ROWS) ? c0 : 0.0;
-      }
-    // next tile (the last iteration reloads the current one into the idle buffer)
-    gather(t + 1 < t1 ? t + 1 : t);
-#pragma unroll
-    for (int kt = 0; kt < KT; ++kt) {
-      const double b = bcur[(4 * kt + kq) * 16 + j];
-#pragma unroll
-      for (int u = 0; u < MTW; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][kt], b, acc[u], 0, 0, 0);
-    }
-    if (valid) {
-#pragma unroll
-      for (int u = 0; u < MTW; ++u)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * (w * MTW + u) + kq + 4 * r;
-          if (row < ROWS) epi(row, e, (double)acc[u][r], aux[u][r]);
-        }
-    }
-    stage(lds + (cur ^ 1) * BT);
-    __syncthreads();
-  }
-}
-
 template <class F>
 struct SweepWaves {  // wavefronts per workgroup of the matrix-core sweep
   static constexpr int value = Tiling64<F::S, F::I>::NW;
@@ -719,7 +611,7 @@ struct SweepWaves {  // wavefronts per workgroup of the matrix-core sweep
 template <class F, bool DEVPAR>
 __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma(
     MeshDev m, Ld64 ld, const double* __restrict__ g, const double* __restrict__ Tf, double* out, ResidArgs ra,
-    double* s0, double* s1, int tiles_per_group, const double* __restrict__ zero) {
+    double* s0, double* s1, int tiles_per_group) {
   using TL = Tiling64<F::S, F::I>;
   constexpr int MTW = TL::MTW, KT = TL::KT;
   const CtrlHead ch = ctrl_head(ra.ctrl);
@@ -745,11 +637,8 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma(
   double d2 = 0.0, n2 = 0.0;
   if constexpr (TL::WPG > 1) {
     __shared__ double bt[2 * KT * 4 * 16];
-    mfma64_shared_b_ptr<F, F::S, F::I, MTW, TL::WPG, F::kPairs>(
-        m, a, t0, t1, bt, zero,
-        [&](int c, int es, const Nb& nb, const double*& p1, const double*& p2) {
-          F::row_ptrs(nb, ld.p, nel, es, c, zero, p1, p2);
-        },
+    mfma64_shared_b<F, F::S, F::I, MTW, TL::WPG>(
+        m, a, t0, t1, bt, [&](int c, int es, const Nb& nb) { return F::row(m, es, nb, ld, c); },
         [&](int row, int es, double& old) {
           old = ld(row, es);
           return g[(size_t)row * nel + es];
@@ -1158,7 +1047,7 @@ template <class F>
 __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
     MeshDev m, double* s0, double* s1, const double* __restrict__ Mf, double* u0, double* u1,
     const double* __restrict__ w_src, const double* __restrict__ gbe, double* __restrict__ g_out, Ctrl* ctrl,
-    unsigned* cnt, int* step_iters, int step_cap, int lag, int tiles_per_group, const double* __restrict__ zero) {
+    unsigned* cnt, int* step_iters, int step_cap, int lag, int tiles_per_group) {
   using TL = typename StepTiling<F>::TL;
   constexpr int MTW = TL::MTW, KT = TL::KT, N = F::N, ROWS = F::N + F::S, COLS = F::N + F::I;
   const CtrlHead ch = ctrl_head(ctrl);
@@ -1190,10 +1079,13 @@ __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
     return v;
   };
   auto init = [&](int q, int es, double&) {
-    // unconditional load; an absent source reads the zero slot
-    const double* pc = q < N ? (w_src ? w_src + (size_t)q * nel + es : zero)
-                             : (gbe ? gbe + (size_t)(q - N) * nel + es : zero);
-    return *pc;
+    double c0 = 0.0;
+    if (q < N) {
+      if (w_src) c0 = w_src[(size_t)q * nel + es];
+    } else if (gbe) {
+      c0 = gbe[(size_t)(q - N) * nel + es];
+    }
+    return c0;
   };
   auto epi = [&](int q, int e, double v, double) {
     if (q < N)
@@ -1203,13 +1095,7 @@ __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
   };
   if constexpr (TL::WPG > 1) {
     __shared__ double bt[2 * KT * 4 * 16];
-    auto colptrs = [&](int c, int es, const Nb& nb, const double*& p1, const double*& p2) {
-      const double *q1, *q2;
-      F::row_ptrs(nb, ld.p, nel, es, c >= N ? c - N : 0, zero, q1, q2);
-      p1 = c < N ? u_old + (size_t)c * nel + es : q1;
-      p2 = c < N ? zero : q2;
-    };
-    mfma64_shared_b_ptr<F, ROWS, COLS, MTW, TL::WPG, F::kPairs>(m, a, t0, t1, bt, zero, colptrs, init, epi);
+    mfma64_shared_b<F, ROWS, COLS, MTW, TL::WPG>(m, a, t0, t1, bt, colval, init, epi);
   } else {
     for (int t = t0 + slot; t < t1; t += TL::TS) {
       const int e = t * 16 + j;
@@ -1311,7 +1197,7 @@ struct Family {
     mfma_groups(dp.mesh.nel, TL::NW, TL::TS, tpg, groups);
     hipLaunchKernelGGL((k_sweep_mfma<F, true>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh,
                        Ld64{dp.s[0], (size_t)dp.mesh.nel}, (const double*)dp.g, dp.Tf64, (double*)nullptr, ra,
-                       dp.s[0], dp.s[1], tpg, (const double*)dp.zero);
+                       dp.s[0], dp.s[1], tpg);
   }
   static void volume(const DevProblem& dp, const double* s_prev, const double* u_old, double* u_out,
                      hipStream_t st) {
@@ -1337,7 +1223,7 @@ struct Family {
     hipLaunchKernelGGL((k_step_mfma<F>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, dp.s[0], dp.s[1],
                        dp.Mf64, dp.u2[0], dp.u2[1], (const double*)(dp.has_src ? dp.w_src : nullptr),
                        (const double*)(dp.has_src ? dp.gbe : nullptr), dp.g, dp.ctrl, dp.counters + kCounterSet,
-                       dp.step_iters, dp.step_cap, lag, tpg, (const double*)dp.zero);
+                       dp.step_iters, dp.step_cap, lag, tpg);
   }
   static void refine32(const DevProblem& dp, const void* lo_in, void* r_out, double tol, hipStream_t st) {
     const size_t ne = (size_t)dp.mesh.nel;
