@@ -169,6 +169,39 @@ int ehdg_set_state(ehdg_handle h, const void* d_src, size_t bytes);
 /* Releases the host-side handle (the workspace stays the caller's). */
 int ehdg_destroy(ehdg_handle h);
 
+/* ---- Batches of independent problems ------------------------------------------
+ * Algorithm 1 treats every element independently, so a set of unrelated problems is
+ * one bigger set of independent local solves.  A batch advances many problems (any
+ * PDE, degree, mesh and coefficients, FP64 precision) together: each sweep is one launch
+ * per operator family in the batch, whose workgroups look up their problem in a table,
+ * and each problem keeps its own control block, stopping test and residual history.  A
+ * problem's iterates, iteration counts and solution are bit for bit those of the same
+ * handle advanced alone.
+ *
+ * handles: host array of n handles (from ehdg_setup, FP64 precision), all distinct; the
+ * batch keeps pointers to them, so they must outlive it, and no call on a member
+ * handle may overlap a batch call.  The workspace (device memory, 256-byte aligned,
+ * at least ehdg_batch_workspace_bytes) holds the problem table; it stays the caller's.
+ * Work is queued on `stream` (NULL = default).  Returns UNSUPPORTED for a handle in a
+ * refinement precision, INVALID_ARG for a repeated or null handle. */
+typedef struct ehdg_batch_s* ehdg_batch;
+int ehdg_batch_workspace_bytes(const ehdg_handle* handles, int32_t n, size_t* bytes);
+int ehdg_batch_create(const ehdg_handle* handles, int32_t n, void* d_workspace, size_t workspace_bytes,
+                      void* stream, ehdg_batch* out);
+
+/* Synchronous: ehdg_solve for every member (each to rel_tol, at most max_iters sweeps,
+ * then its recovery).  iters, rel_res: host arrays of n, or NULL.  Returns the first
+ * non-OK member status in handle order (NOT_CONVERGED / DIVERGED), else OK. */
+int ehdg_batch_solve(ehdg_batch b, double rel_tol, int32_t max_iters, int32_t* iters, double* rel_res);
+
+/* Synchronous: ehdg_step(n_steps) for every member (all must be backward-Euler).
+ * iters_per_step: host array [n][n_steps] (member-major), or NULL. */
+int ehdg_batch_step(ehdg_batch b, int32_t n_steps, double rel_tol, int32_t max_iters_per_step,
+                    int32_t* iters_per_step);
+
+int ehdg_batch_destroy(ehdg_batch b);
+const char* ehdg_batch_last_error(ehdg_batch b);
+
 const char* ehdg_error_string(int code);
 const char* ehdg_last_error(ehdg_handle h);
 

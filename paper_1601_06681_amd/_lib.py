@@ -28,7 +28,8 @@ EXPORTED = [
     "ehdg_reference_points", "ehdg_workspace_bytes", "ehdg_setup", "ehdg_set_forcing", "ehdg_set_initial",
     "ehdg_iterate", "ehdg_solve", "ehdg_step", "ehdg_get_solution", "ehdg_get_residuals", "ehdg_sizes",
     "ehdg_state_bytes", "ehdg_get_state", "ehdg_set_state", "ehdg_destroy", "ehdg_error_string",
-    "ehdg_last_error",
+    "ehdg_last_error", "ehdg_batch_workspace_bytes", "ehdg_batch_create", "ehdg_batch_solve", "ehdg_batch_step",
+    "ehdg_batch_destroy", "ehdg_batch_last_error",
 ]
 
 
@@ -83,6 +84,12 @@ def load():
         "ehdg_destroy": (ctypes.c_int, [P]),
         "ehdg_error_string": (ctypes.c_char_p, [ctypes.c_int]),
         "ehdg_last_error": (ctypes.c_char_p, [P]),
+        "ehdg_batch_workspace_bytes": (ctypes.c_int, [P, I32, ctypes.POINTER(SZ)]),
+        "ehdg_batch_create": (ctypes.c_int, [P, I32, P, SZ, P, ctypes.POINTER(P)]),
+        "ehdg_batch_solve": (ctypes.c_int, [P, D, I32, P, P]),
+        "ehdg_batch_step": (ctypes.c_int, [P, I32, D, I32, P]),
+        "ehdg_batch_destroy": (ctypes.c_int, [P]),
+        "ehdg_batch_last_error": (ctypes.c_char_p, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

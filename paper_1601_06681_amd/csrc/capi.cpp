@@ -1,6 +1,8 @@
 // C ABI of the eHDG library: handles, workspace layout and the iteration drivers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -649,6 +651,318 @@ int ehdg_destroy(ehdg_handle h) {
   delete h;
   return EHDG_OK;
 }
+
+// ---------------------------------------------------------------------------- batches
+}  // extern "C"
+
+struct ehdg_batch_s {
+  struct Group {
+    const KernelSet* ks;
+    int sweep_first, sweep_n, step_first, step_n;
+  };
+  std::vector<ehdg_problem*> h;
+  hipStream_t stream = nullptr;
+  std::vector<Group> groups;
+  BatchProblem* d_probs = nullptr;
+  BatchEntry* d_table = nullptr;
+  Ctrl* d_ctrl = nullptr;
+  std::vector<BatchProblem> probs;
+  std::vector<Ctrl> ctrl;
+  std::string err;
+};
+
+namespace {
+
+int bfail(ehdg_batch_s* b, int code, const std::string& msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+#define HIP_TRY_B(b, call)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) return bfail((b), EHDG_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// Groups by kernel family (in order of first appearance) and the workgroup table: for
+// each family, the sweep entries of its problems, then their step entries.
+void batch_plan(const std::vector<ehdg_problem*>& hs, std::vector<ehdg_batch_s::Group>& groups,
+                std::vector<BatchEntry>& table) {
+  std::vector<const KernelSet*> fams;
+  for (auto* h : hs)
+    if (std::find(fams.begin(), fams.end(), h->ks) == fams.end()) fams.push_back(h->ks);
+  for (const KernelSet* ks : fams) {
+    ehdg_batch_s::Group g{ks, (int)table.size(), 0, 0, 0};
+    for (size_t i = 0; i < hs.size(); ++i) {
+      if (hs[i]->ks != ks) continue;
+      int tpg = 0, ng = 0;
+      ks->sweep_groups(hs[i]->dp.mesh.nel, &tpg, &ng);
+      for (int b = 0; b < ng; ++b) table.push_back({(int)i, b, ng, tpg});
+    }
+    g.sweep_n = (int)table.size() - g.sweep_first;
+    g.step_first = (int)table.size();
+    for (size_t i = 0; i < hs.size(); ++i) {
+      if (hs[i]->ks != ks || !hs[i]->dp.be) continue;
+      int tpg = 0, ng = 0;
+      ks->step_groups(hs[i]->dp.mesh.nel, &tpg, &ng);
+      for (int b = 0; b < ng; ++b) table.push_back({(int)i, b, ng, tpg});
+    }
+    g.step_n = (int)table.size() - g.step_first;
+    groups.push_back(g);
+  }
+}
+
+struct BatchLayout {
+  size_t off_probs, off_table, off_ctrl, total;
+};
+
+BatchLayout batch_layout(size_t n, size_t entries) {
+  BatchLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += align256(bytes);
+    return at;
+  };
+  L.off_probs = take(n * sizeof(BatchProblem));
+  L.off_table = take(entries * sizeof(BatchEntry));
+  L.off_ctrl = take(n * sizeof(Ctrl));
+  L.total = off;
+  return L;
+}
+
+int batch_check(const ehdg_handle* handles, int32_t n, std::vector<ehdg_problem*>& hs) {
+  if (!handles || n < 1) return EHDG_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!handles[i]) return EHDG_ERR_INVALID_ARG;
+    if (std::find(hs.begin(), hs.end(), handles[i]) != hs.end()) return EHDG_ERR_INVALID_ARG;
+    if (mixed(handles[i])) return EHDG_ERR_UNSUPPORTED;
+    hs.push_back(handles[i]);
+  }
+  return EHDG_OK;
+}
+
+// Device copies of the members' current state pointers (forcing may have changed since
+// the batch was made) with each member's step limit, and uploads them.
+int batch_upload(ehdg_batch_s* b, const std::vector<int>& steps_target) {
+  for (size_t i = 0; i < b->h.size(); ++i) {
+    const DevProblem& dp = b->h[i]->dp;
+    BatchProblem& P = b->probs[i];
+    P.mesh = dp.mesh;
+    P.steps_target = steps_target[i];
+    P.hist_cap = dp.hist_cap;
+    P.step_cap = dp.step_cap;
+    P.Tf64 = dp.Tf64;
+    P.Mf64 = dp.Mf64;
+    P.g = dp.g;
+    P.s0 = dp.s[0];
+    P.s1 = dp.s[1];
+    P.u0 = dp.u2[0];
+    P.u1 = dp.u2[1];
+    P.w_src = dp.has_src ? dp.w_src : nullptr;
+    P.gbe = dp.has_src ? dp.gbe : nullptr;
+    P.ctrl = dp.ctrl;
+    P.counters = dp.counters;
+    P.partials = dp.partials;
+    P.hist = dp.hist;
+    P.step_iters = dp.step_iters;
+  }
+  HIP_TRY_B(b, hipMemcpyAsync(b->d_probs, b->probs.data(), b->probs.size() * sizeof(BatchProblem),
+                              hipMemcpyHostToDevice, b->stream));
+  return EHDG_OK;
+}
+
+// waits for the members' own streams, so no earlier work on a member is still queued
+int batch_quiesce(ehdg_batch_s* b) {
+  for (auto* h : b->h) HIP_TRY_B(b, hipStreamSynchronize(h->stream));
+  return EHDG_OK;
+}
+
+int batch_sync_ctrl(ehdg_batch_s* b) {
+  launch_ctrl_gather(b->d_probs, (int)b->h.size(), b->d_ctrl, b->stream);
+  HIP_TRY_B(b, hipMemcpyAsync(b->ctrl.data(), b->d_ctrl, b->ctrl.size() * sizeof(Ctrl), hipMemcpyDeviceToHost,
+                              b->stream));
+  HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+  return EHDG_OK;
+}
+
+int batch_check_launch(ehdg_batch_s* b) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return bfail(b, EHDG_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return EHDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ehdg_batch_workspace_bytes(const ehdg_handle* handles, int32_t n, size_t* bytes) {
+  if (!bytes) return EHDG_ERR_INVALID_ARG;
+  std::vector<ehdg_problem*> hs;
+  int rc = batch_check(handles, n, hs);
+  if (rc) return rc;
+  std::vector<ehdg_batch_s::Group> groups;
+  std::vector<BatchEntry> table;
+  batch_plan(hs, groups, table);
+  *bytes = batch_layout(hs.size(), table.size()).total;
+  return EHDG_OK;
+}
+
+int ehdg_batch_create(const ehdg_handle* handles, int32_t n, void* d_workspace, size_t workspace_bytes, void* stream,
+                      ehdg_batch* out) {
+  if (!out) return EHDG_ERR_INVALID_ARG;
+  *out = nullptr;
+  std::vector<ehdg_problem*> hs;
+  int rc = batch_check(handles, n, hs);
+  if (rc) return rc;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255)) return EHDG_ERR_INVALID_ARG;
+  ehdg_batch_s* b = new (std::nothrow) ehdg_batch_s();
+  if (!b) return EHDG_ERR_INVALID_ARG;
+  b->h = hs;
+  b->stream = (hipStream_t)stream;
+  std::vector<BatchEntry> table;
+  batch_plan(hs, b->groups, table);
+  const BatchLayout L = batch_layout(hs.size(), table.size());
+  if (workspace_bytes < L.total) {
+    delete b;
+    return EHDG_ERR_WORKSPACE_TOO_SMALL;
+  }
+  char* ws = (char*)d_workspace;
+  b->d_probs = (BatchProblem*)(ws + L.off_probs);
+  b->d_table = (BatchEntry*)(ws + L.off_table);
+  b->d_ctrl = (Ctrl*)(ws + L.off_ctrl);
+  b->probs.assign(hs.size(), BatchProblem{});
+  b->ctrl.assign(hs.size(), Ctrl{});
+  if (hipMemcpyAsync(b->d_table, table.data(), table.size() * sizeof(BatchEntry), hipMemcpyHostToDevice,
+                     b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess) {
+    delete b;
+    return EHDG_ERR_HIP;
+  }
+  *out = b;
+  return EHDG_OK;
+}
+
+int ehdg_batch_solve(ehdg_batch b, double rel_tol, int32_t max_iters, int32_t* iters, double* rel_res) {
+  if (!b || max_iters < 1 || !(rel_tol >= 0.0)) return EHDG_ERR_INVALID_ARG;
+  const size_t n = b->h.size();
+  int rc = batch_quiesce(b);
+  if (!rc) rc = batch_upload(b, std::vector<int>(n, INT32_MAX));
+  if (rc) return rc;
+  launch_ctrl_reset_batch(b->d_probs, (int)n, 0, b->stream);
+  int pred = 1;
+  for (auto* h : b->h) pred = std::max(pred, h->predict);
+  int launched = 0, chunk = pred, next = 2;
+  for (;;) {
+    const int nq = std::min(chunk, max_iters - launched);
+    for (int j = 0; j < nq; ++j)
+      for (const auto& g : b->groups)
+        g.ks->sweep64_batch(b->d_table + g.sweep_first, g.sweep_n, b->d_probs, rel_tol, b->stream);
+    launched += nq;
+    if ((rc = batch_check_launch(b)) || (rc = batch_sync_ctrl(b))) return rc;
+    bool all = true;
+    for (const Ctrl& c : b->ctrl) all = all && c.done;
+    if (all || launched >= max_iters) break;
+    chunk = next;
+    next = std::min(next * 2, 64);
+  }
+  int first_bad = EHDG_OK;
+  for (size_t i = 0; i < n; ++i) {
+    ehdg_problem* h = b->h[i];
+    h->mirror = b->ctrl[i];
+    const Ctrl& c = h->mirror;
+    if (iters) iters[i] = c.iters;
+    if (rel_res) rel_res[i] = c.last_res;
+    if (c.status == 1) h->predict = c.iters;
+    const int st = c.status == 2 ? EHDG_ERR_DIVERGED : (c.status == 1 ? EHDG_OK : EHDG_ERR_NOT_CONVERGED);
+    if (st && !first_bad) first_bad = st;
+    h->recovered = -1;
+    if (c.iters > 0 && c.status != 2) {
+      h->ks->volume(h->dp, h->dp.s[(c.base + c.iters - 1) & 1], u_cur(h), u_other(h), b->stream);
+      h->recovered = 1;
+    }
+  }
+  if ((rc = batch_check_launch(b))) return rc;
+  HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+  if (first_bad) b->err = first_bad == EHDG_ERR_DIVERGED ? "a member diverged" : "a member reached the cap";
+  return first_bad;
+}
+
+int ehdg_batch_step(ehdg_batch b, int32_t n_steps, double rel_tol, int32_t max_iters_per_step,
+                    int32_t* iters_per_step) {
+  if (!b || n_steps < 0 || max_iters_per_step < 1 || !(rel_tol >= 0.0)) return EHDG_ERR_INVALID_ARG;
+  for (auto* h : b->h)
+    if (!h->dp.be) return bfail(b, EHDG_ERR_INVALID_ARG, "ehdg_batch_step needs backward-Euler members");
+  if (n_steps == 0) return EHDG_OK;
+  const size_t n = b->h.size();
+  int rc = batch_quiesce(b);
+  if (rc) return rc;
+  // the first step of each member continues from its latest state
+  if ((rc = batch_upload(b, std::vector<int>(n, INT32_MAX)))) return rc;
+  launch_ctrl_reset_batch(b->d_probs, (int)n, 0, b->stream);
+  if ((rc = batch_sync_ctrl(b))) return rc;
+  std::vector<int> first(n), target(n);
+  for (size_t i = 0; i < n; ++i) {
+    first[i] = b->ctrl[i].steps_done;
+    target[i] = first[i] + n_steps;
+  }
+  if ((rc = batch_upload(b, target))) return rc;
+  int pred = 1;
+  for (auto* h : b->h) pred = std::max(pred, h->predict);
+  const int max_outer = max_iters_per_step;
+  int status = EHDG_OK;
+  for (;;) {
+    int remaining = 0;
+    for (size_t i = 0; i < n; ++i) remaining = std::max(remaining, target[i] - b->ctrl[i].steps_done);
+    if (remaining <= 0) break;
+    const int per = std::min(pred + 1, max_outer);
+    for (int r = 0; r < remaining; ++r) {
+      for (int j = 0; j < per; ++j)
+        for (const auto& g : b->groups)
+          g.ks->sweep64_batch(b->d_table + g.sweep_first, g.sweep_n, b->d_probs, rel_tol, b->stream);
+      for (const auto& g : b->groups) g.ks->step_batch(b->d_table + g.step_first, g.step_n, b->d_probs, 1, b->stream);
+    }
+    if ((rc = batch_check_launch(b)) || (rc = batch_sync_ctrl(b))) return rc;
+    bool stuck = false;
+    for (size_t i = 0; i < n; ++i) {
+      const Ctrl& c = b->ctrl[i];
+      if (c.status == 2) status = EHDG_ERR_DIVERGED;
+      if (c.steps_done < target[i] && c.iters >= max_outer) stuck = true;
+    }
+    if (status) break;
+    if (stuck) {
+      status = EHDG_ERR_NOT_CONVERGED;
+      break;
+    }
+    pred = std::min(2 * pred, max_outer);  // a round that left steps undone queued too few sweeps
+  }
+  for (size_t i = 0; i < n; ++i) {
+    ehdg_problem* h = b->h[i];
+    h->mirror = b->ctrl[i];
+    h->recovered = -1;
+    const int done = h->mirror.steps_done - first[i];
+    std::vector<int> its(std::max(done, 0));
+    if (done > 0)
+      HIP_TRY_B(b, hipMemcpy(its.data(), h->dp.step_iters + first[i] % kStepCap, done * sizeof(int),
+                             hipMemcpyDeviceToHost));
+    int mx = 1;
+    for (int v : its) mx = std::max(mx, v);
+    h->predict = mx;
+    if (iters_per_step)
+      for (int k = 0; k < n_steps; ++k) iters_per_step[i * n_steps + k] = k < done ? its[k] : 0;
+    if (!status && done < n_steps) status = EHDG_ERR_NOT_CONVERGED;
+  }
+  if (status) b->err = status == EHDG_ERR_DIVERGED ? "a member diverged" : "a member did not finish its steps";
+  return status;
+}
+
+int ehdg_batch_destroy(ehdg_batch b) {
+  if (!b) return EHDG_ERR_INVALID_ARG;
+  delete b;
+  return EHDG_OK;
+}
+
+const char* ehdg_batch_last_error(ehdg_batch b) { return b ? b->err.c_str() : "null batch"; }
 
 const char* ehdg_error_string(int code) {
   switch (code) {

@@ -89,6 +89,33 @@ struct DevProblem {
   int hist_cap;
 };
 
+// One problem of a batch as the batched kernels see it (device memory, one per problem).
+struct BatchProblem {
+  MeshDev mesh;
+  int steps_target;        // the batched step stops a problem after this many completed steps
+  int hist_cap, step_cap;
+  const double* Tf64;      // fragment-major operators
+  const double* Mf64;
+  const double* g;
+  double* s0;
+  double* s1;
+  double* u0;
+  double* u1;
+  const double* w_src;     // null: no forcing / boundary data
+  const double* gbe;       // null: no forcing / boundary data
+  Ctrl* ctrl;
+  unsigned* counters;
+  double* partials;
+  double* hist;
+  int* step_iters;
+};
+
+// One workgroup of a batched launch: its problem, its index among that problem's
+// workgroups, their number, and the 16-element tiles each of them takes.
+struct BatchEntry {
+  int problem, block, nblocks, tiles_per_group;
+};
+
 // Kernels of one (pde, dim, active axes, face nodes) family.
 struct KernelSet {
   // one FP64 sweep s^{k+1} = g + T in(s^k), buffers from the control block, with the
@@ -109,6 +136,14 @@ struct KernelSet {
   void (*inner32)(const DevProblem&, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t);
   void (*refine16)(const DevProblem&, const void* lo_in, void* r_out, double tol, hipStream_t);
   void (*inner16)(const DevProblem&, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t);
+  // workgroups of the FP64 sweep / step completion for n_el elements (the same shape a
+  // single problem launches with, so batched and single results agree bit for bit)
+  void (*sweep_groups)(int nel, int* tiles_per_group, int* groups);
+  void (*step_groups)(int nel, int* tiles_per_group, int* groups);
+  // one FP64 sweep / one step completion of every problem of a batch that uses this
+  // family: n entries of table, problems in probs (device memory)
+  void (*sweep64_batch)(const BatchEntry* table, int n, const BatchProblem* probs, double tol, hipStream_t);
+  void (*step_batch)(const BatchEntry* table, int n, const BatchProblem* probs, int lag, hipStream_t);
 };
 
 const KernelSet* find_kernels(int pde, int dim, int na, int nf);
@@ -128,6 +163,9 @@ void launch_bc_inputs(const DevProblem& dp, const double* bc, double* in_bc, hip
 // latest state; full = 2: the same, but only if the current segment has finished
 void launch_ctrl_reset(Ctrl* c, int full, hipStream_t st);
 void launch_counters_reset(unsigned* counters, hipStream_t st);
+// the same reset for every problem of a batch, and a copy of their control blocks into out[n]
+void launch_ctrl_reset_batch(const BatchProblem* probs, int n, int full, hipStream_t st);
+void launch_ctrl_gather(const BatchProblem* probs, int n, Ctrl* out, hipStream_t st);
 void launch_cast(const double* src, void* dst, size_t count, int to_bf16, hipStream_t st);
 
 }  // namespace ehdg

@@ -296,9 +296,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// NW: wavefronts per workgroup
+// NW: wavefronts per workgroup; (bid, nb): this workgroup's index among the nb
+// workgroups that share the reduction (a whole launch, or one problem of a batch)
 template <int NW = kWaves>
-__device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
+__device__ void finish_residual(double d2, double n2, const ResidArgs& ra, int bid, int nb) {
   constexpr int NT = 64 * NW;
   __shared__ double sd[NW][2];
   __shared__ int is_last;
@@ -320,10 +321,10 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
     // all XCDs see them).  Waiting for their completion before the arrival is counted
     // orders them before it, without a device-wide release fence: such a fence writes
     // back this XCD's whole L2 and, once per workgroup, costs more than the sweep.
-    __hip_atomic_store(&ra.partials[2 * blockIdx.x], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&ra.partials[2 * blockIdx.x + 1], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ra.partials[2 * bid], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ra.partials[2 * bid + 1], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_s_waitcnt(0);
-    is_last = arrive_last(ra.cnt, blockIdx.x, gridDim.x) ? 1 : 0;
+    is_last = arrive_last(ra.cnt, bid, nb) ? 1 : 0;
   }
   __syncthreads();
   if (!is_last) return;
@@ -332,7 +333,6 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
   // kU partials per thread are loaded together (unconditional loads at clamped
   // indices, so all are in flight at once), then summed in a fixed order
   constexpr int kU = 8;
-  const int nb = (int)gridDim.x;
   double a = 0.0, b = 0.0;
   for (int i0 = threadIdx.x; i0 < nb; i0 += NT * kU) {
     double pa[kU], pb[kU];
@@ -379,6 +379,11 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
       c->done = 1;
     }
   }
+}
+
+template <int NW = kWaves>
+__device__ __forceinline__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
+  finish_residual<NW>(d2, n2, ra, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -609,9 +614,9 @@ struct SweepWaves {  // wavefronts per workgroup of the matrix-core sweep
 };
 
 template <class F, bool DEVPAR>
-__global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma(
-    MeshDev m, Ld64 ld, const double* __restrict__ g, const double* __restrict__ Tf, double* out, ResidArgs ra,
-    double* s0, double* s1, int tiles_per_group) {
+__device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double* __restrict__ g,
+                                                const double* __restrict__ Tf, double* out, const ResidArgs& ra,
+                                                double* s0, double* s1, int tiles_per_group, int bid, int nbk) {
   using TL = Tiling64<F::S, F::I>;
   constexpr int MTW = TL::MTW, KT = TL::KT;
   const CtrlHead ch = ctrl_head(ra.ctrl);
@@ -632,7 +637,7 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma(
   }
   const size_t nel = (size_t)m.nel;
   const int ntiles = (m.nel + 15) >> 4;
-  const int t0 = remap_block(blockIdx.x, gridDim.x) * tiles_per_group;
+  const int t0 = remap_block(bid, nbk) * tiles_per_group;
   const int t1 = min(t0 + tiles_per_group, ntiles);
   double d2 = 0.0, n2 = 0.0;
   if constexpr (TL::WPG > 1) {
@@ -649,7 +654,7 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma(
           d2 += dd * dd;
           n2 += v * v;
         });
-    finish_residual<TL::NW>(d2, n2, ra);
+    finish_residual<TL::NW>(d2, n2, ra, bid, nbk);
     return;
   }
   for (int t = t0 + slot; t < t1; t += TL::TS) {
@@ -694,7 +699,14 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma(
         }
       }
   }
-  finish_residual<TL::NW>(d2, n2, ra);
+  finish_residual<TL::NW>(d2, n2, ra, bid, nbk);
+}
+
+template <class F, bool DEVPAR>
+__global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma(
+    MeshDev m, Ld64 ld, const double* __restrict__ g, const double* __restrict__ Tf, double* out, ResidArgs ra,
+    double* s0, double* s1, int tiles_per_group) {
+  sweep_mfma_body<F, DEVPAR>(m, ld, g, Tf, out, ra, s0, s1, tiles_per_group, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // mixed precision outer step: s_out = s_in (+ lo_in); r = g + T in(s_out) - s_out (FP64);
@@ -1044,10 +1056,11 @@ struct StepTiling {
 };
 
 template <class F>
-__global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
-    MeshDev m, double* s0, double* s1, const double* __restrict__ Mf, double* u0, double* u1,
-    const double* __restrict__ w_src, const double* __restrict__ gbe, double* __restrict__ g_out, Ctrl* ctrl,
-    unsigned* cnt, int* step_iters, int step_cap, int lag, int tiles_per_group) {
+__device__ __forceinline__ void step_mfma_body(MeshDev m, double* s0, double* s1, const double* __restrict__ Mf,
+                                               double* u0, double* u1, const double* __restrict__ w_src,
+                                               const double* __restrict__ gbe, double* __restrict__ g_out,
+                                               Ctrl* ctrl, unsigned* cnt, int* step_iters, int step_cap, int lag,
+                                               int tiles_per_group, int bid, int nbk) {
   using TL = typename StepTiling<F>::TL;
   constexpr int MTW = TL::MTW, KT = TL::KT, N = F::N, ROWS = F::N + F::S, COLS = F::N + F::I;
   const CtrlHead ch = ctrl_head(ctrl);
@@ -1066,7 +1079,7 @@ __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
   const double* __restrict__ u_old = uc ? u1 : u0;
   double* __restrict__ u_new = uc ? u0 : u1;
   const int ntiles = (m.nel + 15) >> 4;
-  const int t0 = remap_block(blockIdx.x, gridDim.x) * tiles_per_group;
+  const int t0 = remap_block(bid, nbk) * tiles_per_group;
   const int t1 = min(t0 + tiles_per_group, ntiles);
   auto colval = [&](int c, int es, const Nb& nb) {
     // inputs: u_old rows, then the gathered trace rows (the branch is uniform across a
@@ -1138,7 +1151,7 @@ __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
   __shared__ int is_last;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) is_last = arrive_last(cnt, blockIdx.x, gridDim.x) ? 1 : 0;
+  if (threadIdx.x == 0) is_last = arrive_last(cnt, bid, nbk) ? 1 : 0;
   __syncthreads();
   if (is_last && threadIdx.x == 0) {
     step_iters[ctrl->steps_done % step_cap] = iters;
@@ -1149,6 +1162,49 @@ __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
     ctrl->done = 0;
     ctrl->status = 0;
   }
+}
+
+template <class F>
+__global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
+    MeshDev m, double* s0, double* s1, const double* __restrict__ Mf, double* u0, double* u1,
+    const double* __restrict__ w_src, const double* __restrict__ gbe, double* __restrict__ g_out, Ctrl* ctrl,
+    unsigned* cnt, int* step_iters, int step_cap, int lag, int tiles_per_group) {
+  step_mfma_body<F>(m, s0, s1, Mf, u0, u1, w_src, gbe, g_out, ctrl, cnt, step_iters, step_cap, lag, tiles_per_group,
+                    (int)blockIdx.x, (int)gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// batched launches: every problem of a batch that shares this family in one launch
+// ---------------------------------------------------------------------------
+// Each workgroup looks up its problem and its place among that problem's workgroups in a
+// table; the work per workgroup is exactly what a single-problem launch gives it.
+template <class F>
+__global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma_batch(
+    const BatchEntry* __restrict__ table, const BatchProblem* __restrict__ probs, double tol, int stop) {
+  const BatchEntry be = table[blockIdx.x];
+  const BatchProblem& P = probs[be.problem];
+  if (P.ctrl->steps_done >= P.steps_target) return;  // this problem has taken its steps
+  ResidArgs ra;
+  ra.ctrl = P.ctrl;
+  ra.cnt = P.counters;
+  ra.partials = P.partials;
+  ra.hist = P.hist;
+  ra.hist_cap = P.hist_cap;
+  ra.tol = tol;
+  ra.stop = stop;
+  sweep_mfma_body<F, true>(P.mesh, Ld64{P.s0, (size_t)P.mesh.nel}, P.g, P.Tf64, nullptr, ra, P.s0, P.s1,
+                           be.tiles_per_group, be.block, be.nblocks);
+}
+
+template <class F>
+__global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma_batch(
+    const BatchEntry* __restrict__ table, const BatchProblem* __restrict__ probs, int lag) {
+  const BatchEntry be = table[blockIdx.x];
+  const BatchProblem& P = probs[be.problem];
+  if (P.ctrl->steps_done >= P.steps_target) return;
+  step_mfma_body<F>(P.mesh, P.s0, P.s1, P.Mf64, P.u0, P.u1, P.w_src, P.gbe, const_cast<double*>(P.g), P.ctrl,
+                    P.counters + kCounterSet, P.step_iters, P.step_cap, lag, be.tiles_per_group, be.block,
+                    be.nblocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -1215,6 +1271,25 @@ struct Family {
       hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, s_prev, dp.Mvol, (const double*)nullptr, wsrc,
                          (const double*)nullptr, u_out);
     }
+  }
+  static void sweep_groups(int nel, int* tpg, int* groups) {
+    using TL = Tiling64<F::S, F::I>;
+    mfma_groups(nel, TL::NW, TL::TS, *tpg, *groups);
+  }
+  static void step_groups(int nel, int* tpg, int* groups) {
+    using TL = typename StepTiling<F>::TL;
+    mfma_groups(nel, TL::NW, TL::TS, *tpg, *groups);
+  }
+  static void sweep64_batch(const BatchEntry* table, int n, const BatchProblem* probs, double tol, hipStream_t st) {
+    using TL = Tiling64<F::S, F::I>;
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_sweep_mfma_batch<F>), dim3(n), dim3(64 * TL::NW), 0, st, table, probs, tol,
+                       tol >= 0.0 ? 1 : 0);
+  }
+  static void step_batch(const BatchEntry* table, int n, const BatchProblem* probs, int lag, hipStream_t st) {
+    using TL = typename StepTiling<F>::TL;
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_step_mfma_batch<F>), dim3(n), dim3(64 * TL::NW), 0, st, table, probs, lag);
   }
   static void step(const DevProblem& dp, int lag, hipStream_t st) {
     using TL = typename StepTiling<F>::TL;
@@ -1362,10 +1437,12 @@ struct HasMfmaTiling<TransportFam<3, 3, 4>> {
 // ---------------------------------------------------------------------------
 template <class F>
 static const KernelSet* set_of() {
-  static const KernelSet ks = {&Family<F>::sweep64,  &Family<F>::volume,
-                               &Family<F>::step,     &Family<F>::refine32,
-                               &Family<F>::inner32,  Bf16Ops<F, HasMfmaTiling<F>::value>::refine,
-                               Bf16Ops<F, HasMfmaTiling<F>::value>::inner};
+  static const KernelSet ks = {&Family<F>::sweep64,       &Family<F>::volume,
+                               &Family<F>::step,          &Family<F>::refine32,
+                               &Family<F>::inner32,       Bf16Ops<F, HasMfmaTiling<F>::value>::refine,
+                               Bf16Ops<F, HasMfmaTiling<F>::value>::inner,
+                               &Family<F>::sweep_groups,  &Family<F>::step_groups,
+                               &Family<F>::sweep64_batch, &Family<F>::step_batch};
   return &ks;
 }
 
@@ -1494,8 +1571,7 @@ void launch_fill_bytes(void* p, size_t bytes, hipStream_t st) {
                      (uint32_t*)p, words);
 }
 
-__global__ void k_ctrl_reset(Ctrl* c, int full) {
-  if (threadIdx.x != 0) return;
+__device__ void ctrl_reset(Ctrl* c, int full) {
   if (full == 1) {
     c->base = 0;
     c->ucur = 0;
@@ -1508,6 +1584,28 @@ __global__ void k_ctrl_reset(Ctrl* c, int full) {
   c->done = 0;
   c->iters = 0;
   c->status = 0;
+}
+
+__global__ void k_ctrl_reset(Ctrl* c, int full) {
+  if (threadIdx.x == 0) ctrl_reset(c, full);
+}
+
+__global__ void k_ctrl_reset_batch(const BatchProblem* probs, int n, int full) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) ctrl_reset(probs[i].ctrl, full);
+}
+
+__global__ void k_ctrl_gather(const BatchProblem* probs, int n, Ctrl* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = *probs[i].ctrl;
+}
+
+void launch_ctrl_reset_batch(const BatchProblem* probs, int n, int full, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_ctrl_reset_batch, dim3((n + 63) / 64), dim3(64), 0, st, probs, n, full);
+}
+
+void launch_ctrl_gather(const BatchProblem* probs, int n, Ctrl* out, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_ctrl_gather, dim3((n + 63) / 64), dim3(64), 0, st, probs, n, out);
 }
 
 __global__ void k_counters_reset(unsigned* cnt) {

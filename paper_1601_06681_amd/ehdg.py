@@ -10,11 +10,12 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (EHDG_BF16_REFINE, EHDG_ERR_DIVERGED, EHDG_ERR_NOT_CONVERGED, EHDG_ERR_UNSUPPORTED,
-                   EHDG_FP32_REFINE, EHDG_FP64, EHDG_EULER, EHDG_OK, EHDG_SWE, EHDG_TRANSPORT, ehdg_desc)
+from ._lib import (EHDG_BF16_REFINE, EHDG_ERR_DIVERGED, EHDG_ERR_HIP, EHDG_ERR_INVALID_ARG, EHDG_ERR_NOT_CONVERGED,
+                   EHDG_ERR_UNSUPPORTED, EHDG_ERR_WORKSPACE_TOO_SMALL, EHDG_FP32_REFINE, EHDG_FP64, EHDG_EULER, EHDG_OK,
+                   EHDG_SWE, EHDG_TRANSPORT, ehdg_desc)
 
 __all__ = [
-    "EhdgError", "Problem", "make_desc", *_lib.EXPORTED,
+    "EhdgError", "Problem", "Batch", "make_desc", *_lib.EXPORTED,
     "EHDG_TRANSPORT", "EHDG_SWE", "EHDG_EULER", "EHDG_FP64", "EHDG_FP32_REFINE", "EHDG_BF16_REFINE",
 ]
 
@@ -167,7 +168,101 @@ def ehdg_last_error(h):
     return _lib.load().ehdg_last_error(h).decode()
 
 
+def _aligned_bytes(torch, nbytes, device):
+    """A uint8 tensor of nbytes whose data pointer is 256-byte aligned (the ABI's workspace rule)."""
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % 256
+    return raw[off:off + nbytes]
+
+
+def _handle_array(handles):
+    arr = (ctypes.c_void_p * len(handles))()
+    for i, h in enumerate(handles):
+        arr[i] = h.value if isinstance(h, ctypes.c_void_p) else h
+    return arr
+
+
+def _check_batch(rc, b, ok=(EHDG_OK,)):
+    if rc in ok:
+        return rc
+    lib = _lib.load()
+    msg = lib.ehdg_error_string(rc).decode()
+    if b is not None:
+        last = lib.ehdg_batch_last_error(b).decode()
+        if last:
+            msg += f" ({last})"
+    raise EhdgError(rc, msg)
+
+
+def ehdg_batch_workspace_bytes(handles):
+    out = ctypes.c_size_t(0)
+    _check(_lib.load().ehdg_batch_workspace_bytes(_handle_array(handles), len(handles), ctypes.byref(out)))
+    return out.value
+
+
+def ehdg_batch_create(handles, workspace, stream=None):
+    b = ctypes.c_void_p()
+    _check(_lib.load().ehdg_batch_create(_handle_array(handles), len(handles), _ptr(workspace),
+                                         workspace.numel() * workspace.element_size(), _stream_ptr(stream),
+                                         ctypes.byref(b)))
+    return b
+
+
+def ehdg_batch_solve(b, n, rel_tol, max_iters, allow=(EHDG_OK,)):
+    its = np.zeros(n, dtype=np.int32)
+    res = np.zeros(n)
+    rc = _lib.load().ehdg_batch_solve(b, float(rel_tol), int(max_iters), its.ctypes.data_as(ctypes.c_void_p),
+                                      res.ctypes.data_as(ctypes.c_void_p))
+    _check_batch(rc, b, ok=allow)
+    return rc, its.tolist(), res.tolist()
+
+
+def ehdg_batch_step(b, n, n_steps, rel_tol, max_iters_per_step, allow=(EHDG_OK,)):
+    its = np.zeros((n, max(n_steps, 1)), dtype=np.int32)
+    rc = _lib.load().ehdg_batch_step(b, int(n_steps), float(rel_tol), int(max_iters_per_step),
+                                     its.ctypes.data_as(ctypes.c_void_p))
+    _check_batch(rc, b, ok=allow)
+    return rc, its[:, :n_steps].tolist()
+
+
+def ehdg_batch_destroy(b):
+    _check(_lib.load().ehdg_batch_destroy(b))
+
+
+def ehdg_batch_last_error(b):
+    return _lib.load().ehdg_batch_last_error(b).decode()
+
+
 # ---------------------------------------------------------------------------- convenience
+class Batch:
+    """Several Problems advanced together (ehdg_batch_*).  The Problems must outlive it."""
+
+    def __init__(self, problems, stream=None):
+        torch = _torch()
+        self.problems = list(problems)
+        handles = [p.h for p in self.problems]
+        nbytes = ehdg_batch_workspace_bytes(handles)
+        self.workspace = _aligned_bytes(torch, max(nbytes, 256), self.problems[0].device)
+        self.b = ehdg_batch_create(handles, self.workspace, stream)
+
+    def solve(self, tol, max_iters=100000, allow=(EHDG_OK,)):
+        return ehdg_batch_solve(self.b, len(self.problems), tol, max_iters, allow)
+
+    def step(self, n_steps, tol, max_iters=100000, allow=(EHDG_OK,)):
+        return ehdg_batch_step(self.b, len(self.problems), n_steps, tol, max_iters, allow)
+
+    def close(self):
+        if self.b is not None:
+            ehdg_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Problem:
     """A handle with its device workspace.  Closed-form data are sampled on the device
     at the physical points implied by the library's reference points."""
@@ -186,7 +281,7 @@ class Problem:
         self.device = torch.device(device)
         self.stream = stream
         nbytes = ehdg_workspace_bytes(self.desc)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.workspace = _aligned_bytes(torch, nbytes, self.device)
         self.h = ehdg_setup(self.desc, self.workspace, stream)
         sz = ehdg_sizes(self.h)
         self.nel, self.m, self.Np, self.S, self.I = sz["n_el"], sz["m"], sz["n_p"], sz["S"], sz["I"]

@@ -1,0 +1,128 @@
+"""Batches of independent problems (ehdg_batch_*), through the C ABI.
+
+A batch advances many problems together: each sweep is one launch per operator family,
+whose workgroups look up their problem in a table.  Each member gets exactly the work it
+gets alone, so the bar is bitwise: every member's iteration counts, residual history and
+solution equal those of the same problem advanced on its own.  One member of each batch
+is also checked against the FP64 oracle (same iteration count, 1e-10).
+"""
+import numpy as np
+import pytest
+
+from oracle import ehdg as O
+from tests._cases import gpu_transport, oracle_swe, oracle_transport, rel_err, swe_random_fns
+
+pytestmark = pytest.mark.gpu
+
+# mixed families (2D / 3D transport, degrees 2..4, ragged meshes, flow directions), two
+# members sharing one family
+STEADY = [
+    dict(n=(16, 12), L=(1.0, 1.0), p=2, beta=(1.0, 0.5), sigma=1.0),
+    dict(n=(9, 21), L=(1.0, 0.8), p=3, beta=(-0.7, 0.4), sigma=0.6),
+    dict(n=(30, 7), L=(1.0, 1.0), p=4, beta=(0.3, -1.0), sigma=1.5),
+    dict(n=(6, 5, 4), L=(1.0, 1.0, 1.0), p=2, beta=(1.0, 0.7, 0.3), sigma=1.0),
+    dict(n=(17, 3), L=(1.0, 1.0), p=2, beta=(1.0, 0.5), sigma=1.0),
+    dict(n=(5, 4, 3), L=(1.0, 0.9, 0.8), p=3, beta=(-0.6, 0.8, -1.0), sigma=0.5),
+]
+
+
+def _transport(c, **kw):
+    return gpu_transport(c["n"], c["L"], c["p"], c["beta"], c["sigma"], **kw)
+
+
+def _u(prob):
+    return prob.solution().cpu().numpy().reshape(prob.nel, -1)
+
+
+def test_batch_solve_equals_solo_and_oracle():
+    from paper_1601_06681_amd.ehdg import Batch
+    solo = []
+    for c in STEADY:
+        prob = _transport(c)
+        rc, it, res = prob.solve(1e-10, 5000)
+        solo.append((it, res, prob.solution().clone(), prob.residuals(0, it)))
+        prob.close()
+    members = [_transport(c) for c in STEADY]
+    batch = Batch(members)
+    rc, its, ress = batch.solve(1e-10, 5000)
+    assert rc == 0
+    for i, prob in enumerate(members):
+        it, res, u, hist = solo[i]
+        assert its[i] == it, (i, its[i], it)
+        assert ress[i] == res
+        assert bool((prob.solution() == u).all()), i
+        np.testing.assert_array_equal(prob.residuals(0, it), hist)
+    c = STEADY[1]
+    op, F, _, _ = oracle_transport(c["n"], c["L"], c["p"], c["beta"], c["sigma"])
+    ref = O.solve(op, F, np.zeros((op.mesh.nel, op.ref.Np)), tol=1e-10, max_iter=5000)
+    assert its[1] == ref["iters"]
+    assert rel_err(_u(members[1]), ref["u"]) < 1e-10
+    batch.close()
+
+
+def _swe(n, p, dt, periodic, seed):
+    from paper_1601_06681_amd.ehdg import EHDG_SWE, Problem
+    per = (1, 1, 0) if periodic else (0, 0, 0)
+    prob = Problem(EHDG_SWE, 2, n, L=(1.0, 1.0), periodic=per, degree=p, Phi=1.0, dt=dt)
+    prob.set_initial(swe_random_fns(seed))
+    return prob
+
+
+def _be_members():
+    import torch
+    out = [lambda: _swe((16, 16), 3, 1e-3, True, 1), lambda: _swe((12, 10), 2, 2e-3, False, 2),
+           lambda: _swe((9, 13), 4, 5e-4, True, 3)]
+
+    def transport_be():
+        c = dict(n=(10, 8), L=(1.0, 1.0), p=3, beta=(0.6, -0.8), sigma=0.5)
+        op, F, ue, f = oracle_transport(c["n"], c["L"], c["p"], c["beta"], c["sigma"], dt=0.02)
+        u0 = op.interpolate(lambda X: np.cos(3 * X[..., 0]) * np.sin(2 * X[..., 1]))
+        prob = _transport(c, dt=0.02)
+        prob.set_initial(torch.tensor(u0.reshape(op.mesh.nel, 1, -1), device=prob.device))
+        return prob
+    out.append(transport_be)
+    return out
+
+
+def test_batch_step_equals_solo_and_oracle():
+    from paper_1601_06681_amd.ehdg import Batch
+    makers = _be_members()
+    solo = []
+    for mk in makers:
+        prob = mk()
+        rc, its = prob.step(4, 1e-10, 1000)
+        solo.append((its, prob.solution().clone()))
+        prob.close()
+    members = [mk() for mk in makers]
+    batch = Batch(members)
+    rc, its = batch.step(4, 1e-10, 1000)
+    assert rc == 0
+    for i, prob in enumerate(members):
+        assert its[i] == solo[i][0], (i, its[i], solo[i][0])
+        assert bool((prob.solution() == solo[i][1]).all()), i
+    # two more steps continue each member from where the batch left it
+    rc, its2 = batch.step(2, 1e-10, 1000)
+    assert rc == 0 and all(len(v) == 2 and min(v) > 0 for v in its2)
+    # member 0 against the oracle over the first 4 steps
+    op = oracle_swe((16, 16), 3, 1.0, 1e-3, True)
+    fns = swe_random_fns(1)
+    u0 = op.interpolate([lambda X, fn=fn: fn(X, np) for fn in fns])
+    ref_u, ref_its = O.be_steps(op, u0, 4, tol=1e-10)
+    assert its[0] == ref_its
+    batch.close()
+
+
+def test_batch_iteration_cap_and_refinement_member():
+    from paper_1601_06681_amd import ehdg as E
+    members = [_transport(c) for c in STEADY[:3]]
+    batch = E.Batch(members)
+    rc, its, ress = batch.solve(1e-10, 5, allow=(E.EHDG_OK, E.EHDG_ERR_NOT_CONVERGED))
+    assert rc == E.EHDG_ERR_NOT_CONVERGED and its == [5, 5, 5]
+    batch.close()
+    low = _transport(STEADY[0], precision=1, inner=2)
+    with pytest.raises(E.EhdgError) as ei:
+        E.Batch([members[0], low])
+    assert ei.value.code == E.EHDG_ERR_UNSUPPORTED
+    with pytest.raises(E.EhdgError) as ei:
+        E.Batch([members[0], members[0]])
+    assert ei.value.code == E.EHDG_ERR_INVALID_ARG
