@@ -223,6 +223,87 @@ def run_transport3d(torch, args):
     return out
 
 
+def run_batch(torch, args):
+    """Batched uneven solves: the batch_mix problems (seed 0) advanced as two batches (the
+    steady transport members solved to 1e-10, the shallow-water members 5 backward-Euler
+    steps to 1e-10 each), against the same problems solved one after another."""
+    import numpy as np
+    from paper_1601_06681_amd import workloads as W
+    from paper_1601_06681_amd.ehdg import EHDG_SWE, EHDG_TRANSPORT, Batch, Problem
+    specs = W.batch_mix(args.batch_size, 0)
+    hump = W.gaussian_hump(W.hump_centre(0))
+
+    def make(sp):
+        if sp["kind"] == "transport":
+            prob = Problem(EHDG_TRANSPORT, 2, (sp["n"], sp["n"]), L=(1.0, 1.0), degree=sp["degree"], beta=sp["beta"],
+                           sigma=sp["sigma"])
+            ue, f = W.transport_manufactured_2d(sp["beta"], sp["sigma"])
+            prob.set_forcing([f], ue)
+            prob.set_initial(None)
+        else:
+            prob = Problem(EHDG_SWE, 2, (sp["n"], sp["n"]), L=(1.0, 1.0), periodic=(1, 1, 0), degree=sp["degree"],
+                           Phi=1.0, dt=sp["dt"])
+            prob.set_initial(hump)
+        return prob
+
+    t0 = time.perf_counter()
+    probs = [make(sp) for sp in specs]
+    torch.cuda.synchronize()
+    log(f"[bench] batch: {len(probs)} problems set up in {time.perf_counter() - t0:.1f} s")
+    tr = [i for i, sp in enumerate(specs) if sp["kind"] == "transport"]
+    sw = [i for i, sp in enumerate(specs) if sp["kind"] == "swe"]
+    dofs = [p.nel * p.m * p.Np for p in probs]
+    out = {"workload": f"batch_mix_{len(specs)}", "problems": len(specs), "transport": len(tr), "swe": len(sw),
+           "elements": int(sum(p.nel for p in probs)), "dofs": int(sum(dofs))}
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t
+
+    bt = Batch([probs[i] for i in tr])
+    bs = Batch([probs[i] for i in sw])
+    bt.solve(1e-10, 100000)                      # warm-up: kernel loading, predictions
+    bs.step(1, 1e-10, 1000)
+    for i in tr:
+        probs[i].set_initial(None)
+    for i in sw:
+        probs[i].set_initial(hump)
+    (rc_t, its_t, _), wall_t = timed(lambda: bt.solve(1e-10, 100000))
+    (rc_s, its_s), wall_s = timed(lambda: bs.step(5, 1e-10, 1000))
+    upd_t = sum(dofs[i] * its_t[k] for k, i in enumerate(tr))
+    upd_s = sum(dofs[i] * sum(its_s[k]) for k, i in enumerate(sw))
+    out["batched"] = {"transport_solve_ms": wall_t * 1e3, "transport_sweeps_total": int(sum(its_t)),
+                      "swe_5_steps_ms": wall_s * 1e3, "swe_sweeps_total": int(sum(sum(v) for v in its_s)),
+                      "dof_updates_per_s": (upd_t + upd_s) / (wall_t + wall_s)}
+    log(f"[bench] batch: transport {wall_t * 1e3:.1f} ms, swe {wall_s * 1e3:.1f} ms, "
+        f"{out['batched']['dof_updates_per_s']:.3e} DOF-updates/s")
+    # the same problems one after another (the first args.batch_solo of each kind)
+    k = args.batch_solo
+    for i in tr[:k]:
+        probs[i].set_initial(None)
+    for i in sw[:k]:
+        probs[i].set_initial(hump)
+    upd, wall = 0, 0.0
+    for i in tr[:k]:
+        (rc, it, _), w = timed(lambda: probs[i].solve(1e-10, 100000))
+        upd += dofs[i] * it
+        wall += w
+    for i in sw[:k]:
+        (rc, its), w = timed(lambda: probs[i].step(5, 1e-10, 1000))
+        upd += dofs[i] * sum(its)
+        wall += w
+    out["one_by_one_first"] = {"problems_per_kind": k, "dof_updates_per_s": upd / wall}
+    log(f"[bench] batch: one by one (first {k} of each kind) {upd / wall:.3e} DOF-updates/s")
+    bt.close()
+    bs.close()
+    for p in probs:
+        p.close()
+    return out
+
+
 def run_counter_sample(torch, args):
     """For rocprofv3 --pmc runs: a plain device-to-device copy of 256 MiB (the
     calibration kernel: it must fetch and write exactly 256 MiB each), then 20 FP64
@@ -315,6 +396,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-size", type=int, default=512)
+    ap.add_argument("--batch-solo", type=int, default=16,
+                    help="problems of each kind timed one by one for the comparison")
     ap.add_argument("--counter-sample", action="store_true",
                     help="only the copy-calibration kernel and a few sweeps, for rocprofv3 --pmc")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -341,6 +426,8 @@ def main():
     out = run_swe(args, torch)
     if not args.no_3d:
         out["transport3d"] = run_transport3d(torch, args)
+    if not args.no_batch:
+        out["batch"] = run_batch(torch, args)
     print(json.dumps(out))
 
 

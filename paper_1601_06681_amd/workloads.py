@@ -14,6 +14,7 @@ Workloads (the paper prints no timings; these are the synthetic shapes measured)
                         Gaussian-hump initial height from seed 0
   transport3d_64c_p3    3D transport on 64^3 hexes, degree 3, b = (1, 0.7, 0.3),
                         sigma = 1, manufactured u = sin(pi x) cos(pi y) sin(pi z)
+  batch_mix_512         512 independent problems drawn from seed 0 (batch_mix below)
 """
 import math
 
@@ -89,4 +90,31 @@ def scaled(cfg, n):
     """The same workload on a smaller mesh (parity tests)."""
     out = dict(cfg)
     out["n"] = tuple(n)
+    return out
+
+
+# ---------------------------------------------------------------------------- batches
+def batch_mix(count=512, seed=0):
+    """`count` independent problems drawn from numpy PCG64(seed), in draw order.
+
+    Each: side N ~ U{16..256} (N x N unit square), degree p ~ U{1..5}, and with
+    probability 1/2 each:
+      transport: steady, b = (cos t, sin t), t ~ U[0, 2 pi), sigma ~ U[0.5, 2], the
+                 manufactured solution of transport_manufactured_2d, inflow data u_e;
+      swe:       periodic shallow water, Phi = 1, the Gaussian hump of seed 0, 5
+                 backward-Euler steps with dt (p+1)(p+2) / h = 0.25.
+    Transport problems of degree 1 are drawn at degree 2 instead (the degree-1 kernels
+    with two active axes are held back)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.integers(16, 257))
+        p = int(rng.integers(1, 6))
+        if rng.random() < 0.5:
+            t = float(rng.uniform(0.0, 2.0 * PI))
+            sigma = float(rng.uniform(0.5, 2.0))
+            out.append(dict(kind="transport", n=n, degree=max(p, 2), beta=(math.cos(t), math.sin(t)), sigma=sigma))
+        else:
+            h = 1.0 / n
+            out.append(dict(kind="swe", n=n, degree=p, dt=0.25 * h / ((p + 1) * (p + 2)), steps=5))
     return out
