@@ -304,6 +304,43 @@ def run_batch(torch, args):
     return out
 
 
+def run_serving(torch, args):
+    """Serving with continuous batching: the serving_requests stream (seed 0) arriving as a
+    Poisson process at 0.8 x the capacity of the plain FP64 first-in-first-out server
+    (measured: every request set up and solved alone, one after another), served by the
+    continuous-batching server within an HBM budget.  Latency percentiles and throughput
+    of both."""
+    import numpy as np
+    from paper_1601_06681_amd import serving as S
+    from paper_1601_06681_amd import workloads as W
+    reqs = W.serving_requests(args.serve_count, 0)
+    for kind in ("euler", "transport"):         # warm-up: kernel loading
+        S.solve_alone(next(r for r in reqs if r["kind"] == kind), 1e-10)
+    t = time.perf_counter()
+    service = np.array([S.solve_alone(r, 1e-10)[0] for r in reqs])
+    log(f"[bench] serving: {len(reqs)} requests alone in {time.perf_counter() - t:.1f} s, "
+        f"mean service {service.mean() * 1e3:.2f} ms")
+    rate = 0.8 / service.mean()
+    arrivals = np.cumsum([r["gap"] for r in reqs]) / rate
+    fifo_lat, fifo_end = S.fifo_latencies(arrivals, service)
+    out = S.Server(args.serve_hbm_gb * 2 ** 30, rounds=args.serve_rounds).run(reqs, arrivals)
+    lat = out["latency"]
+
+    def pct(x):
+        return {"p50_ms": float(np.percentile(x, 50) * 1e3), "p99_ms": float(np.percentile(x, 99) * 1e3)}
+    res = {"workload": f"serving_{len(reqs)}", "requests": len(reqs),
+           "euler": sum(r["kind"] == "euler" for r in reqs), "arrival_rate_per_s": rate,
+           "fifo_fp64": {**pct(fifo_lat), "throughput_per_s": len(reqs) / fifo_end,
+                         "mean_service_ms": float(service.mean() * 1e3)},
+           "continuous_batching": {**pct(lat), "throughput_per_s": len(reqs) / out["makespan"],
+                                   "ticks": out["ticks"], "batches": out["batches"],
+                                   "peak_workspace_gb": out["peak_bytes"] / 2 ** 30,
+                                   "hbm_budget_gb": args.serve_hbm_gb, "rounds_per_tick": args.serve_rounds}}
+    log(f"[bench] serving: FIFO p50 {res['fifo_fp64']['p50_ms']:.1f} ms p99 {res['fifo_fp64']['p99_ms']:.1f} ms; "
+        f"batched p50 {res['continuous_batching']['p50_ms']:.1f} ms p99 {res['continuous_batching']['p99_ms']:.1f} ms")
+    return res
+
+
 def run_counter_sample(torch, args):
     """For rocprofv3 --pmc runs: a plain device-to-device copy of 256 MiB (the
     calibration kernel: it must fetch and write exactly 256 MiB each), then 20 FP64
@@ -400,6 +437,10 @@ def main():
     ap.add_argument("--batch-size", type=int, default=512)
     ap.add_argument("--batch-solo", type=int, default=16,
                     help="problems of each kind timed one by one for the comparison")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--serve-hbm-gb", type=float, default=64.0)
+    ap.add_argument("--serve-rounds", type=int, default=8)
     ap.add_argument("--counter-sample", action="store_true",
                     help="only the copy-calibration kernel and a few sweeps, for rocprofv3 --pmc")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -428,6 +469,8 @@ def main():
         out["transport3d"] = run_transport3d(torch, args)
     if not args.no_batch:
         out["batch"] = run_batch(torch, args)
+    if not args.no_serving:
+        out["serving"] = run_serving(torch, args)
     print(json.dumps(out))
 
 

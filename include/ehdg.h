@@ -199,6 +199,17 @@ int ehdg_batch_solve(ehdg_batch b, double rel_tol, int32_t max_iters, int32_t* i
 int ehdg_batch_step(ehdg_batch b, int32_t n_steps, double rel_tol, int32_t max_iters_per_step,
                     int32_t* iters_per_step);
 
+/* Asynchronous work, synchronous report: `rounds` rounds for every member, each one
+ * sweep (stopping test at rel_tol) and, for backward-Euler members, a step completion.
+ * Steady members stop at convergence.  Backward-Euler member i stops once it has
+ * completed step_targets[i] steps since its last ehdg_set_initial (NULL: one more step
+ * than it had completed when the call started).  Meant for serving loops that change the
+ * batch between calls: a member's state lives in its own workspace, so it continues
+ * where it stopped.  state: host array of n, 0 running, 1 finished (converged / took its
+ * steps), 2 non-finite increment.  ehdg_get_solution then gives a finished member's
+ * result. */
+int ehdg_batch_advance(ehdg_batch b, int32_t rounds, double rel_tol, const int32_t* step_targets, int32_t* state);
+
 int ehdg_batch_destroy(ehdg_batch b);
 const char* ehdg_batch_last_error(ehdg_batch b);
 

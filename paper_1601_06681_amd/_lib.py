@@ -29,7 +29,7 @@ EXPORTED = [
     "ehdg_iterate", "ehdg_solve", "ehdg_step", "ehdg_get_solution", "ehdg_get_residuals", "ehdg_sizes",
     "ehdg_state_bytes", "ehdg_get_state", "ehdg_set_state", "ehdg_destroy", "ehdg_error_string",
     "ehdg_last_error", "ehdg_batch_workspace_bytes", "ehdg_batch_create", "ehdg_batch_solve", "ehdg_batch_step",
-    "ehdg_batch_destroy", "ehdg_batch_last_error",
+    "ehdg_batch_advance", "ehdg_batch_destroy", "ehdg_batch_last_error",
 ]
 
 
@@ -88,6 +88,7 @@ def load():
         "ehdg_batch_create": (ctypes.c_int, [P, I32, P, SZ, P, ctypes.POINTER(P)]),
         "ehdg_batch_solve": (ctypes.c_int, [P, D, I32, P, P]),
         "ehdg_batch_step": (ctypes.c_int, [P, I32, D, I32, P]),
+        "ehdg_batch_advance": (ctypes.c_int, [P, I32, D, P, P]),
         "ehdg_batch_destroy": (ctypes.c_int, [P]),
         "ehdg_batch_last_error": (ctypes.c_char_p, [P]),
     }

@@ -956,6 +956,41 @@ int ehdg_batch_step(ehdg_batch b, int32_t n_steps, double rel_tol, int32_t max_i
   return status;
 }
 
+int ehdg_batch_advance(ehdg_batch b, int32_t rounds, double rel_tol, const int32_t* step_targets, int32_t* state) {
+  if (!b || rounds < 0 || !(rel_tol >= 0.0) || !state) return EHDG_ERR_INVALID_ARG;
+  const size_t n = b->h.size();
+  int rc = batch_quiesce(b);
+  if (rc) return rc;
+  std::vector<int> target(n, INT32_MAX);
+  bool any_be = false;
+  for (size_t i = 0; i < n; ++i) {
+    if (!b->h[i]->dp.be) continue;
+    any_be = true;
+    target[i] = step_targets ? step_targets[i] : b->h[i]->mirror.steps_done + 1;
+  }
+  if ((rc = batch_upload(b, target))) return rc;
+  for (int r = 0; r < rounds; ++r) {
+    for (const auto& g : b->groups)
+      g.ks->sweep64_batch(b->d_table + g.sweep_first, g.sweep_n, b->d_probs, rel_tol, b->stream);
+    if (any_be)
+      for (const auto& g : b->groups) g.ks->step_batch(b->d_table + g.step_first, g.step_n, b->d_probs, 1, b->stream);
+  }
+  if ((rc = batch_check_launch(b)) || (rc = batch_sync_ctrl(b))) return rc;
+  for (size_t i = 0; i < n; ++i) {
+    ehdg_problem* h = b->h[i];
+    h->mirror = b->ctrl[i];
+    h->recovered = -1;
+    const Ctrl& c = h->mirror;
+    if (c.status == 2)
+      state[i] = 2;
+    else if (h->dp.be)
+      state[i] = c.steps_done >= target[i] ? 1 : 0;
+    else
+      state[i] = c.status == 1 ? 1 : 0;
+  }
+  return EHDG_OK;
+}
+
 int ehdg_batch_destroy(ehdg_batch b) {
   if (!b) return EHDG_ERR_INVALID_ARG;
   delete b;

@@ -225,6 +225,18 @@ def ehdg_batch_step(b, n, n_steps, rel_tol, max_iters_per_step, allow=(EHDG_OK,)
     return rc, its[:, :n_steps].tolist()
 
 
+def ehdg_batch_advance(b, n, rounds, rel_tol, step_targets=None):
+    state = np.zeros(n, dtype=np.int32)
+    tg = None
+    if step_targets is not None:
+        tg = np.ascontiguousarray(step_targets, dtype=np.int32)
+    rc = _lib.load().ehdg_batch_advance(b, int(rounds), float(rel_tol),
+                                        tg.ctypes.data_as(ctypes.c_void_p) if tg is not None else None,
+                                        state.ctypes.data_as(ctypes.c_void_p))
+    _check_batch(rc, b)
+    return state.tolist()
+
+
 def ehdg_batch_destroy(b):
     _check(_lib.load().ehdg_batch_destroy(b))
 
@@ -250,6 +262,10 @@ class Batch:
 
     def step(self, n_steps, tol, max_iters=100000, allow=(EHDG_OK,)):
         return ehdg_batch_step(self.b, len(self.problems), n_steps, tol, max_iters, allow)
+
+    def advance(self, rounds, tol, step_targets=None):
+        """Member states after `rounds` more rounds: 0 running, 1 finished, 2 failed."""
+        return ehdg_batch_advance(self.b, len(self.problems), rounds, tol, step_targets)
 
     def close(self):
         if self.b is not None:

@@ -118,3 +118,41 @@ def batch_mix(count=512, seed=0):
             h = 1.0 / n
             out.append(dict(kind="swe", n=n, degree=p, dt=0.25 * h / ((p + 1) * (p + 2)), steps=5))
     return out
+
+
+# ---------------------------------------------------------------------------- serving
+EULER_U0 = (0.5, 0.25)
+EULER_C0 = 1.0
+
+
+def serving_requests(count=2000, seed=0):
+    """`count` requests drawn from numpy PCG64(seed), in arrival order.
+
+    Each has `gap`, an Exponential(1) inter-arrival time (the server scales it to its
+    arrival rate), and with probability 1/2 each:
+      euler:     linearized Euler about (rho0, U0, c0) = (1, (0.5, 0.25), 1), periodic
+                 N x N unit square, N ~ U{32..512}, degree 3, 10 backward-Euler steps,
+                 dt (p+1)(p+2) (|U0| + c0) / h = 0.25, a Gaussian density/pressure pulse;
+      transport: steady 3D transport, N^3 unit cube, N ~ U{16..64}, degree 2,
+                 b = (1, 0.7, 0.3), sigma = 1, the manufactured solution of
+                 transport_manufactured_3d."""
+    rng = np.random.default_rng(seed)
+    lam = math.hypot(*EULER_U0) + EULER_C0
+    out = []
+    for i in range(count):
+        gap = float(rng.exponential(1.0))
+        if rng.random() < 0.5:
+            n = int(rng.integers(32, 513))
+            p = 3
+            out.append(dict(id=i, gap=gap, kind="euler", n=n, degree=p, steps=10,
+                            dt=0.25 * (1.0 / n) / ((p + 1) * (p + 2) * lam)))
+        else:
+            n = int(rng.integers(16, 65))
+            out.append(dict(id=i, gap=gap, kind="transport", n=n, degree=2, beta=(1.0, 0.7, 0.3), sigma=1.0))
+    return out
+
+
+def euler_pulse(width=0.1, centre=(0.5, 0.5)):
+    """rho' = p' = exp(-d^2 / (2 w^2)) (periodic distance d to `centre`), u' = v' = 0."""
+    phi, zero, _ = gaussian_hump(centre, width=width)
+    return [phi, zero, zero, phi]
