@@ -323,8 +323,11 @@ def run_serving(torch, args):
     rate = 0.8 / service.mean()
     arrivals = np.cumsum([r["gap"] for r in reqs]) / rate
     fifo_lat, fifo_end = S.fifo_latencies(arrivals, service)
-    out = S.Server(args.serve_hbm_gb * 2 ** 30, rounds=args.serve_rounds).run(reqs, arrivals)
+    server = S.Server(args.serve_hbm_gb * 2 ** 30, rounds=args.serve_rounds)
+    out = server.run(reqs, arrivals)
     lat = out["latency"]
+    # capacity: everything queued at once (the FIFO capacity is 1 / mean service time)
+    sat = server.run(reqs, np.zeros(len(reqs)))
 
     def pct(x):
         return {"p50_ms": float(np.percentile(x, 50) * 1e3), "p99_ms": float(np.percentile(x, 99) * 1e3)}
@@ -335,9 +338,12 @@ def run_serving(torch, args):
            "continuous_batching": {**pct(lat), "throughput_per_s": len(reqs) / out["makespan"],
                                    "ticks": out["ticks"], "batches": out["batches"],
                                    "peak_workspace_gb": out["peak_bytes"] / 2 ** 30,
-                                   "hbm_budget_gb": args.serve_hbm_gb, "rounds_per_tick": args.serve_rounds}}
+                                   "hbm_budget_gb": args.serve_hbm_gb, "rounds_per_tick": args.serve_rounds},
+           "capacity_per_s": {"fifo_fp64": float(1.0 / service.mean()),
+                              "continuous_batching": len(reqs) / sat["makespan"]}}
     log(f"[bench] serving: FIFO p50 {res['fifo_fp64']['p50_ms']:.1f} ms p99 {res['fifo_fp64']['p99_ms']:.1f} ms; "
-        f"batched p50 {res['continuous_batching']['p50_ms']:.1f} ms p99 {res['continuous_batching']['p99_ms']:.1f} ms")
+        f"batched p50 {res['continuous_batching']['p50_ms']:.1f} ms p99 {res['continuous_batching']['p99_ms']:.1f} ms; "
+        f"capacity {res['capacity_per_s']['fifo_fp64']:.1f} vs {res['capacity_per_s']['continuous_batching']:.1f} /s")
     return res
 
 
@@ -440,7 +446,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--serve-hbm-gb", type=float, default=64.0)
-    ap.add_argument("--serve-rounds", type=int, default=8)
+    ap.add_argument("--serve-rounds", type=int, default=96)
     ap.add_argument("--counter-sample", action="store_true",
                     help="only the copy-calibration kernel and a few sweeps, for rocprofv3 --pmc")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
