@@ -107,6 +107,36 @@ int ehdg_workspace_bytes(const ehdg_desc* desc, size_t* bytes);
 int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes, void* stream,
                ehdg_handle* out);
 
+/* Transport with a velocity field beta(x): the steady problems of Sections 4.1-4.3
+ * (beta = (y, x); beta = (1 + sin(pi y / 2), 2) with discontinuous inflow data;
+ * beta = (z, x, y)).  The local equation is the one of eq. transportLocal with beta
+ * inside the integrals,
+ *   A_e = -(psi_j, div(beta psi_i))_K + sum_f <(beta.n + |beta.n|) psi_j, psi_i>_f + sigma (psi_j, psi_i)_K,
+ * lifts <|beta.n| mu_a, psi_i>_f, and the upwind trace of eq. transportLocale.  Every
+ * element has its own operator: setup builds A_e, its inverse and T_e = Q A_e^{-1} L_e
+ * per element on the host, all integrals by the p+2 point Gauss rule, and the sweep
+ * streams T_e from the workspace.
+ * Requirement: on the faces normal to axis a, beta_a has one strict sign at every face
+ * Gauss point (or is 0 at all of them: the axis carries no transport); then the upwind
+ * side of every face is fixed and the trace is the upwind element's face values, as
+ * for a constant velocity.  Otherwise UNSUPPORTED.
+ * desc: pde = EHDG_TRANSPORT, dt = 0, precision = EHDG_FP64 (else UNSUPPORTED); beta[]
+ * is ignored.  Velocity samples, HOST memory, read during the call only:
+ *   beta_q     double [n_el][dim][(p+2)^dim]: beta at the tensor Gauss points (point
+ *              order as d_forcing_q of ehdg_set_forcing)
+ *   div_beta_q double [n_el][(p+2)^dim]: div beta there, or NULL for 0
+ *   beta_face  double [n_el][2 dim][(p+2)^(dim-1)]: on face f (order x-, x+, y-, ...),
+ *              the component beta_(f/2) at the face's tensor Gauss points (tangential
+ *              axes in increasing order, first fastest)
+ * Boundary data (ehdg_set_forcing d_bc) are the nodal values of the inflow trace in the
+ * face space (for non-polynomial g, e.g. its L2 projection on each face).
+ * ehdg_variable_workspace_bytes gives a size that fits every velocity on the mesh.  The
+ * handle takes every call of a steady FP64 handle; batches return UNSUPPORTED for it. */
+int ehdg_variable_workspace_bytes(const ehdg_desc* desc, size_t* bytes);
+int ehdg_setup_variable(const ehdg_desc* desc, const double* beta_q, const double* div_beta_q,
+                        const double* beta_face, void* d_workspace, size_t workspace_bytes, void* stream,
+                        ehdg_handle* out);
+
 /* Problem data (Section 3 local equations' right-hand sides).
  *   d_forcing_q: right-hand side of each field's equation sampled at the tensor Gauss
  *                points, double [n_el][m][(p+2)^dim] with point q = q0 + (p+2) q1 +

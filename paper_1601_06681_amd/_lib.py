@@ -29,7 +29,8 @@ EXPORTED = [
     "ehdg_iterate", "ehdg_solve", "ehdg_step", "ehdg_get_solution", "ehdg_get_residuals", "ehdg_sizes",
     "ehdg_state_bytes", "ehdg_get_state", "ehdg_set_state", "ehdg_destroy", "ehdg_error_string",
     "ehdg_last_error", "ehdg_batch_workspace_bytes", "ehdg_batch_create", "ehdg_batch_solve", "ehdg_batch_step",
-    "ehdg_batch_advance", "ehdg_batch_destroy", "ehdg_batch_last_error",
+    "ehdg_batch_advance", "ehdg_batch_destroy", "ehdg_batch_last_error", "ehdg_variable_workspace_bytes",
+    "ehdg_setup_variable",
 ]
 
 
@@ -91,6 +92,8 @@ def load():
         "ehdg_batch_advance": (ctypes.c_int, [P, I32, D, P, P]),
         "ehdg_batch_destroy": (ctypes.c_int, [P]),
         "ehdg_batch_last_error": (ctypes.c_char_p, [P]),
+        "ehdg_variable_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(ehdg_desc), ctypes.POINTER(SZ)]),
+        "ehdg_setup_variable": (ctypes.c_int, [ctypes.POINTER(ehdg_desc), P, P, P, P, SZ, P, ctypes.POINTER(P)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -29,6 +29,9 @@ struct ehdg_problem {
   double* W = nullptr;
   double* Bfull = nullptr;  // n x (m * nq_el), block diagonal load matrix
   double* scratch = nullptr;
+  // variable velocity: per-element operators (T_e, R_e in dp; W_e = A_e^{-1} here)
+  bool var = false;
+  double* Wv = nullptr;
   // host mirror of the device control block, valid after every synchronizing call
   Ctrl mirror{};
   int recovered = -1;     // 1 when u2[ucur ^ 1] holds the solution of the current iterate
@@ -81,10 +84,12 @@ struct Layout {
       off_G,
       off_B, off_Mv, off_gbe;
   size_t off_s0, off_s1, off_g, off_gsrc, off_wsrc, off_u0, off_u1, off_lo0, off_lo1, off_rlo0, off_rlo1, off_scratch;
+  size_t off_Tv, off_Rv, off_Wv;
   size_t total;
 };
 
-Layout layout_for(const Operators& o, long long nel, bool lowp) {
+// var: room for the per-element operators of a variable velocity
+Layout layout_for(const Operators& o, long long nel, bool lowp, bool var = false) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -93,7 +98,8 @@ Layout layout_for(const Operators& o, long long nel, bool lowp) {
     return at;
   };
   // one partial pair per workgroup: at most one workgroup per 16-element tile
-  const size_t nb = (size_t)((nel + kMfmaTileElems - 1) / kMfmaTileElems);
+  size_t nb = (size_t)((nel + kMfmaTileElems - 1) / kMfmaTileElems);
+  if (var) nb = std::max(nb, (size_t)var_sweep_groups(nel, o.S));
   const size_t S = o.S, I = o.I, n = o.n, ne = (size_t)nel;
   const size_t Sp = (size_t)padded_rows(o.S);
   L.off_ctrl = take(sizeof(Ctrl));
@@ -128,6 +134,9 @@ Layout layout_for(const Operators& o, long long nel, bool lowp) {
   L.off_rlo1 = take(lowp ? S * ne * 4 : 8);
   const size_t scr = std::max((size_t)o.m * o.nq_el, I);
   L.off_scratch = take(scr * ne * 8);
+  L.off_Tv = take(var ? S * I * ne * 8 : 8);
+  L.off_Rv = take(var ? n * I * ne * 8 : 8);
+  L.off_Wv = take(var ? n * n * ne * 8 : 8);
   L.total = off;
   return L;
 }
@@ -278,23 +287,29 @@ int ehdg_workspace_bytes(const ehdg_desc* desc, size_t* bytes) {
   return EHDG_OK;
 }
 
-int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes, void* stream, ehdg_handle* out) {
+// smp: velocity samples of a variable-velocity transport problem, else null
+static int setup_impl(const ehdg_desc* desc, const VarSamples* smp, void* d_workspace, size_t workspace_bytes,
+                      void* stream, ehdg_handle* out) {
   if (!out || !desc) return EHDG_ERR_INVALID_ARG;
   *out = nullptr;
   std::string v = validate(desc);
   if (!v.empty()) return EHDG_ERR_INVALID_ARG;
   if (!d_workspace || ((uintptr_t)d_workspace & 255)) return EHDG_ERR_INVALID_ARG;
+  if (smp && desc->precision != EHDG_FP64) return EHDG_ERR_UNSUPPORTED;
   ehdg_problem* h = new (std::nothrow) ehdg_problem();
   if (!h) return EHDG_ERR_INVALID_ARG;
   h->desc = *desc;
   h->stream = (hipStream_t)stream;
-  std::string e = build_operators(to_desc(desc), h->ops);
+  h->var = smp != nullptr;
+  VarOperators vo;
+  std::string e = smp ? build_variable_operators(to_desc(desc), smp, h->ops, &vo) : build_operators(to_desc(desc), h->ops);
   if (!e.empty()) {
     delete h;
     return EHDG_ERR_UNSUPPORTED;
   }
   const Operators& o = h->ops;
-  h->ks = find_kernels(desc->pde, desc->dim, desc->pde == 0 ? o.na : 0, desc->degree);
+  h->ks = smp ? find_var_kernels(desc->dim, o.na, desc->degree)
+              : find_kernels(desc->pde, desc->dim, desc->pde == 0 ? o.na : 0, desc->degree);
   const bool lowp = desc->precision != EHDG_FP64;
   if (!h->ks || (desc->precision == EHDG_BF16_REFINE && !h->ks->refine16) ||
       (desc->precision == EHDG_FP32_REFINE && !h->ks->refine32)) {
@@ -302,7 +317,7 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
     return EHDG_ERR_UNSUPPORTED;
   }
   const long long nel = nel_of(desc);
-  Layout L = layout_for(o, nel, lowp);
+  Layout L = layout_for(o, nel, lowp, h->var);
   if (workspace_bytes < L.total) {
     delete h;
     return EHDG_ERR_WORKSPACE_TOO_SMALL;
@@ -363,6 +378,10 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   h->W = (double*)(ws + L.off_W);
   h->Bfull = (double*)(ws + L.off_B);
   h->scratch = (double*)(ws + L.off_scratch);
+  dp.in_scratch = h->scratch;
+  dp.Tv = (const double*)(ws + L.off_Tv);
+  dp.Rv = (const double*)(ws + L.off_Rv);
+  h->Wv = (double*)(ws + L.off_Wv);
   int rc = 0;
   const size_t SI = (size_t)padded_rows(o.S) * o.I;
   // operators (FP64 host -> device, rows zero-padded to whole row groups) and the
@@ -389,7 +408,10 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
       (rc = upload(h, h->W, o.W.a.data(), (size_t)o.n * o.n * 8)) ||
       (rc = upload(h, h->Bfull, B.data(), B.size() * 8)) ||
       (o.be && (rc = upload(h, (void*)dp.P, o.P.a.data(), (size_t)o.n * o.n * 8))) ||
-      (o.be && (rc = upload(h, (void*)dp.G, o.G.a.data(), (size_t)o.S * o.n * 8)))) {
+      (o.be && (rc = upload(h, (void*)dp.G, o.G.a.data(), (size_t)o.S * o.n * 8))) ||
+      (h->var && ((rc = upload(h, (void*)dp.Tv, vo.T.data(), vo.T.size() * 8)) ||
+                  (rc = upload(h, (void*)dp.Rv, vo.R.data(), vo.R.size() * 8)) ||
+                  (rc = upload(h, h->Wv, vo.W.data(), vo.W.size() * 8))))) {
     delete h;
     return rc;
   }
@@ -413,6 +435,30 @@ int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes,
   return EHDG_OK;
 }
 
+int ehdg_setup(const ehdg_desc* desc, void* d_workspace, size_t workspace_bytes, void* stream, ehdg_handle* out) {
+  return setup_impl(desc, nullptr, d_workspace, workspace_bytes, stream, out);
+}
+
+int ehdg_variable_workspace_bytes(const ehdg_desc* desc, size_t* bytes) {
+  if (!bytes) return EHDG_ERR_INVALID_ARG;
+  std::string v = validate(desc);
+  if (!v.empty()) return EHDG_ERR_INVALID_ARG;
+  if (desc->precision != EHDG_FP64) return EHDG_ERR_UNSUPPORTED;
+  Operators ops;
+  std::string e = build_variable_operators(to_desc(desc), nullptr, ops, nullptr);
+  if (!e.empty()) return EHDG_ERR_UNSUPPORTED;
+  *bytes = layout_for(ops, nel_of(desc), false, true).total;
+  return EHDG_OK;
+}
+
+int ehdg_setup_variable(const ehdg_desc* desc, const double* beta_q, const double* div_beta_q,
+                        const double* beta_face, void* d_workspace, size_t workspace_bytes, void* stream,
+                        ehdg_handle* out) {
+  if (!beta_q || !beta_face) return EHDG_ERR_INVALID_ARG;
+  const VarSamples smp{beta_q, div_beta_q, beta_face};
+  return setup_impl(desc, &smp, d_workspace, workspace_bytes, stream, out);
+}
+
 int ehdg_set_forcing(ehdg_handle h, const double* d_forcing_q, const double* d_bc) {
   if (!h) return EHDG_ERR_INVALID_ARG;
   DevProblem& dp = h->dp;
@@ -424,13 +470,19 @@ int ehdg_set_forcing(ehdg_handle h, const double* d_forcing_q, const double* d_b
     // F = (f, psi) per field (u_other is free here), then w_src = A^{-1} F
     launch_ext_to_soa(d_forcing_q, h->scratch, o.m * o.nq_el, nel, st);
     launch_matvec(h->Bfull, o.n, o.m * o.nq_el, h->scratch, u_other(h), nel, false, st);
-    launch_matvec(h->W, o.n, o.n, u_other(h), dp.w_src, nel, false, st);
+    if (h->var)
+      launch_matvec_pe(h->Wv, o.n, o.n, u_other(h), dp.w_src, nel, false, st);
+    else
+      launch_matvec(h->W, o.n, o.n, u_other(h), dp.w_src, nel, false, st);
   } else {
     launch_fill(dp.w_src, 0.0, (size_t)o.n * nel, st);
   }
   if (d_bc) {
     launch_bc_inputs(dp, d_bc, h->scratch, st);
-    launch_matvec(dp.R, o.n, o.I, h->scratch, dp.w_src, nel, true, st);
+    if (h->var)
+      launch_matvec_pe(dp.Rv, o.n, o.I, h->scratch, dp.w_src, nel, true, st);
+    else
+      launch_matvec(dp.R, o.n, o.I, h->scratch, dp.w_src, nel, true, st);
   }
   launch_matvec(h->Q, o.S, o.n, dp.w_src, dp.g_src, nel, false, st);
   dp.has_src = d_forcing_q != nullptr || d_bc != nullptr;
@@ -736,7 +788,7 @@ int batch_check(const ehdg_handle* handles, int32_t n, std::vector<ehdg_problem*
   for (int i = 0; i < n; ++i) {
     if (!handles[i]) return EHDG_ERR_INVALID_ARG;
     if (std::find(hs.begin(), hs.end(), handles[i]) != hs.end()) return EHDG_ERR_INVALID_ARG;
-    if (mixed(handles[i])) return EHDG_ERR_UNSUPPORTED;
+    if (mixed(handles[i]) || handles[i]->var) return EHDG_ERR_UNSUPPORTED;
     hs.push_back(handles[i]);
   }
   return EHDG_OK;

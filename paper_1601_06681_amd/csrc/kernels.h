@@ -87,6 +87,12 @@ struct DevProblem {
   unsigned* counters;      // kCounterBytes: arrival counters (zero between launches)
   double* hist;            // residual ring
   int hist_cap;
+  // variable velocity: per-element operators, entry-major with the element index
+  // fastest (T_e: Tv[(c * S + r) * nel + e], R_e: Rv[(c * N_p + r) * nel + e]), and
+  // room for the gathered inputs of every element (I x nel)
+  const double* Tv;
+  const double* Rv;
+  double* in_scratch;
 };
 
 // One problem of a batch as the batched kernels see it (device memory, one per problem).
@@ -148,10 +154,26 @@ struct KernelSet {
 
 const KernelSet* find_kernels(int pde, int dim, int na, int nf);
 
+// Variable-velocity transport sweep: a wavefront takes 16 elements and a block of
+// 4 * var_rows_per_lane(S) operator rows (lane l: element l % 16, rows l / 16 + 4 k);
+// workgroups of 4 wavefronts.
+inline constexpr int var_row_blocks(int S) { return (S + 11) / 12; }
+inline constexpr int var_rows_per_lane(int S) {
+  return (S + 4 * var_row_blocks(S) - 1) / (4 * var_row_blocks(S));
+}
+inline long long var_sweep_groups(long long nel, int S) {
+  return ((nel + kMfmaTileElems - 1) / kMfmaTileElems * var_row_blocks(S) + 3) / 4;
+}
+// Kernels of variable-velocity transport (sweep64 and volume; the rest null).
+const KernelSet* find_var_kernels(int dim, int na, int p);
+
 // Generic setup-time kernels (FP64, runtime sizes).
 // y[r][e] = (accumulate ? y[r][e] : 0) + sum_c M[r][c] x[c][e]
 void launch_matvec(const double* M, int rows, int cols, const double* x, double* y, int nel, bool accumulate,
                    hipStream_t st);
+// per-element operators: y[r][e] = (accumulate ? y[r][e] : 0) + sum_c M[(c * rows + r) * nel + e] x[c][e]
+void launch_matvec_pe(const double* M, int rows, int cols, const double* x, double* y, int nel, bool accumulate,
+                      hipStream_t st);
 // SoA [K][nel] <-> external [nel][K]
 void launch_ext_to_soa(const double* ext, double* soa, int K, int nel, hipStream_t st);
 void launch_soa_to_ext(const double* soa, double* ext, int K, int nel, hipStream_t st);

@@ -1503,6 +1503,135 @@ const KernelSet* find_kernels(int pde, int dim, int na, int p) {
 }
 
 // ---------------------------------------------------------------------------
+// variable velocity: per-element operators streamed from HBM
+// ---------------------------------------------------------------------------
+// s^{k+1}_e = g_e + T_e in_e(s^k) with a different T_e (S x I) for every element.  No
+// operator entry is used by two elements, so the sweep is a stream of the T_e from
+// HBM (matrix cores would only help with reuse).  T is stored entry-major with the
+// element index fastest; lane l of a wavefront takes element 16 t + l % 16 of tile t
+// and rows 4 RPL rb + l / 16 + 4 k (k < RPL) of row block rb, so every operator load
+// of a wavefront is four 128-byte runs.  The same lanes gather the inputs in_e(c)
+// (the four lanes of an element read one address).
+template <class F>
+__global__ __launch_bounds__(256) void k_sweep_var(MeshDev m, const double* __restrict__ g,
+                                                    const double* __restrict__ Tv, ResidArgs ra, double* s0,
+                                                    double* s1) {
+  constexpr int NRB = var_row_blocks(F::S), RPL = var_rows_per_lane(F::S);
+  const CtrlHead ch = ctrl_head(ra.ctrl);
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int item = remap_block(blockIdx.x, gridDim.x) * 4 + w;  // (tile, row block) of this wavefront
+  const int tile = item / NRB, rb = item - tile * NRB;
+  const int e = tile * 16 + (lane & 15);
+  const bool valid = e < m.nel;
+  const int es = valid ? e : 0;  // stand-in element for lanes past the end: loads stay in bounds
+  const size_t nel = (size_t)m.nel;
+  int row[RPL];
+  bool live[RPL];
+  double acc[RPL];
+#pragma unroll
+  for (int k = 0; k < RPL; ++k) {
+    const int r = rb * 4 * RPL + (lane >> 4) + 4 * k;
+    live[k] = valid && r < F::S;
+    row[k] = r < F::S ? r : F::S - 1;
+    acc[k] = g[(size_t)row[k] * nel + es];
+  }
+  if (ch.done) return;
+  const int parity = (ch.base + ch.iters) & 1;
+  const Ld64 ld{parity ? s1 : s0, nel};
+  double* out = parity ? s0 : s1;
+  Nb nb;
+  F::neighbours(m, es, nb);
+  const double* __restrict__ Te = Tv + es;
+#pragma unroll 8
+  for (int c = 0; c < F::I; ++c) {
+    const double x = F::row(m, es, nb, ld, c);
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) acc[k] = fma(Te[((size_t)c * F::S + row[k]) * nel], x, acc[k]);
+  }
+  double d2 = 0.0, n2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < RPL; ++k) {
+    const double old = ld(row[k], es);
+    if (live[k]) {
+      out[(size_t)row[k] * nel + e] = acc[k];
+      const double dd = acc[k] - old;
+      d2 += dd * dd;
+      n2 += acc[k] * acc[k];
+    }
+  }
+  finish_residual<4>(d2, n2, ra);
+}
+
+// in(s) of every element into in[c][e] (recovery of the element solutions)
+template <class F>
+__global__ __launch_bounds__(kBlock) void k_gather_var(MeshDev m, const double* __restrict__ s, double* __restrict__ in) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nel) return;
+  Nb nb;
+  F::neighbours(m, e, nb);
+  const Ld64 ld{s, (size_t)m.nel};
+#pragma unroll 4
+  for (int c = 0; c < F::I; ++c) in[(size_t)c * m.nel + e] = F::row(m, e, nb, ld, c);
+}
+
+template <class F>
+struct VarFamily {
+  static void sweep64(const DevProblem& dp, double tol, hipStream_t st) {
+    const ResidArgs ra = resid_args(dp, tol, tol >= 0.0 ? 1 : 0);
+    const long long groups = var_sweep_groups(dp.mesh.nel, F::S);
+    hipLaunchKernelGGL((k_sweep_var<F>), dim3((unsigned)groups), dim3(256), 0, st, dp.mesh, (const double*)dp.g,
+                       dp.Tv, ra, dp.s[0], dp.s[1]);
+  }
+  // u_out = w_src + R_e in(s_prev)  (steady only)
+  static void volume(const DevProblem& dp, const double* s_prev, const double*, double* u_out, hipStream_t st) {
+    const int nel = dp.mesh.nel;
+    hipLaunchKernelGGL((k_gather_var<F>), dim3(nblocks(nel)), dim3(kBlock), 0, st, dp.mesh, s_prev, dp.in_scratch);
+    if (dp.has_src) (void)hipMemcpyAsync(u_out, dp.w_src, (size_t)F::N * nel * 8, hipMemcpyDeviceToDevice, st);
+    launch_matvec_pe(dp.Rv, F::N, F::I, dp.in_scratch, u_out, nel, dp.has_src, st);
+  }
+};
+
+template <class F>
+static const KernelSet* var_set_of() {
+  static const KernelSet ks = {&VarFamily<F>::sweep64, &VarFamily<F>::volume};
+  return &ks;
+}
+
+template <int DIM, int NA>
+static const KernelSet* var_transport_p(int p) {
+  if constexpr (DIM == 2) {
+    switch (p) {
+      case 1: return var_set_of<TransportFam<2, NA, 2>>();
+      case 2: return var_set_of<TransportFam<2, NA, 3>>();
+      case 3: return var_set_of<TransportFam<2, NA, 4>>();
+      case 4: return var_set_of<TransportFam<2, NA, 5>>();
+      case 5: return var_set_of<TransportFam<2, NA, 6>>();
+      case 6: return var_set_of<TransportFam<2, NA, 7>>();
+    }
+  } else {
+    switch (p) {
+      case 1: return var_set_of<TransportFam<3, NA, 2>>();
+      case 2: return var_set_of<TransportFam<3, NA, 3>>();
+      case 3: return var_set_of<TransportFam<3, NA, 4>>();
+      case 4: return var_set_of<TransportFam<3, NA, 5>>();
+    }
+  }
+  return nullptr;
+}
+
+const KernelSet* find_var_kernels(int dim, int na, int p) {
+  if (dim == 2) {
+    if (na == 1) return var_transport_p<2, 1>(p);
+    if (na == 2) return var_transport_p<2, 2>(p);
+  } else if (dim == 3) {
+    if (na == 1) return var_transport_p<3, 1>(p);
+    if (na == 2) return var_transport_p<3, 2>(p);
+    if (na == 3) return var_transport_p<3, 3>(p);
+  }
+  return nullptr;
+}
+
+// ---------------------------------------------------------------------------
 // setup-time kernels (FP64, runtime sizes)
 // ---------------------------------------------------------------------------
 __global__ void k_matvec(const double* __restrict__ M, int rows, int cols, const double* __restrict__ x,
@@ -1521,6 +1650,24 @@ void launch_matvec(const double* M, int rows, int cols, const double* x, double*
                    hipStream_t st) {
   hipLaunchKernelGGL(k_matvec, dim3(nblocks(nel)), dim3(kBlock), 0, st, M, rows, cols, x, y, nel,
                      accumulate ? 1 : 0);
+}
+
+__global__ void k_matvec_pe(const double* __restrict__ M, int rows, int cols, const double* __restrict__ x,
+                            double* __restrict__ y, int nel, int accumulate) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // = r * nel + e
+  if (t >= (size_t)rows * nel) return;
+  const size_t n = (size_t)nel;
+  const size_t r = t / n, e = t - r * n;
+  double acc = accumulate ? y[t] : 0.0;
+  for (int c = 0; c < cols; ++c) acc = fma(M[((size_t)c * rows + r) * n + e], x[c * n + e], acc);
+  y[t] = acc;
+}
+
+void launch_matvec_pe(const double* M, int rows, int cols, const double* x, double* y, int nel, bool accumulate,
+                      hipStream_t st) {
+  const size_t total = (size_t)rows * nel;
+  hipLaunchKernelGGL(k_matvec_pe, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, M, rows,
+                     cols, x, y, nel, accumulate ? 1 : 0);
 }
 
 __global__ void k_transpose(const double* __restrict__ src, double* __restrict__ dst, int K, int nel, int to_soa) {

@@ -6,9 +6,12 @@
 // mass matrices M1 and 1D convection matrices K1, scaled by the half-widths h/2.
 #include "setup.h"
 
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <thread>
 
 namespace ehdg {
 
@@ -115,7 +118,8 @@ Basis1D make_basis(int p) {
     D[(size_t)i * n + i] = diag;
   }
   b.B.assign((size_t)nq * n, 0.0);
-  std::vector<double> dB((size_t)nq * n, 0.0);
+  b.dB.assign((size_t)nq * n, 0.0);
+  std::vector<double>& dB = b.dB;
   for (int q = 0; q < nq; ++q) {
     lagrange_at(b.x, lam, b.xq[q], &b.B[(size_t)q * n]);
     for (int j = 0; j < n; ++j) {
@@ -518,6 +522,196 @@ std::string build_operators(const Desc& d, Operators& ops) {
       }
       ops.Bload(i, q) = v;
     }
+  return "";
+}
+
+
+std::string build_variable_operators(const Desc& d, const VarSamples* smp, Operators& ops, VarOperators* vo) {
+  if (d.pde != 0) return "a velocity field applies to transport";
+  if (d.dt != 0.0) return "variable-velocity transport is steady (dt = 0)";
+  if (d.dim != 2 && d.dim != 3) return "dim must be 2 or 3";
+  const int dim = d.dim, p = d.degree;
+  if (p < 1 || p > (dim == 2 ? 6 : 4)) return "degree out of range for transport";
+  long long nel = 1;
+  for (int a = 0; a < dim; ++a) {
+    if (d.n[a] < 1) return "n[a] must be >= 1";
+    nel *= d.n[a];
+  }
+  const int n1 = p + 1, nq = p + 2;
+  int nqf = 1, Nq = 1;
+  for (int a = 0; a < dim; ++a) Nq *= nq;
+  for (int a = 1; a < dim; ++a) nqf *= nq;
+  // upwind direction of each axis from the signs of beta_a on the faces normal to it
+  Desc dc = d;
+  for (int a = 0; a < 3; ++a) dc.beta[a] = a < dim ? 1.0 : 0.0;
+  if (smp) {
+    if (!smp->beta_q || !smp->beta_face) return "velocity samples missing";
+    for (int a = 0; a < dim; ++a) {
+      bool pos = false, neg = false, zero = false;
+      for (long long e = 0; e < nel; ++e)
+        for (int side = 0; side < 2; ++side) {
+          const double* v = smp->beta_face + ((size_t)e * 2 * dim + 2 * a + side) * nqf;
+          for (int q = 0; q < nqf; ++q) {
+            if (!std::isfinite(v[q])) return "velocity samples must be finite";
+            pos |= v[q] > 0.0;
+            neg |= v[q] < 0.0;
+            zero |= v[q] == 0.0;
+          }
+        }
+      if ((pos && neg) || (zero && (pos || neg)))
+        return "a velocity component changes sign or vanishes on the faces normal to its axis";
+      dc.beta[a] = pos ? 1.0 : (neg ? -1.0 : 0.0);
+    }
+    const size_t nvq = (size_t)nel * dim * Nq;
+    for (size_t k = 0; k < nvq; ++k)
+      if (!std::isfinite(smp->beta_q[k])) return "velocity samples must be finite";
+    if (smp->div_q)
+      for (size_t k = 0; k < (size_t)nel * Nq; ++k)
+        if (!std::isfinite(smp->div_q[k])) return "velocity samples must be finite";
+  }
+  // shape, Q and the load matrix are those of a constant velocity with the same signs
+  std::string err = build_operators(dc, ops);
+  if (!err.empty()) return err;
+  if (!vo) return "";
+
+  const Basis1D b = make_basis(p);
+  double hh[3] = {1, 1, 1};
+  for (int a = 0; a < dim; ++a) hh[a] = 0.5 * d.L[a] / d.n[a];
+  const ElementOps E = element_ops(b, dim, hh);
+  const int Np = E.Np, nf = E.nf, S = ops.S, I = ops.I, na = ops.na;
+  double J = 1.0;
+  for (int a = 0; a < dim; ++a) J *= hh[a];
+  // reference tables at the tensor Gauss points (axis 0 fastest): psi_i, d psi_i / d xi_a, weights
+  std::vector<double> Psi((size_t)Nq * Np), G((size_t)dim * Nq * Np), wvol(Nq);
+  for (int q = 0; q < Nq; ++q) {
+    int qa[3] = {0, 0, 0}, r = q;
+    for (int a = 0; a < dim; ++a) { qa[a] = r % nq; r /= nq; }
+    double w = J;
+    for (int a = 0; a < dim; ++a) w *= b.wq[qa[a]];
+    wvol[q] = w;
+    for (int i = 0; i < Np; ++i) {
+      double v = 1.0;
+      for (int a = 0; a < dim; ++a) v *= b.B[(size_t)qa[a] * n1 + E.nodeidx[i][a]];
+      Psi[(size_t)q * Np + i] = v;
+      for (int a = 0; a < dim; ++a) {
+        double g = b.dB[(size_t)qa[a] * n1 + E.nodeidx[i][a]];
+        for (int t = 0; t < dim; ++t)
+          if (t != a) g *= b.B[(size_t)qa[t] * n1 + E.nodeidx[i][t]];
+        G[((size_t)a * Nq + q) * Np + i] = g;
+      }
+    }
+  }
+  // face tables: trace basis mu_c at the face Gauss points (first tangential axis
+  // fastest, as the face nodes) and the face weights with the face Jacobian
+  std::vector<double> mu((size_t)nqf * nf), wfc((size_t)2 * dim * nqf);
+  for (int qf = 0; qf < nqf; ++qf)
+    for (int c = 0; c < nf; ++c) {
+      int rq = qf, rc = c;
+      double v = 1.0;
+      for (int t = 0; t < dim - 1; ++t) {
+        v *= b.B[(size_t)(rq % nq) * n1 + rc % n1];
+        rq /= nq;
+        rc /= n1;
+      }
+      mu[(size_t)qf * nf + c] = v;
+    }
+  for (int f = 0; f < 2 * dim; ++f) {
+    int tang[2] = {0, 0}, nt = 0;
+    for (int t = 0; t < dim; ++t)
+      if (t != f / 2) tang[nt++] = t;
+    for (int qf = 0; qf < nqf; ++qf) {
+      int rq = qf;
+      double w = 1.0;
+      for (int t = 0; t < nt; ++t) {
+        w *= b.wq[rq % nq] * hh[tang[t]];
+        rq /= nq;
+      }
+      wfc[(size_t)f * nqf + qf] = w;
+    }
+  }
+  const size_t ne = (size_t)nel;
+  vo->T.assign((size_t)S * I * ne, 0.0);
+  vo->R.assign((size_t)Np * I * ne, 0.0);
+  vo->W.assign((size_t)Np * Np * ne, 0.0);
+  std::atomic<long long> singular(-1);
+  auto work = [&](long long e0, long long e1) {
+    Mat A(Np, Np), L(Np, I), Ainv;
+    std::vector<double> H((size_t)Nq * Np), Mw((size_t)nf * nf);
+    for (long long e = e0; e < e1; ++e) {
+      // volume: A(i, j) = sigma M(i, j) - sum_q w_q psi_j (beta . grad psi_i + div(beta) psi_i)
+      const double* bq = smp->beta_q + (size_t)e * dim * Nq;
+      const double* dq = smp->div_q ? smp->div_q + (size_t)e * Nq : nullptr;
+      for (int q = 0; q < Nq; ++q) {
+        double ca[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) ca[a] = wvol[q] * bq[(size_t)a * Nq + q] / hh[a];
+        const double cd = dq ? wvol[q] * dq[q] : 0.0;
+        for (int i = 0; i < Np; ++i) {
+          double v = cd * Psi[(size_t)q * Np + i];
+          for (int a = 0; a < dim; ++a) v += ca[a] * G[((size_t)a * Nq + q) * Np + i];
+          H[(size_t)q * Np + i] = v;
+        }
+      }
+      for (int i = 0; i < Np; ++i)
+        for (int j = 0; j < Np; ++j) A(i, j) = d.sigma * E.M(i, j);
+      for (int q = 0; q < Nq; ++q)
+        for (int i = 0; i < Np; ++i) {
+          const double h = H[(size_t)q * Np + i];
+          if (h == 0.0) continue;
+          for (int j = 0; j < Np; ++j) A(i, j) -= h * Psi[(size_t)q * Np + j];
+        }
+      // faces of the active axes: weighted face mass Mw = <|beta.n| mu_c, mu_a>_f
+      std::fill(L.a.begin(), L.a.end(), 0.0);
+      for (int t = 0; t < na; ++t) {
+        const int ax = ops.ax[t];
+        const int f_in = 2 * ax + (ops.dir[t] > 0 ? 0 : 1), f_out = f_in ^ 1;
+        for (int side = 0; side < 2; ++side) {
+          const int f = side ? f_out : f_in;
+          const double* bf = smp->beta_face + ((size_t)e * 2 * dim + f) * nqf;
+          std::fill(Mw.begin(), Mw.end(), 0.0);
+          for (int qf = 0; qf < nqf; ++qf) {
+            const double w = wfc[(size_t)f * nqf + qf] * std::fabs(bf[qf]);
+            for (int c = 0; c < nf; ++c) {
+              const double wc = w * mu[(size_t)qf * nf + c];
+              for (int k = 0; k < nf; ++k) Mw[(size_t)c * nf + k] += wc * mu[(size_t)qf * nf + k];
+            }
+          }
+          const int col0 = (side ? na + t : t) * nf;
+          for (int c = 0; c < nf; ++c)
+            for (int k = 0; k < nf; ++k) {
+              L(E.fn[f][c], col0 + k) = Mw[(size_t)c * nf + k];
+              // beta.n + |beta.n| = 2 |beta.n| on the outflow face, 0 on the inflow face
+              if (side) A(E.fn[f][c], E.fn[f][k]) += 2.0 * Mw[(size_t)c * nf + k];
+            }
+        }
+      }
+      if (!invert(A, Ainv)) {
+        singular.store(e);
+        continue;
+      }
+      const Mat R = matmul(Ainv, L);
+      for (int col = 0; col < I; ++col) {
+        for (int r = 0; r < Np; ++r) vo->R[((size_t)col * Np + r) * ne + e] = R(r, col);
+        for (int t = 0; t < na; ++t) {
+          const int ax = ops.ax[t];
+          const int f_out = (2 * ax + (ops.dir[t] > 0 ? 0 : 1)) ^ 1;
+          for (int c = 0; c < nf; ++c) vo->T[((size_t)col * S + t * nf + c) * ne + e] = R(E.fn[f_out][c], col);
+        }
+      }
+      for (int col = 0; col < Np; ++col)
+        for (int r = 0; r < Np; ++r) vo->W[((size_t)col * Np + r) * ne + e] = Ainv(r, col);
+    }
+  };
+  unsigned nt = std::thread::hardware_concurrency();
+  nt = std::max(1u, std::min(nt, 16u));
+  if ((long long)nt > nel) nt = (unsigned)nel;
+  std::vector<std::thread> pool;
+  const long long chunk = (nel + nt - 1) / nt;
+  for (unsigned k = 0; k < nt; ++k) {
+    const long long e0 = k * chunk, e1 = std::min(nel, e0 + chunk);
+    if (e0 < e1) pool.emplace_back(work, e0, e1);
+  }
+  for (auto& th : pool) th.join();
+  if (singular.load() >= 0) return "the local operator of an element is singular";
   return "";
 }
 

@@ -22,6 +22,7 @@ struct Basis1D {
   std::vector<double> x, w;    // GLL nodes and weights (p+1)
   std::vector<double> xq, wq;  // Gauss points and weights (p+2)
   std::vector<double> B;       // nq x (p+1): l_j(xq_i)
+  std::vector<double> dB;      // nq x (p+1): l_j'(xq_i)
   std::vector<double> M1;      // (p+1)^2: int l_i l_j
   std::vector<double> K1;      // (p+1)^2: K1[i][j] = int l_j l_i'
 };
@@ -76,5 +77,26 @@ struct Desc {
 
 // Builds the operators; returns an empty string on success, else an error message.
 std::string build_operators(const Desc& d, Operators& ops);
+
+// Transport with a velocity field beta(x) (the steady problems of Sections 4.1-4.3).
+// Every element has its own local operator
+//   A_e = -(psi_j, div(beta psi_i)) + sum_f <(beta.n + |beta.n|) psi_j, psi_i>_f + sigma (psi_j, psi_i)
+// with the lifts L_e = <|beta.n| mu_a, psi_i>_f of the inflow and own outflow faces, so
+// the trace form keeps per element T_e = Q A_e^{-1} L_e, R_e = A_e^{-1} L_e and
+// W_e = A_e^{-1}, each stored entry-major with the element index fastest:
+// X[(col * rows + row) * nel + e].  The trace keeps the constant-velocity structure
+// when every velocity component is one-signed on the faces normal to its axis (no
+// face quadrature point with beta.n = 0 or of the other sign); that is checked.
+struct VarSamples {
+  const double* beta_q;     // [nel][dim][nq^dim]   velocity at the tensor Gauss points
+  const double* div_q;      // [nel][nq^dim]        div beta there, or null (zero)
+  const double* beta_face;  // [nel][2 dim][nq^(dim-1)]  beta_(f/2) at the face Gauss points
+};
+struct VarOperators {
+  std::vector<double> T, R, W;
+};
+// ops gets the shape, Q and the load matrix (the element-independent parts); with
+// vo == null only the shape for the maximum number of active axes (workspace sizing).
+std::string build_variable_operators(const Desc& d, const VarSamples* smp, Operators& ops, VarOperators* vo);
 
 }  // namespace ehdg

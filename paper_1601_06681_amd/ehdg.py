@@ -96,6 +96,29 @@ def ehdg_setup(desc, workspace, stream=None):
     return h
 
 
+def ehdg_variable_workspace_bytes(desc):
+    lib = _lib.load()
+    out = ctypes.c_size_t(0)
+    _check(lib.ehdg_variable_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def _host_f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def ehdg_setup_variable(desc, beta_q, div_beta_q, beta_face, workspace, stream=None):
+    """beta_q, div_beta_q (or None), beta_face: host arrays in the C ABI's layouts."""
+    lib = _lib.load()
+    bq, dq, bf = _host_f64(beta_q), _host_f64(div_beta_q), _host_f64(beta_face)
+    vp = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    h = ctypes.c_void_p()
+    _check(lib.ehdg_setup_variable(ctypes.byref(desc), vp(bq), vp(dq), vp(bf), _ptr(workspace),
+                                   workspace.numel() * workspace.element_size(), _stream_ptr(stream),
+                                   ctypes.byref(h)))
+    return h
+
+
 def ehdg_set_forcing(h, forcing_q=None, bc=None):
     _check(_lib.load().ehdg_set_forcing(h, _ptr(forcing_q), _ptr(bc)), h)
 
@@ -285,7 +308,9 @@ class Problem:
 
     def __init__(self, pde, dim, n, L=(1.0, 1.0, 1.0), periodic=(0, 0, 0), degree=1, beta=(0.0, 0.0, 0.0),
                  sigma=0.0, Phi=1.0, dt=0.0, precision=EHDG_FP64, inner_sweeps=1, device="cuda", stream=None,
-                 U0=(0.0, 0.0), c0=1.0, rho0=1.0):
+                 U0=(0.0, 0.0), c0=1.0, rho0=1.0, velocity=None):
+        """velocity: (beta_fn, div_fn) for transport with a velocity field (ehdg_setup_variable);
+        beta_fn(X, xp) -> (..., dim), div_fn(X, xp) -> (...) or None for div beta = 0."""
         torch = _torch()
         self.torch = torch
         self.desc = make_desc(pde, dim, n, L, periodic, degree, beta, sigma, Phi, dt, precision, inner_sweeps,
@@ -296,12 +321,19 @@ class Problem:
         self.periodic = tuple(int(v) for v in periodic[:dim])
         self.device = torch.device(device)
         self.stream = stream
-        nbytes = ehdg_workspace_bytes(self.desc)
-        self.workspace = _aligned_bytes(torch, nbytes, self.device)
-        self.h = ehdg_setup(self.desc, self.workspace, stream)
+        self.gll, self.gq, self.gw = ehdg_reference_points(degree)
+        if velocity is None:
+            nbytes = ehdg_workspace_bytes(self.desc)
+            self.workspace = _aligned_bytes(torch, nbytes, self.device)
+            self.h = ehdg_setup(self.desc, self.workspace, stream)
+        else:
+            self.nel = int(np.prod(self.n))
+            bq, dq, bf = self.velocity_samples(*velocity)
+            nbytes = ehdg_variable_workspace_bytes(self.desc)
+            self.workspace = _aligned_bytes(torch, nbytes, self.device)
+            self.h = ehdg_setup_variable(self.desc, bq, dq, bf, self.workspace, stream)
         sz = ehdg_sizes(self.h)
         self.nel, self.m, self.Np, self.S, self.I = sz["n_el"], sz["m"], sz["n_p"], sz["S"], sz["I"]
-        self.gll, self.gq, self.gw = ehdg_reference_points(degree)
 
     def close(self):
         if self.h is not None:
@@ -339,6 +371,42 @@ class Problem:
         ref = self._tensor_ref(self.gll if which == "nodes" else self.gq)
         hh = self.torch.tensor(h, dtype=self.torch.float64, device=self.device)
         return x0[:, None, :] + (ref[None, :, :] + 1.0) * 0.5 * hh
+
+    def face_quad_points(self):
+        """Physical Gauss points of every element face: (n_el, 2 dim, (p+2)^(dim-1), dim), face f
+        on axis f // 2 at its minus (f even) or plus end, tangential axes first-fastest."""
+        torch = self.torch
+        x0, h = self._elem_corners()
+        hh = torch.tensor(h, dtype=torch.float64, device=self.device)
+        d = self.dim
+        g = torch.tensor(self.gq, dtype=torch.float64, device=self.device)
+        k = len(self.gq)
+        out = []
+        for f in range(2 * d):
+            ax = f // 2
+            tang = [t for t in range(d) if t != ax]
+            ref = torch.zeros(k ** (d - 1), d, dtype=torch.float64, device=self.device)
+            ref[:, ax] = -1.0 if f % 2 == 0 else 1.0
+            idx = torch.arange(k ** (d - 1), device=self.device)
+            for j, t in enumerate(tang):
+                ref[:, t] = g[(idx // (k ** j)) % k]
+            out.append(x0[:, None, :] + (ref[None] + 1.0) * 0.5 * hh)
+        return torch.stack(out, dim=1)
+
+    def velocity_samples(self, beta_fn, div_fn=None):
+        """Host arrays (beta_q, div_beta_q, beta_face) of ehdg_setup_variable from callables (X, xp)."""
+        torch = self.torch
+        Xq = self.points("quad")
+        bq = torch.as_tensor(beta_fn(Xq, torch), dtype=torch.float64).permute(0, 2, 1).contiguous()
+        dq = None
+        if div_fn is not None:
+            dq = torch.as_tensor(div_fn(Xq, torch), dtype=torch.float64).expand(Xq.shape[:2]).contiguous()
+        Xf = self.face_quad_points()
+        Bf = torch.as_tensor(beta_fn(Xf, torch), dtype=torch.float64)           # (nel, 2d, nqf, d)
+        axis = torch.arange(2 * self.dim, device=Bf.device) // 2
+        bf = torch.gather(Bf, 3, axis[None, :, None, None].expand(*Bf.shape[:3], 1))[..., 0].contiguous()
+        cpu = lambda t: None if t is None else t.cpu().numpy()
+        return cpu(bq), cpu(dq), cpu(bf)
 
     def boundary_points(self):
         """Face-node points of every non-periodic side, in the C ABI's bc layout: (nbc, dim)."""

@@ -75,3 +75,21 @@ def test_error_strings():
     from paper_1601_06681_amd import ehdg as E
     for code in range(7):
         assert E.ehdg_error_string(code)
+
+
+def test_variable_workspace_bytes():
+    """Variable-velocity workspaces hold the per-element operators T_e (S x I), R_e and
+    A_e^{-1} (N_p x I, N_p x N_p), sized for every axis active; unsupported forms refused."""
+    from paper_1601_06681_amd import ehdg as E
+    d = E.make_desc(E.EHDG_TRANSPORT, 2, (32, 32), degree=4)
+    nbytes = E.ehdg_variable_workspace_bytes(d)
+    S, I, Np, nel = 10, 20, 25, 32 * 32
+    assert nbytes >= nel * (S * I + Np * I + Np * Np) * 8
+    assert nbytes > E.ehdg_workspace_bytes(E.make_desc(E.EHDG_TRANSPORT, 2, (32, 32), degree=4, beta=(1, 1)))
+    for bad in (dict(dt=1e-3), dict(precision=E.EHDG_FP32_REFINE, inner_sweeps=2)):
+        with pytest.raises(E.EhdgError) as ei:
+            E.ehdg_variable_workspace_bytes(E.make_desc(E.EHDG_TRANSPORT, 2, (8, 8), degree=2, **bad))
+        assert ei.value.code == 2
+    with pytest.raises(E.EhdgError) as ei:
+        E.ehdg_variable_workspace_bytes(E.make_desc(E.EHDG_SWE, 2, (8, 8), degree=2, dt=1e-3))
+    assert ei.value.code == 2
