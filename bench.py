@@ -1,7 +1,7 @@
 """Benchmark of the eHDG hot path on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload swe2d|transport3d|transport2d]
-                [--no-cpu-baseline] [--no-forms]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-forms]
+                [--no-3d] [--no-variable] [--no-batch] [--no-serving]
 
 A step is one backward-Euler time step of the linearized shallow-water workload
 (256 x 256 periodic quads, degree 4, 3 fields, 4 915 200 DOFs): build the step's
@@ -10,6 +10,10 @@ condensed local operator, write new traces, FP64 residual) until the relative tr
 increment is below 1e-10, recover the element solution.  K = 20 steps is the whole
 workload.  The printed value is whole-job throughput: DOFs x sweeps / wall time of
 the K timed steps, inputs resident in HBM.
+
+Further sections of the same JSON line (each can be switched off): 64^3 steady
+transport in FP64 and the mixed-precision forms, Section 4.1 / 4.3 variable-velocity
+transport (per-element operators), a batch of 512 mixed problems, and a serving run.
 
 One JSON line on stdout; progress on stderr.
 """
@@ -223,6 +227,10 @@ def run_transport3d(torch, args):
     return out
 
 
+# Section 4.1's velocity beta = (y, x) (div beta = 0)
+VARIABLE_BETA_2D = (lambda X, xp: xp.stack([X[..., 1], X[..., 0]], -1), None)
+
+
 def run_variable(torch, args):
     """Transport with a velocity field (per-element operators): Section 4.1's problem
     (beta = (y, x), 256 x 256, degree 4) and Section 4.3's (beta = (z, x, y), 16^3,
@@ -230,8 +238,7 @@ def run_variable(torch, args):
     from paper_1601_06681_amd.ehdg import EHDG_TRANSPORT, Problem, ehdg_set_forcing
     pi = 3.141592653589793
     cases = [
-        ("sec4.1 beta=(y,x) 256x256 p4", (256, 256), 4,
-         lambda X, xp: xp.stack([X[..., 1], X[..., 0]], -1),
+        ("sec4.1 beta=(y,x) 256x256 p4", (256, 256), 4, VARIABLE_BETA_2D[0],
          lambda X, xp: xp.sin(pi * X[..., 0]) * xp.cos(pi * X[..., 1]) / pi,
          lambda X, xp: (X[..., 1] * xp.cos(pi * X[..., 0]) * xp.cos(pi * X[..., 1])
                         - X[..., 0] * xp.sin(pi * X[..., 0]) * xp.sin(pi * X[..., 1]))),
@@ -268,10 +275,15 @@ def run_variable(torch, args):
         t_sweep = time_sweeps(torch, prob, 100)
         alg = (prob.S * prob.I + 3 * prob.S) * 8 * prob.nel
         dofs = prob.nel * prob.Np
+        tag = "variable_sweep_p4_256x256" if len(n) == 2 else None
         row = {"workload": name, "dofs": dofs, "setup_s": t_setup, "sweeps": iters, "rel_res": rr,
                "time_to_tol_ms": t * 1e3, "dof_updates_per_s": dofs * iters / t, "max_err_vs_exact": err,
-               "sweep_us": t_sweep * 1e6, "sweep_alg_bytes": alg, "sweep_GBps": alg / t_sweep / 1e9,
-               "sweep_hbm_frac": alg / t_sweep / HBM_PEAK}
+               "roofline": {"bound": "hbm", "achieved": alg / t_sweep / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                            "frac": alg / t_sweep / HBM_PEAK,
+                            "traffic": traffic_from_profiles(tag, alg) if tag else None,
+                            "kernel": f"k_sweep_var<TransportFam<{len(n)}, {len(n)}, {p + 1}>> (per-element "
+                                      "operators streamed, residual fused)",
+                            "alg_bytes_per_launch": alg, "avg_launch_us": t_sweep * 1e6}}
         log(f"[bench] variable {name}: setup {t_setup:.2f} s, {iters} sweeps in {t * 1e3:.1f} ms, sweep "
             f"{t_sweep * 1e6:.1f} us ({alg / t_sweep / 1e9:.0f} GB/s), err {err:.2e}")
         out.append(row)
@@ -406,8 +418,9 @@ def run_serving(torch, args):
 def run_counter_sample(torch, args):
     """For rocprofv3 --pmc runs: a plain device-to-device copy of 256 MiB (the
     calibration kernel: it must fetch and write exactly 256 MiB each), then 20 FP64
-    sweeps and 2 backward-Euler steps of the shallow-water workload and, unless --no-3d,
-    5 sweeps of the 64^3 transport workload."""
+    sweeps and 2 backward-Euler steps of the shallow-water workload, unless --no-3d
+    5 sweeps of the 64^3 transport workload, and unless --no-variable 20 sweeps of
+    Section 4.1's variable-velocity problem at 256 x 256, degree 4."""
     from paper_1601_06681_amd import workloads as W
     n = 256 * 1024 * 1024 // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -433,6 +446,13 @@ def run_counter_sample(torch, args):
         p3.iterate(5)
         torch.cuda.synchronize()
         p3.close()
+    if not args.no_variable:
+        from paper_1601_06681_amd.ehdg import EHDG_TRANSPORT, Problem
+        pv = Problem(EHDG_TRANSPORT, 2, (256, 256), degree=4, velocity=VARIABLE_BETA_2D)
+        pv.set_initial(None)
+        pv.iterate(20)
+        torch.cuda.synchronize()
+        pv.close()
     log("[bench] counter sample done")
 
 
@@ -440,6 +460,7 @@ PMC_KERNELS = {  # summary tag -> kernel name prefix (as rocprofv3 prints it)
     "swe_sweep_p4_256x256": "void ehdg::k_sweep_mfma<ehdg::SweFam<5>, true>",
     "swe_step_p4_256x256": "void ehdg::k_step_mfma<ehdg::SweFam<5> >",
     "transport3d_sweep_p3_64x64x64": "void ehdg::k_sweep_mfma<ehdg::TransportFam<3, 3, 4>, true>",
+    "variable_sweep_p4_256x256": "void ehdg::k_sweep_var<ehdg::TransportFam<2, 2, 5> >",
 }
 
 

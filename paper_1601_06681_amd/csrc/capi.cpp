@@ -134,7 +134,7 @@ Layout layout_for(const Operators& o, long long nel, bool lowp, bool var = false
   L.off_rlo1 = take(lowp ? S * ne * 4 : 8);
   const size_t scr = std::max((size_t)o.m * o.nq_el, I);
   L.off_scratch = take(scr * ne * 8);
-  L.off_Tv = take(var ? S * I * ne * 8 : 8);
+  L.off_Tv = take(var ? S * I * ((ne + 15) / 16 * 16) * 8 : 8);
   L.off_Rv = take(var ? n * I * ne * 8 : 8);
   L.off_Wv = take(var ? n * n * ne * 8 : 8);
   L.total = off;

@@ -87,9 +87,10 @@ struct DevProblem {
   unsigned* counters;      // kCounterBytes: arrival counters (zero between launches)
   double* hist;            // residual ring
   int hist_cap;
-  // variable velocity: per-element operators, entry-major with the element index
-  // fastest (T_e: Tv[(c * S + r) * nel + e], R_e: Rv[(c * N_p + r) * nel + e]), and
-  // room for the gathered inputs of every element (I x nel)
+  // variable velocity: per-element operators.  T_e tile-major (element e = 16 t + j:
+  // Tv[((t * I + c) * S + r) * 16 + j], tiles padded with zeros), R_e entry-major with
+  // the element index fastest (Rv[(c * N_p + r) * nel + e]), and room for the gathered
+  // inputs of every element (I x nel)
   const double* Tv;
   const double* Rv;
   double* in_scratch;

@@ -1507,10 +1507,12 @@ const KernelSet* find_kernels(int pde, int dim, int na, int p) {
 // ---------------------------------------------------------------------------
 // s^{k+1}_e = g_e + T_e in_e(s^k) with a different T_e (S x I) for every element.  No
 // operator entry is used by two elements, so the sweep is a stream of the T_e from
-// HBM (matrix cores would only help with reuse).  T is stored entry-major with the
-// element index fastest; lane l of a wavefront takes element 16 t + l % 16 of tile t
-// and rows 4 RPL rb + l / 16 + 4 k (k < RPL) of row block rb, so every operator load
-// of a wavefront is four 128-byte runs.  The same lanes gather the inputs in_e(c)
+// HBM (matrix cores would only help with reuse).  T is stored tile-major: the
+// operators of a tile of 16 elements are one contiguous block, entry (c, r) of its
+// elements 16 consecutive doubles.  Lane l of a wavefront takes element 16 t + l % 16
+// of tile t and rows 4 RPL rb + l / 16 + 4 k (k < RPL) of row block rb, so every
+// operator load of a wavefront is one contiguous 512-byte run and a wavefront streams
+// one contiguous range per input column.  The same lanes gather the inputs in_e(c)
 // (the four lanes of an element read one address).
 template <class F>
 __global__ __launch_bounds__(256) void k_sweep_var(MeshDev m, const double* __restrict__ g,
@@ -1541,12 +1543,14 @@ __global__ __launch_bounds__(256) void k_sweep_var(MeshDev m, const double* __re
   double* out = parity ? s0 : s1;
   Nb nb;
   F::neighbours(m, es, nb);
-  const double* __restrict__ Te = Tv + es;
+  const int ntiles = (m.nel + 15) >> 4;
+  const double* __restrict__ Te =
+      Tv + (size_t)(tile < ntiles ? tile : 0) * (F::I * F::S * 16) + (lane & 15);  // in bounds for idle lanes
 #pragma unroll 8
   for (int c = 0; c < F::I; ++c) {
     const double x = F::row(m, es, nb, ld, c);
 #pragma unroll
-    for (int k = 0; k < RPL; ++k) acc[k] = fma(Te[((size_t)c * F::S + row[k]) * nel], x, acc[k]);
+    for (int k = 0; k < RPL; ++k) acc[k] = fma(Te[(c * F::S + row[k]) * 16], x, acc[k]);
   }
   double d2 = 0.0, n2 = 0.0;
 #pragma unroll

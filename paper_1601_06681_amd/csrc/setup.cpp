@@ -630,7 +630,8 @@ std::string build_variable_operators(const Desc& d, const VarSamples* smp, Opera
     }
   }
   const size_t ne = (size_t)nel;
-  vo->T.assign((size_t)S * I * ne, 0.0);
+  const size_t ntiles = (ne + 15) / 16;
+  vo->T.assign((size_t)S * I * ntiles * 16, 0.0);
   vo->R.assign((size_t)Np * I * ne, 0.0);
   vo->W.assign((size_t)Np * Np * ne, 0.0);
   std::atomic<long long> singular(-1);
@@ -694,7 +695,8 @@ std::string build_variable_operators(const Desc& d, const VarSamples* smp, Opera
         for (int t = 0; t < na; ++t) {
           const int ax = ops.ax[t];
           const int f_out = (2 * ax + (ops.dir[t] > 0 ? 0 : 1)) ^ 1;
-          for (int c = 0; c < nf; ++c) vo->T[((size_t)col * S + t * nf + c) * ne + e] = R(E.fn[f_out][c], col);
+          for (int c = 0; c < nf; ++c)
+            vo->T[(((size_t)(e / 16) * I + col) * S + t * nf + c) * 16 + e % 16] = R(E.fn[f_out][c], col);
         }
       }
       for (int col = 0; col < Np; ++col)

@@ -83,8 +83,10 @@ std::string build_operators(const Desc& d, Operators& ops);
 //   A_e = -(psi_j, div(beta psi_i)) + sum_f <(beta.n + |beta.n|) psi_j, psi_i>_f + sigma (psi_j, psi_i)
 // with the lifts L_e = <|beta.n| mu_a, psi_i>_f of the inflow and own outflow faces, so
 // the trace form keeps per element T_e = Q A_e^{-1} L_e, R_e = A_e^{-1} L_e and
-// W_e = A_e^{-1}, each stored entry-major with the element index fastest:
-// X[(col * rows + row) * nel + e].  The trace keeps the constant-velocity structure
+// W_e = A_e^{-1}.  T is tile-major for the sweep (element e = 16 t + j:
+// T[((t * I + col) * S + row) * 16 + j], the last tile padded with zeros); R and W are
+// entry-major with the element index fastest: X[(col * rows + row) * nel + e].
+// The trace keeps the constant-velocity structure
 // when every velocity component is one-signed on the faces normal to its axis (no
 // face quadrature point with beta.n = 0 or of the other sign); that is checked.
 struct VarSamples {
