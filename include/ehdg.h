@@ -8,9 +8,9 @@
  * recomputes the traces from the new element solutions (eq. transportLocale for
  * transport; the trace formula below the shallow-water local solver for SWE).
  *
- * Supported problems (uniform axis-aligned meshes, constant coefficients, tensor
- * Lagrange elements of degree p on Gauss-Lobatto-Legendre nodes, Gauss-Legendre
- * quadrature with p+2 points per direction):
+ * Supported problems (uniform axis-aligned meshes, constant coefficients unless set up
+ * with ehdg_setup_variable, tensor Lagrange elements of degree p on Gauss-Lobatto-Legendre
+ * nodes, Gauss-Legendre quadrature with p+2 points per direction):
  *   EHDG_TRANSPORT  beta . grad u + sigma u = f (steady) or its backward-Euler step
  *                   (Section 3, eq. transportLocal and the time-dependent paragraph)
  *   EHDG_SWE        linearized shallow water, backward Euler, 2D, Coriolis,
