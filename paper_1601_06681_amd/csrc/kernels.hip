@@ -519,10 +519,10 @@ typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaMaxA = 48;  // operator doubles per lane a wavefront keeps in registers
 
-template <int ROWS, int COLS>
+template <int ROWS, int COLS, int MAXA = kMfmaMaxA>
 struct Tiling64 {
   static constexpr int MT = (ROWS + 15) / 16, KT = (COLS + 3) / 4;
-  static constexpr int pick(int d) { return d <= 1 ? 1 : ((MT % d == 0 && d * KT <= kMfmaMaxA) ? d : pick(d - 1)); }
+  static constexpr int pick(int d) { return d <= 1 ? 1 : ((MT % d == 0 && d * KT <= MAXA) ? d : pick(d - 1)); }
   static constexpr int MTW = pick(MT);              // row tiles per wavefront
   static constexpr int WPG = MT / MTW;              // wavefronts per element tile
   static constexpr int TS = WPG > 1 ? 1 : 4;          // element tiles in flight per workgroup
@@ -1049,9 +1049,15 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_inner32_mfma(
 // The same step completion on the matrix cores: [u_new; g_next] = [w_src; gbe] + M
 // [u_old; in(s_prev)] with the stacked operator M of (N + S) x (N + I) held as
 // fragments (fragment-major copy Mf, laid out like the sweep operator's).
+// The step completion keeps half the sweep's operator registers per wavefront (one
+// row tile of the stacked operator for the shallow-water family instead of two): at
+// 48 doubles its wavefronts needed 244 VGPRs, so only two fitted per SIMD and the
+// matrix cores were busy a third of the time; at 24 they need about 120, and twice as
+// many wavefronts share each element tile.
+constexpr int kStepMaxA = 24;
 template <class F>
 struct StepTiling {
-  using TL = Tiling64<F::N + F::S, F::N + F::I>;
+  using TL = Tiling64<F::N + F::S, F::N + F::I, kStepMaxA>;
   static constexpr int value = TL::NW;
 };
 
@@ -1213,13 +1219,25 @@ __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma_batch(
 static inline int nblocks(int nel) { return (nel + kBlock - 1) / kBlock; }
 static inline int ngroups(int nel) { return (nel + kLanes - 1) / kLanes; }
 
-// Matrix-core launches: about 4096 wavefronts (4 per SIMD), each workgroup (nw
-// wavefronts, ts element tiles in flight) taking a contiguous range of 16-element
-// tiles.  groups <= number of tiles.
-static inline void mfma_groups(int nel, int nw, int ts, int& tiles_per_group, int& groups) {
+// Workgroups of a kernel that the device holds at once (its occupancy by registers,
+// LDS and wave slots, times the compute units).
+template <typename K>
+static int resident_groups(K kernel, int threads) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  return per_cu * cus;
+}
+
+// Matrix-core launches: one round of resident workgroups (resident = how many the
+// device holds at once), each taking a contiguous range of 16-element tiles, a
+// multiple of ts (tiles in flight per workgroup).  A second, partial round would
+// leave most of the chip idle while it runs.  groups <= number of tiles.
+static inline void mfma_groups(int nel, int ts, int resident, int& tiles_per_group, int& groups) {
   const int ntiles = (nel + kMfmaTileElems - 1) / kMfmaTileElems;
-  const int target = std::max(1, 4096 / nw);
-  tiles_per_group = std::max(ts, (ntiles + target - 1) / target);
+  resident = std::max(1, resident);
+  tiles_per_group = std::max(ts, (ntiles + resident - 1) / resident);
   tiles_per_group = (tiles_per_group + ts - 1) / ts * ts;
   groups = (ntiles + tiles_per_group - 1) / tiles_per_group;
 }
@@ -1246,11 +1264,29 @@ template <class F>
 struct Family {
   static constexpr size_t lds_in64 = (size_t)F::I * kLanes * 8;
   static constexpr size_t lds_in32 = (size_t)F::I * kLanes * 4;
+  // resident workgroups of each matrix-core kernel (queried once)
+  static int res_sweep() {
+    static const int r = resident_groups(k_sweep_mfma<F, true>, 64 * Tiling64<F::S, F::I>::NW);
+    return r;
+  }
+  static int res_step() {
+    static const int r = resident_groups(k_step_mfma<F>, 64 * StepTiling<F>::value);
+    return r;
+  }
+  static int res_inner32() {
+    static const int r = resident_groups(k_inner32_mfma<F>, 64 * Tiling64<F::S, F::I>::NW);
+    return r;
+  }
+  template <class LD, class ST>
+  static int res_refine() {
+    static const int r = resident_groups(k_refine_mfma<F, LD, ST>, 64 * Tiling64<F::S, F::I>::NW);
+    return r;
+  }
   static void sweep64(const DevProblem& dp, double tol, hipStream_t st) {
     using TL = Tiling64<F::S, F::I>;
     const ResidArgs ra = resid_args(dp, tol, tol >= 0.0 ? 1 : 0);
     int tpg, groups;
-    mfma_groups(dp.mesh.nel, TL::NW, TL::TS, tpg, groups);
+    mfma_groups(dp.mesh.nel, TL::TS, res_sweep(), tpg, groups);
     hipLaunchKernelGGL((k_sweep_mfma<F, true>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh,
                        Ld64{dp.s[0], (size_t)dp.mesh.nel}, (const double*)dp.g, dp.Tf64, (double*)nullptr, ra,
                        dp.s[0], dp.s[1], tpg);
@@ -1274,11 +1310,11 @@ struct Family {
   }
   static void sweep_groups(int nel, int* tpg, int* groups) {
     using TL = Tiling64<F::S, F::I>;
-    mfma_groups(nel, TL::NW, TL::TS, *tpg, *groups);
+    mfma_groups(nel, TL::TS, res_sweep(), *tpg, *groups);
   }
   static void step_groups(int nel, int* tpg, int* groups) {
     using TL = typename StepTiling<F>::TL;
-    mfma_groups(nel, TL::NW, TL::TS, *tpg, *groups);
+    mfma_groups(nel, TL::TS, res_step(), *tpg, *groups);
   }
   static void sweep64_batch(const BatchEntry* table, int n, const BatchProblem* probs, double tol, hipStream_t st) {
     using TL = Tiling64<F::S, F::I>;
@@ -1294,7 +1330,7 @@ struct Family {
   static void step(const DevProblem& dp, int lag, hipStream_t st) {
     using TL = typename StepTiling<F>::TL;
     int tpg, groups;
-    mfma_groups(dp.mesh.nel, TL::NW, TL::TS, tpg, groups);
+    mfma_groups(dp.mesh.nel, TL::TS, res_step(), tpg, groups);
     hipLaunchKernelGGL((k_step_mfma<F>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, dp.s[0], dp.s[1],
                        dp.Mf64, dp.u2[0], dp.u2[1], (const double*)(dp.has_src ? dp.w_src : nullptr),
                        (const double*)(dp.has_src ? dp.gbe : nullptr), dp.g, dp.ctrl, dp.counters + kCounterSet,
@@ -1313,14 +1349,14 @@ struct Family {
     using TL = Tiling64<F::S, F::I>;
     const ResidArgs ra = resid_args(dp, tol, 1);
     int tpg, groups;
-    mfma_groups(dp.mesh.nel, TL::NW, TL::TS, tpg, groups);
+    mfma_groups(dp.mesh.nel, TL::TS, res_refine<LD, ST>(), tpg, groups);
     hipLaunchKernelGGL((k_refine_mfma<F, LD, ST>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, ld,
                        (const double*)dp.g, dp.Tf64, dp.s[0], dp.s[1], store, ra, tpg);
   }
   static void inner32(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
     using TL = Tiling64<F::S, F::I>;
     int tpg, groups;
-    mfma_groups(dp.mesh.nel, TL::NW, TL::TS, tpg, groups);
+    mfma_groups(dp.mesh.nel, TL::TS, res_inner32(), tpg, groups);
     hipLaunchKernelGGL((k_inner32_mfma<F>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh,
                        Ld32{(const float*)lo_in, (size_t)dp.mesh.nel}, (const float*)r_lo, dp.Tf32,
                        (float*)lo_out, (const Ctrl*)dp.ctrl, tpg);
