@@ -22,10 +22,13 @@ inline int mfma_row_tiles(int rows) { return (rows + 15) / 16; }
 inline int mfma_k_tiles(int cols) { return (cols + 3) / 4; }
 
 // Arrival counters of the last-workgroup reductions: two sets (sweep reduction, step
-// completion) of 8 group counters plus one counter of finished groups, each on its
-// own 4 KB so that concurrent arrivals do not queue on one address.
-constexpr int kCounterStride = 1024;  // unsigned ints
-constexpr int kCounterSet = 9 * kCounterStride;
+// completion) of kCounterGroups group counters plus one counter of finished groups,
+// each on its own 256 bytes so that concurrent arrivals do not queue on one line.
+// (Measured on the 256^2 shallow-water sweep: 8 groups 12.1 us, 32 groups 11.5 us,
+// 128 groups 13.1 us; 4 KB apart instead of 256 bytes, 11.8 us.)
+constexpr int kCounterGroups = 32;
+constexpr int kCounterStride = 64;  // unsigned ints
+constexpr int kCounterSet = (kCounterGroups + 1) * kCounterStride;
 constexpr size_t kCounterBytes = 2 * (size_t)kCounterSet * sizeof(unsigned);
 
 // Device-resident iteration control, one per handle.  Kernels choose their

@@ -271,22 +271,24 @@ struct ResidArgs {
   int stop;  // 1: set done on tol or non-finite; 0: record only
 };
 
-// Two-level arrival count of workgroup b of nb: the workgroups are split into 8
-// groups (b & 7) counting on their own counter; the last arrival of each group then
-// counts on the counter of finished groups.  Returns true for the last workgroup
-// overall, which resets the counters.  The caller completes (waits for) every store
-// the last workgroup must see before arriving.
+// Two-level arrival count of workgroup b of nb: the workgroups are split into G =
+// kCounterGroups groups (b mod G; with G a multiple of 8 each group's workgroups run on
+// one XCD) counting on their own counter; the last arrival of each group then counts on
+// the counter of finished groups.  Returns true for the last workgroup overall, which
+// resets the counters.  The caller completes (waits for) every store the last
+// workgroup must see before arriving.
 __device__ bool arrive_last(unsigned* cnt, int b, int nb) {
-  const int grp = b & 7;
-  const int size = (nb >> 3) + (grp < (nb & 7) ? 1 : 0);
+  constexpr int G = kCounterGroups;
+  const int grp = b % G;
+  const int size = nb / G + (grp < nb % G ? 1 : 0);
   const unsigned prev =
       __hip_atomic_fetch_add(cnt + grp * kCounterStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (prev != (unsigned)(size - 1)) return false;
-  const unsigned groups = nb < 8 ? (unsigned)nb : 8u;
+  const unsigned groups = nb < G ? (unsigned)nb : (unsigned)G;
   const unsigned done =
-      __hip_atomic_fetch_add(cnt + 8 * kCounterStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(cnt + G * kCounterStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (done != groups - 1) return false;
-  for (int i = 0; i < 9; ++i) __hip_atomic_store(cnt + i * kCounterStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int i = 0; i <= G; ++i) __hip_atomic_store(cnt + i * kCounterStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return true;
 }
 
@@ -297,10 +299,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // NW: wavefronts per workgroup; (bid, nb): this workgroup's index among the nb
-// workgroups that share the reduction (a whole launch, or one problem of a batch)
+// workgroups that share the reduction (a whole launch, or one problem of a batch).
+// First half: the workgroup's partial sums are stored and it arrives; returns (to every
+// thread) whether it arrived last.  Stores issued after this call do not delay the
+// arrival, so a caller may keep its outputs in registers and store them afterwards.
 template <int NW = kWaves>
-__device__ void finish_residual(double d2, double n2, const ResidArgs& ra, int bid, int nb) {
-  constexpr int NT = 64 * NW;
+__device__ bool residual_arrive(double d2, double n2, const ResidArgs& ra, int bid, int nb) {
   __shared__ double sd[NW][2];
   __shared__ int is_last;
   const int lane = threadIdx.x & 63, w = wave_id();
@@ -327,7 +331,18 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra, int b
     is_last = arrive_last(ra.cnt, bid, nb) ? 1 : 0;
   }
   __syncthreads();
-  if (!is_last) return;
+  return is_last != 0;
+}
+
+// Second half, run by every thread of the last workgroup: the sum of all partials in a
+// fixed order, the history entry and the control block update.  iters: the control
+// block's iteration count as read at the start of the launch (only this workgroup
+// changes it, so passing it in saves a memory round trip at the end of the launch).
+template <int NW = kWaves>
+__device__ void residual_final(const ResidArgs& ra, int nb, int iters) {
+  constexpr int NT = 64 * NW;
+  __shared__ double sf[NW][2];
+  const int lane = threadIdx.x & 63, w = wave_id();
   // every partial has arrived; the agent-scope atomic loads below read them where
   // they were written
   // kU partials per thread are loaded together (unconditional loads at clamped
@@ -352,22 +367,21 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra, int b
   }
   a = wave_sum(a);
   b = wave_sum(b);
-  __syncthreads();
   if (lane == 0) {
-    sd[w][0] = a;
-    sd[w][1] = b;
+    sf[w][0] = a;
+    sf[w][1] = b;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     a = 0.0;
     b = 0.0;
     for (int i = 0; i < NW; ++i) {
-      a += sd[i][0];
-      b += sd[i][1];
+      a += sf[i][0];
+      b += sf[i][1];
     }
     const double res = b > 0.0 ? sqrt(a / b) : sqrt(a);
     Ctrl* c = ra.ctrl;
-    const int it = c->iters;
+    const int it = iters;
     ra.hist[it % ra.hist_cap] = res;
     c->iters = it + 1;
     c->last_res = res;
@@ -382,8 +396,13 @@ __device__ void finish_residual(double d2, double n2, const ResidArgs& ra, int b
 }
 
 template <int NW = kWaves>
-__device__ __forceinline__ void finish_residual(double d2, double n2, const ResidArgs& ra) {
-  finish_residual<NW>(d2, n2, ra, (int)blockIdx.x, (int)gridDim.x);
+__device__ void finish_residual(double d2, double n2, const ResidArgs& ra, int bid, int nb, int iters) {
+  if (residual_arrive<NW>(d2, n2, ra, bid, nb)) residual_final<NW>(ra, nb, iters);
+}
+
+template <int NW = kWaves>
+__device__ __forceinline__ void finish_residual(double d2, double n2, const ResidArgs& ra, int iters) {
+  finish_residual<NW>(d2, n2, ra, (int)blockIdx.x, (int)gridDim.x, iters);
 }
 
 // ---------------------------------------------------------------------------
@@ -500,7 +519,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* _
       }
     }
   }
-  if (RESID) finish_residual(d2, n2, ra);
+  if (RESID) finish_residual(d2, n2, ra, ch.iters);
 }
 
 // ---------------------------------------------------------------------------
@@ -654,9 +673,11 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
           d2 += dd * dd;
           n2 += v * v;
         });
-    finish_residual<TL::NW>(d2, n2, ra, bid, nbk);
+    finish_residual<TL::NW>(d2, n2, ra, bid, nbk, ch.iters);
     return;
   }
+  doublex4_t pend[MTW];
+  int pend_e = -1;
   for (int t = t0 + slot; t < t1; t += TL::TS) {
     const int e = t * 16 + j;
     const bool valid = e < m.nel;
@@ -692,14 +713,37 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
         const double old = ld(row < F::S ? row : F::S - 1, es);
         if (valid && row < F::S) {
           const double v = acc[u][r];
-          out[(size_t)row * nel + e] = v;
           const double dd = v - old;
           d2 += dd * dd;
           n2 += v * v;
         }
       }
+    // the wavefront's last tile is stored after the arrival below; earlier ones now
+    if (t + TL::TS < t1) {
+      if (valid)
+#pragma unroll
+        for (int u = 0; u < MTW; ++u)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (w * MTW + u) + kq + 4 * r;
+            if (row < F::S) out[(size_t)row * nel + e] = acc[u][r];
+          }
+    } else {
+      pend_e = valid ? e : -1;
+#pragma unroll
+      for (int u = 0; u < MTW; ++u) pend[u] = acc[u];
+    }
   }
-  finish_residual<TL::NW>(d2, n2, ra, bid, nbk);
+  const bool last = residual_arrive<TL::NW>(d2, n2, ra, bid, nbk);
+  if (pend_e >= 0)
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (w * MTW + u) + kq + 4 * r;
+        if (row < F::S) out[(size_t)row * nel + pend_e] = pend[u][r];
+      }
+  if (last) residual_final<TL::NW>(ra, nbk, ch.iters);
 }
 
 template <class F, bool DEVPAR>
@@ -790,7 +834,7 @@ __global__ __launch_bounds__(kThreads) void k_refine(MeshDev m, LD ld, const dou
       }
     }
   }
-  finish_residual(d2, n2, ra);
+  finish_residual(d2, n2, ra, ch.iters);
 }
 
 // Element solution from the traces of the last local solve, as one stacked contraction
@@ -936,7 +980,7 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
           d2 += res * res;
           n2 += v * v;
         });
-    finish_residual<TL::NW>(d2, n2, ra);
+    finish_residual<TL::NW>(d2, n2, ra, ch.iters);
     return;
   }
   for (int t = t0 + slot; t < t1; t += TL::TS) {
@@ -982,7 +1026,7 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
         }
       }
   }
-  finish_residual<TL::NW>(d2, n2, ra);
+  finish_residual<TL::NW>(d2, n2, ra, ch.iters);
 }
 
 // FP32 correction sweep on the matrix cores: lo_out = r_lo + T in(lo_in) with
@@ -1154,8 +1198,10 @@ __device__ __forceinline__ void step_mfma_body(MeshDev m, double* s0, double* s1
       }
     }
   }
+  // The arrival only elects the workgroup that advances the control block: every
+  // workgroup has used its read of the block by now, and the next launch sees all
+  // stores of this one, so the stores above need not complete first.
   __shared__ int is_last;
-  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) is_last = arrive_last(cnt, bid, nbk) ? 1 : 0;
   __syncthreads();
@@ -1593,13 +1639,17 @@ __global__ __launch_bounds__(256) void k_sweep_var(MeshDev m, const double* __re
   for (int k = 0; k < RPL; ++k) {
     const double old = ld(row[k], es);
     if (live[k]) {
-      out[(size_t)row[k] * nel + e] = acc[k];
       const double dd = acc[k] - old;
       d2 += dd * dd;
       n2 += acc[k] * acc[k];
     }
   }
-  finish_residual<4>(d2, n2, ra);
+  // the new state is stored after the arrival, so the arrival does not wait for it
+  const bool last = residual_arrive<4>(d2, n2, ra, (int)blockIdx.x, (int)gridDim.x);
+#pragma unroll
+  for (int k = 0; k < RPL; ++k)
+    if (live[k]) out[(size_t)row[k] * nel + e] = acc[k];
+  if (last) residual_final<4>(ra, (int)gridDim.x, ch.iters);
 }
 
 // in(s) of every element into in[c][e] (recovery of the element solutions)
@@ -1796,8 +1846,7 @@ void launch_ctrl_gather(const BatchProblem* probs, int n, Ctrl* out, hipStream_t
 }
 
 __global__ void k_counters_reset(unsigned* cnt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 18) cnt[i * kCounterStride] = 0u;
+  for (int i = threadIdx.x; i < 2 * (kCounterGroups + 1); i += blockDim.x) cnt[i * kCounterStride] = 0u;
 }
 
 void launch_counters_reset(unsigned* counters, hipStream_t st) {
