@@ -37,6 +37,7 @@ struct ehdg_problem {
   int recovered = -1;     // 1 when u2[ucur ^ 1] holds the solution of the current iterate
   int predict = 4;        // sweeps the next solve / step is expected to need
   int predict_outer = 2;  // refinements the next mixed-precision solve / step is expected to need
+  unsigned seq = 0;       // launch number of the last FP64 sweep queued (the sweeps' lagged tests)
   std::string err;
 };
 
@@ -104,7 +105,8 @@ Layout layout_for(const Operators& o, long long nel, bool lowp, bool var = false
   const size_t Sp = (size_t)padded_rows(o.S);
   L.off_ctrl = take(sizeof(Ctrl));
   L.off_counters = take(kCounterBytes);
-  L.off_partials = take(2 * nb * sizeof(double));
+  // two sets of one (d2, n2) pair per workgroup (FP64 sweeps alternate between them)
+  L.off_partials = take(2 * 2 * nb * sizeof(double));
   L.off_hist = take(kHistCap * sizeof(double));
   L.off_steps = take(kStepCap * sizeof(int));
   L.off_T64 = take(Sp * I * 8);
@@ -211,7 +213,7 @@ struct Outer {
   void queue(double tol) {
     DevProblem& dp = h->dp;
     if (!mixed(h)) {
-      h->ks->sweep64(dp, tol, h->stream);
+      h->ks->sweep64(dp, tol, ++h->seq, h->stream);
       return;
     }
     const bool bf = h->desc.precision == EHDG_BF16_REFINE;
@@ -244,6 +246,8 @@ int run_segment(ehdg_problem* h, double tol, int max_outer) {
     const int n = std::min(chunk, max_outer - launched);
     for (int j = 0; j < n; ++j) o.queue(tol);
     launched += n;
+    // FP64 sweeps leave their own stopping test to the next launch: take the last one
+    if (!mixed(h)) launch_reduce_lagged(h->dp, tol, h->seq + 1, h->stream);
     int rc = check_launch(h);
     if (rc) return rc;
     rc = sync_ctrl(h);
@@ -347,6 +351,18 @@ static int setup_impl(const ehdg_desc* desc, const VarSamples* smp, void* d_work
   dp.ctrl = (Ctrl*)(ws + L.off_ctrl);
   dp.counters = (unsigned*)(ws + L.off_counters);
   dp.partials = (double*)(ws + L.off_partials);
+  dp.partial_stride = (int)((L.off_hist - L.off_partials) / sizeof(double) / 2);
+  if (h->ks->sweep_groups) {
+    int tpg = 0, groups = 0;
+    h->ks->sweep_groups((int)nel, &tpg, &groups);
+    dp.nb_sweep = groups;
+  } else {
+    dp.nb_sweep = (int)var_sweep_groups(nel, o.S);
+  }
+  if (2 * (long long)dp.nb_sweep > dp.partial_stride) {
+    delete h;
+    return EHDG_ERR_INVALID_ARG;
+  }
   dp.hist = (double*)(ws + L.off_hist);
   dp.hist_cap = kHistCap;
   dp.step_iters = (int*)(ws + L.off_steps);
@@ -422,7 +438,7 @@ static int setup_impl(const ehdg_desc* desc, const VarSamples* smp, void* d_work
   launch_fill_bytes(dp.partials, L.off_hist - L.off_partials, h->stream);
   launch_fill(dp.hist, 0.0, kHistCap, h->stream);
   launch_fill_bytes(dp.step_iters, kStepCap * sizeof(int), h->stream);
-  launch_ctrl_reset(dp.ctrl, 1, h->stream);
+  launch_ctrl_reset(dp.ctrl, 1, h->seq + 1, h->stream);
   // the host buffers above are pageable: the copies complete before this returns
   rc = sync_ctrl(h);
   if (!rc) rc = ehdg_set_forcing(h, nullptr, nullptr);
@@ -500,7 +516,7 @@ int ehdg_set_initial(ehdg_handle h, const double* d_u0) {
   if (!h) return EHDG_ERR_INVALID_ARG;
   DevProblem& dp = h->dp;
   const int nel = dp.mesh.nel;
-  launch_ctrl_reset(dp.ctrl, 1, h->stream);
+  launch_ctrl_reset(dp.ctrl, 1, h->seq + 1, h->stream);
   h->mirror.base = 0;
   h->mirror.ucur = 0;
   h->mirror.iters = 0;
@@ -520,8 +536,10 @@ int ehdg_iterate(ehdg_handle h, int32_t n_iters) {
   if (!h || n_iters < 0) return EHDG_ERR_INVALID_ARG;
   if (mixed(h)) return fail(h, EHDG_ERR_UNSUPPORTED, "iterate runs the FP64 sweep");
   // a finished solve is continued in a new segment from its last iterate (on the device)
-  launch_ctrl_reset(h->dp.ctrl, 2, h->stream);
-  for (int j = 0; j < n_iters; ++j) h->ks->sweep64(h->dp, -1.0, h->stream);
+  launch_ctrl_reset(h->dp.ctrl, 2, h->seq + 1, h->stream);
+  for (int j = 0; j < n_iters; ++j) h->ks->sweep64(h->dp, -1.0, ++h->seq, h->stream);
+  // the last sweep's increment is recorded by the next launch: take it now
+  if (n_iters > 0) launch_reduce_lagged(h->dp, -1.0, h->seq + 1, h->stream);
   h->recovered = -1;
   return check_launch(h);
 }
@@ -529,7 +547,7 @@ int ehdg_iterate(ehdg_handle h, int32_t n_iters) {
 int ehdg_solve(ehdg_handle h, double rel_tol, int32_t max_iters, int32_t* iters, double* rel_res) {
   if (!h || max_iters < 1 || !(rel_tol >= 0.0)) return EHDG_ERR_INVALID_ARG;
   DevProblem& dp = h->dp;
-  launch_ctrl_reset(dp.ctrl, 0, h->stream);  // a new segment from the latest state
+  launch_ctrl_reset(dp.ctrl, 0, h->seq + 1, h->stream);  // a new segment from the latest state
   const int s = mixed(h) ? h->desc.inner_sweeps : 1;
   const int max_outer = std::max(1, (max_iters + s - 1) / s);
   int rc = run_segment(h, rel_tol, max_outer);
@@ -560,7 +578,7 @@ int ehdg_step(ehdg_handle h, int32_t n_steps, double rel_tol, int32_t max_iters_
   const int max_outer = std::max(1, (max_iters_per_step + s - 1) / s);
   int& pred = mixed(h) ? h->predict_outer : h->predict;
   // the first step continues from the latest state of whatever ran before
-  launch_ctrl_reset(dp.ctrl, 0, h->stream);
+  launch_ctrl_reset(dp.ctrl, 0, h->seq + 1, h->stream);
   int rc = sync_ctrl(h);
   if (rc) return rc;
   const int first = h->mirror.steps_done, target = first + n_steps;
@@ -575,7 +593,7 @@ int ehdg_step(ehdg_handle h, int32_t n_steps, double rel_tol, int32_t max_iters_
     const int per = std::min(std::max(1, pred) + 1, max_outer);
     for (int r = 0; r < remaining; ++r) {
       for (int j = 0; j < per; ++j) o.queue(rel_tol);
-      h->ks->step(dp, lag, h->stream);
+      h->ks->step(dp, lag, h->seq + 1, rel_tol, mixed(h) ? 0 : 1, h->stream);
     }
     rc = check_launch(h);
     if (rc) return rc;

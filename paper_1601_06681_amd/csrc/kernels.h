@@ -38,10 +38,10 @@ constexpr size_t kCounterBytes = 2 * (size_t)kCounterSet * sizeof(unsigned);
 struct Ctrl {
   // the first four fields are read together by every sweep (one 16-byte load)
   int done;           // set once the stopping test holds (or the increment is non-finite)
-  int iters;          // sweeps (or refinements) of the current segment
+  int iters;          // sweeps (or refinements) of the current segment whose increment is known
   int base;           // state buffer holding s^0 of the current segment
   int status;         // 0 running, 1 converged, 2 non-finite increment
-  unsigned unused0;
+  unsigned seg_seq;   // FP64 sweeps: launch number of the sweep before the segment's first
   int ucur;           // solution buffer holding the current time level
   int steps_done;     // backward-Euler steps completed since the last initial state
   unsigned unused1;
@@ -85,7 +85,9 @@ struct DevProblem {
   int step_cap;
   void* lo[2];             // low-precision correction, double buffered (S)
   void* rlo[2];            // low-precision residual, double buffered (S)
-  double* partials;        // 2 per block
+  double* partials;        // per workgroup (d2, n2); FP64 sweeps: two sets, partial_stride apart
+  int partial_stride;      // doubles between the two sets
+  int nb_sweep;            // workgroups of one FP64 sweep launch
   Ctrl* ctrl;
   unsigned* counters;      // kCounterBytes: arrival counters (zero between launches)
   double* hist;            // residual ring
@@ -128,16 +130,21 @@ struct BatchEntry {
 
 // Kernels of one (pde, dim, active axes, face nodes) family.
 struct KernelSet {
-  // one FP64 sweep s^{k+1} = g + T in(s^k), buffers from the control block, with the
-  // relative-increment reduction (tol < 0: record only, never stop)
-  void (*sweep64)(const DevProblem&, double tol, hipStream_t);
+  // one FP64 sweep s^{k+1} = g + T in(s^k), launch number seq (the host numbers every
+  // sweep of a handle), buffers from the control block and seq.  The stopping test of
+  // the previous sweep is taken at the start (tol < 0: record only, never stop); this
+  // sweep's own increment is left as partial sums for the next launch (or
+  // launch_reduce_lagged)
+  void (*sweep64)(const DevProblem&, double tol, unsigned seq, hipStream_t);
   // element solution u_out = w_src + R in(s_prev) (+ P u_old for BE); no control change
   void (*volume)(const DevProblem&, const double* s_prev, const double* u_old, double* u_out, hipStream_t);
   // backward-Euler step completion, queued after a step's sweeps: if the step has
   // converged, u[ucur^1] = solution of the last local solve (lag 1: it read
   // s^{K-1}; lag 0: refinement, it reads s^K), next g, and the control block
-  // advances to the next step; otherwise nothing happens
-  void (*step)(const DevProblem&, int lag, hipStream_t);
+  // advances to the next step; otherwise nothing happens.  lagged (FP64 sweeps): the
+  // last sweep's increment is still pending and is tested here against tol; seq_next
+  // is the launch number the next sweep will get
+  void (*step)(const DevProblem&, int lag, unsigned seq_next, double tol, int lagged, hipStream_t);
   // mixed precision outer step: s' = s^k + lo_in (lo_in ignored on the segment's
   // first refinement); r = g + T in(s') - s' in FP64 into r_out (low precision);
   // s' stored as s^{k+1}; reduction of ||r|| / ||s' + r||
@@ -186,8 +193,12 @@ void launch_fill_bytes(void* p, size_t bytes, hipStream_t st);
 // transport boundary inputs: in_bc[c][e] (I rows) from the compact side layout
 void launch_bc_inputs(const DevProblem& dp, const double* bc, double* in_bc, hipStream_t st);
 // full = 1: everything (new initial state); full = 0: start a new segment from the
-// latest state; full = 2: the same, but only if the current segment has finished
-void launch_ctrl_reset(Ctrl* c, int full, hipStream_t st);
+// latest state; full = 2: the same, but only if the current segment has finished.
+// seq_next: the launch number of the next FP64 sweep
+void launch_ctrl_reset(Ctrl* c, int full, unsigned seq_next, hipStream_t st);
+// the stopping test of the last FP64 sweep before launch number seq (its increment
+// pending as partial sums), as the sweep launched as seq would take it
+void launch_reduce_lagged(const DevProblem& dp, double tol, unsigned seq, hipStream_t st);
 void launch_counters_reset(unsigned* counters, hipStream_t st);
 // the same reset for every problem of a batch, and a copy of their control blocks into out[n]
 void launch_ctrl_reset_batch(const BatchProblem* probs, int n, int full, hipStream_t st);

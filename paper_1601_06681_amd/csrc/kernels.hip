@@ -298,15 +298,82 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// NW: wavefronts per workgroup; (bid, nb): this workgroup's index among the nb
-// workgroups that share the reduction (a whole launch, or one problem of a batch).
-// First half: the workgroup's partial sums are stored and it arrives; returns (to every
-// thread) whether it arrived last.  Stores issued after this call do not delay the
-// arrival, so a caller may keep its outputs in registers and store them afterwards.
-template <int NW = kWaves>
-__device__ bool residual_arrive(double d2, double n2, const ResidArgs& ra, int bid, int nb) {
+// The sum of nb partial pairs (d2, n2) at p in one canonical order, independent of the
+// kernel and of its workgroup size: virtual lane v (0..255) adds pairs v, v + 256, v +
+// 512, ... in turn; the lanes of virtual wavefront q (lanes 64q .. 64q + 63) are summed by
+// a shuffle tree (lane 0's result); the four wavefront sums are added in order q = 0..3.
+// Wavefront w of an NW-wavefront workgroup takes virtual wavefronts w, w + NW, ... and
+// leaves their sums in sq[q]; after a barrier, canonical_total() gives every thread the
+// same bits.  ATOMIC: agent-scope loads (partials of the same launch).
+constexpr int kVirtLanes = 256;
+template <int NW, bool ATOMIC>
+__device__ __forceinline__ void canonical_sums(const double* __restrict__ p, int nb, double (*sq)[2]) {
+  const int lane = threadIdx.x & 63, w = wave_id();
+  constexpr int kU = 4;
+#pragma unroll
+  for (int q = w; q < kVirtLanes / 64; q += NW) {
+    const int v = 64 * q + lane;
+    double a = 0.0, b = 0.0;
+    for (int i0 = v; i0 < nb; i0 += kVirtLanes * kU) {
+      double pa[kU], pb[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = i0 + kVirtLanes * u;
+        const int ic = i < nb ? i : nb - 1;
+        if constexpr (ATOMIC) {
+          pa[u] = __hip_atomic_load(&p[2 * ic], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          pb[u] = __hip_atomic_load(&p[2 * ic + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          pa[u] = p[2 * ic];
+          pb[u] = p[2 * ic + 1];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const bool in = i0 + kVirtLanes * u < nb;
+        a += in ? pa[u] : 0.0;
+        b += in ? pb[u] : 0.0;
+      }
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+      sq[q][0] = a;
+      sq[q][1] = b;
+    }
+  }
+}
+__device__ __forceinline__ double canonical_total(const double (*sq)[2], double& b) {
+  b = ((sq[0][1] + sq[1][1]) + sq[2][1]) + sq[3][1];
+  return ((sq[0][0] + sq[1][0]) + sq[2][0]) + sq[3][0];
+}
+__device__ __forceinline__ double relative_increment(double a, double b) { return b > 0.0 ? sqrt(a / b) : sqrt(a); }
+
+// Control block update for the stopping test of sweep number `it` (1-based) of the
+// segment with relative increment res.  Returns whether the segment stops.
+__device__ __forceinline__ bool stop_test(double res, double tol, int stop) {
+  return isfinite(res) ? (stop && res < tol) : (stop != 0);
+}
+__device__ __forceinline__ void record_test(Ctrl* c, double* hist, int hist_cap, int it, double res, double tol,
+                                            int stop) {
+  hist[(it - 1) % hist_cap] = res;
+  c->iters = it;
+  c->last_res = res;
+  if (!isfinite(res)) {
+    c->status = 2;
+    if (stop) c->done = 1;
+  } else if (stop && res < tol) {
+    c->status = 1;
+    c->done = 1;
+  }
+}
+
+// Block sum of (d2, n2) over an NW-wavefront workgroup (lane 0 of each wavefront, then
+// the wavefronts in order): the value every reduction of this library stores as the
+// workgroup's partial.  Valid in thread 0 after the call (which contains a barrier).
+template <int NW>
+__device__ __forceinline__ void block_pair(double& d2, double& n2) {
   __shared__ double sd[NW][2];
-  __shared__ int is_last;
   const int lane = threadIdx.x & 63, w = wave_id();
   d2 = wave_sum(d2);
   n2 = wave_sum(n2);
@@ -321,6 +388,22 @@ __device__ bool residual_arrive(double d2, double n2, const ResidArgs& ra, int b
       a += sd[i][0];
       b += sd[i][1];
     }
+    d2 = a;
+    n2 = b;
+  }
+}
+
+// NW: wavefronts per workgroup; (bid, nb): this workgroup's index among the nb
+// workgroups that share the reduction (a whole launch, or one problem of a batch).
+// First half: the workgroup's partial sums are stored and it arrives; returns (to every
+// thread) whether it arrived last.  Stores issued after this call do not delay the
+// arrival, so a caller may keep its outputs in registers and store them afterwards.
+template <int NW = kWaves>
+__device__ bool residual_arrive(double d2, double n2, const ResidArgs& ra, int bid, int nb) {
+  __shared__ int is_last;
+  block_pair<NW>(d2, n2);
+  if (threadIdx.x == 0) {
+    const double a = d2, b = n2;
     // The partials are agent-scope atomic stores (written through to the level where
     // all XCDs see them).  Waiting for their completion before the arrival is counted
     // orders them before it, without a device-wide release fence: such a fence writes
@@ -334,64 +417,20 @@ __device__ bool residual_arrive(double d2, double n2, const ResidArgs& ra, int b
   return is_last != 0;
 }
 
-// Second half, run by every thread of the last workgroup: the sum of all partials in a
-// fixed order, the history entry and the control block update.  iters: the control
+// Second half, run by every thread of the last workgroup: the sum of all partials in the
+// canonical order (every partial has arrived; the agent-scope loads read them where they
+// were written), the history entry and the control block update.  iters: the control
 // block's iteration count as read at the start of the launch (only this workgroup
 // changes it, so passing it in saves a memory round trip at the end of the launch).
 template <int NW = kWaves>
 __device__ void residual_final(const ResidArgs& ra, int nb, int iters) {
-  constexpr int NT = 64 * NW;
-  __shared__ double sf[NW][2];
-  const int lane = threadIdx.x & 63, w = wave_id();
-  // every partial has arrived; the agent-scope atomic loads below read them where
-  // they were written
-  // kU partials per thread are loaded together (unconditional loads at clamped
-  // indices, so all are in flight at once), then summed in a fixed order
-  constexpr int kU = 8;
-  double a = 0.0, b = 0.0;
-  for (int i0 = threadIdx.x; i0 < nb; i0 += NT * kU) {
-    double pa[kU], pb[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int i = i0 + u * NT;
-      const int ic = i < nb ? i : nb - 1;
-      pa[u] = __hip_atomic_load(&ra.partials[2 * ic], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      pb[u] = __hip_atomic_load(&ra.partials[2 * ic + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const bool in = i0 + u * NT < nb;
-      a += in ? pa[u] : 0.0;
-      b += in ? pb[u] : 0.0;
-    }
-  }
-  a = wave_sum(a);
-  b = wave_sum(b);
-  if (lane == 0) {
-    sf[w][0] = a;
-    sf[w][1] = b;
-  }
+  __shared__ double sq[kVirtLanes / 64][2];
+  canonical_sums<NW, true>(ra.partials, nb, sq);
   __syncthreads();
   if (threadIdx.x == 0) {
-    a = 0.0;
-    b = 0.0;
-    for (int i = 0; i < NW; ++i) {
-      a += sf[i][0];
-      b += sf[i][1];
-    }
-    const double res = b > 0.0 ? sqrt(a / b) : sqrt(a);
-    Ctrl* c = ra.ctrl;
-    const int it = iters;
-    ra.hist[it % ra.hist_cap] = res;
-    c->iters = it + 1;
-    c->last_res = res;
-    if (!isfinite(res)) {
-      c->status = 2;
-      if (ra.stop) c->done = 1;
-    } else if (ra.stop && res < ra.tol) {
-      c->status = 1;
-      c->done = 1;
-    }
+    double b;
+    const double a = canonical_total(sq, b);
+    record_test(ra.ctrl, ra.hist, ra.hist_cap, iters + 1, relative_increment(a, b), ra.tol, ra.stop);
   }
 }
 
@@ -632,13 +671,63 @@ struct SweepWaves {  // wavefronts per workgroup of the matrix-core sweep
   static constexpr int value = Tiling64<F::S, F::I>::NW;
 };
 
-template <class F, bool DEVPAR>
+// Lagged stopping test (LAGGED; single-problem FP64 sweeps).  The host numbers the
+// sweeps of a handle (seq); the control block holds the number of the sweep before the
+// segment's first (seg_seq), so this sweep is number k = seq - seg_seq of its segment.
+// It leaves its own increment as per-workgroup partial sums in set seq & 1 and takes
+// the stopping test of sweep k - 1 from set (seq - 1) & 1 before it writes anything:
+// every workgroup sums the partials in the canonical order and reaches the same
+// decision; workgroup 0 records it.  No workgroup waits for another, so the launch has
+// no arrival and no last-workgroup tail.  Without LAGGED (batched launches) the last
+// workgroup to arrive takes the test of this sweep, as before.
+struct LagArgs {
+  unsigned seq;     // this launch's sweep number
+  int stride;       // doubles between the two partial sets
+};
+
+// Start of a lagged sweep, all threads: the previous sweep's partials are summed (their
+// loads overlap the control block's), the control block's done flag is made uniform
+// across the workgroup, and the stopping test of sweep k - 1 is taken.  Returns k (> 0),
+// or 0 if the segment has stopped (then the caller writes nothing).
+template <int NW>
+__device__ __forceinline__ int lagged_begin(const ResidArgs& ra, const LagArgs& lag, int nb, int bid,
+                                            const CtrlHead& ch, unsigned seg) {
+  __shared__ double sq[kVirtLanes / 64][2];
+  __shared__ int s_done;
+  canonical_sums<NW, false>(ra.partials + (size_t)((lag.seq - 1u) & 1u) * lag.stride, nb, sq);
+  if (threadIdx.x == 0) s_done = ch.done;
+  __syncthreads();
+  if (s_done) return 0;
+  const int k = (int)(lag.seq - seg);
+  if (k >= 2) {
+    double b;
+    const double res = relative_increment(canonical_total(sq, b), b);
+    if (bid == 0 && threadIdx.x == 0) record_test(ra.ctrl, ra.hist, ra.hist_cap, k - 1, res, ra.tol, ra.stop);
+    if (stop_test(res, ra.tol, ra.stop)) return 0;
+  }
+  return k;
+}
+
+// End of a lagged sweep, all threads: the workgroup's partial sums into set seq & 1.
+template <int NW>
+__device__ __forceinline__ void lagged_end(double d2, double n2, const ResidArgs& ra, const LagArgs& lag, int bid) {
+  block_pair<NW>(d2, n2);
+  if (threadIdx.x == 0) {
+    double* p = ra.partials + (size_t)(lag.seq & 1u) * lag.stride;
+    p[2 * bid] = d2;
+    p[2 * bid + 1] = n2;
+  }
+}
+
+template <class F, bool DEVPAR, bool LAGGED>
 __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double* __restrict__ g,
                                                 const double* __restrict__ Tf, double* out, const ResidArgs& ra,
-                                                double* s0, double* s1, int tiles_per_group, int bid, int nbk) {
+                                                double* s0, double* s1, int tiles_per_group, int bid, int nbk,
+                                                LagArgs lag) {
   using TL = Tiling64<F::S, F::I>;
   constexpr int MTW = TL::MTW, KT = TL::KT;
   const CtrlHead ch = ctrl_head(ra.ctrl);
+  const unsigned seg = LAGGED ? ra.ctrl->seg_seq : 0u;
   const int lane = threadIdx.x & 63, wave = wave_id();
   const int w = wave % TL::WPG, slot = wave / TL::WPG;  // row-tile group, tile slot
   const int j = lane & 15, kq = lane >> 4;
@@ -648,9 +737,16 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
   for (int u = 0; u < MTW; ++u)
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) a[u][kt] = Tf[((w * MTW + u) * KT + kt) * 64 + lane];
-  if (ch.done) return;
+  int k;
+  if constexpr (LAGGED) {
+    k = lagged_begin<TL::NW>(ra, lag, nbk, bid, ch, seg);
+    if (k == 0) return;
+  } else {
+    if (ch.done) return;
+    k = ch.iters + 1;
+  }
   if constexpr (DEVPAR) {
-    const int parity = (ch.base + ch.iters) & 1;
+    const int parity = (ch.base + k - 1) & 1;  // s^(k-1) of the segment
     ld.p = parity ? s1 : s0;
     out = parity ? s0 : s1;
   }
@@ -673,7 +769,10 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
           d2 += dd * dd;
           n2 += v * v;
         });
-    finish_residual<TL::NW>(d2, n2, ra, bid, nbk, ch.iters);
+    if constexpr (LAGGED)
+      lagged_end<TL::NW>(d2, n2, ra, lag, bid);
+    else
+      finish_residual<TL::NW>(d2, n2, ra, bid, nbk, ch.iters);
     return;
   }
   doublex4_t pend[MTW];
@@ -734,7 +833,9 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
       for (int u = 0; u < MTW; ++u) pend[u] = acc[u];
     }
   }
-  const bool last = residual_arrive<TL::NW>(d2, n2, ra, bid, nbk);
+  // the arrival (without LAGGED) goes first; the last tile's stores follow it
+  bool last = false;
+  if constexpr (!LAGGED) last = residual_arrive<TL::NW>(d2, n2, ra, bid, nbk);
   if (pend_e >= 0)
 #pragma unroll
     for (int u = 0; u < MTW; ++u)
@@ -743,14 +844,18 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
         const int row = 16 * (w * MTW + u) + kq + 4 * r;
         if (row < F::S) out[(size_t)row * nel + pend_e] = pend[u][r];
       }
-  if (last) residual_final<TL::NW>(ra, nbk, ch.iters);
+  if constexpr (LAGGED)
+    lagged_end<TL::NW>(d2, n2, ra, lag, bid);
+  else if (last)
+    residual_final<TL::NW>(ra, nbk, ch.iters);
 }
 
 template <class F, bool DEVPAR>
 __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma(
     MeshDev m, Ld64 ld, const double* __restrict__ g, const double* __restrict__ Tf, double* out, ResidArgs ra,
-    double* s0, double* s1, int tiles_per_group) {
-  sweep_mfma_body<F, DEVPAR>(m, ld, g, Tf, out, ra, s0, s1, tiles_per_group, (int)blockIdx.x, (int)gridDim.x);
+    double* s0, double* s1, int tiles_per_group, LagArgs lag) {
+  sweep_mfma_body<F, DEVPAR, true>(m, ld, g, Tf, out, ra, s0, s1, tiles_per_group, (int)blockIdx.x,
+                                   (int)gridDim.x, lag);
 }
 
 // mixed precision outer step: s_out = s_in (+ lo_in); r = g + T in(s_out) - s_out (FP64);
@@ -1105,15 +1210,27 @@ struct StepTiling {
   static constexpr int value = TL::NW;
 };
 
+// Lagged stopping test of a step's last sweep (lagged FP64 sweeps leave it pending).
+struct StepLag {
+  int lagged;             // 0: the sweeps took their own tests (batched or refinement)
+  unsigned seq_next;      // number the next sweep launch will get
+  double tol;
+  const double* partials; // the sweeps' partial sets, stride apart, nb pairs each
+  int stride, nb;
+  double* hist;
+  int hist_cap;
+};
+
 template <class F>
 __device__ __forceinline__ void step_mfma_body(MeshDev m, double* s0, double* s1, const double* __restrict__ Mf,
                                                double* u0, double* u1, const double* __restrict__ w_src,
                                                const double* __restrict__ gbe, double* __restrict__ g_out,
                                                Ctrl* ctrl, unsigned* cnt, int* step_iters, int step_cap, int lag,
-                                               int tiles_per_group, int bid, int nbk) {
+                                               int tiles_per_group, int bid, int nbk, const StepLag& sl) {
   using TL = typename StepTiling<F>::TL;
   constexpr int MTW = TL::MTW, KT = TL::KT, N = F::N, ROWS = F::N + F::S, COLS = F::N + F::I;
   const CtrlHead ch = ctrl_head(ctrl);
+  const unsigned seg = ctrl->seg_seq;
   const int lane = threadIdx.x & 63, wave = wave_id();
   const int w = wave % TL::WPG, slot = wave / TL::WPG;
   const int j = lane & 15, kq = lane >> 4;
@@ -1122,8 +1239,37 @@ __device__ __forceinline__ void step_mfma_body(MeshDev m, double* s0, double* s1
   for (int u = 0; u < MTW; ++u)
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) a[u][kt] = Mf[((w * MTW + u) * KT + kt) * 64 + lane];
-  if (ch.status != 1) return;
-  const int iters = ch.iters, base = ch.base, uc = ctrl->ucur;
+  // K: sweeps of this step (its last local solve read s^(K-1)); conv: the step converged
+  int K = ch.iters;
+  bool conv = ch.status == 1, reduced = false;
+  double res = 0.0;
+  if (sl.lagged) {
+    __shared__ double sq[kVirtLanes / 64][2];
+    __shared__ int s_done, s_status;
+    canonical_sums<TL::NW, false>(sl.partials + (size_t)((sl.seq_next - 1u) & 1u) * sl.stride, sl.nb, sq);
+    if (threadIdx.x == 0) {
+      s_done = ch.done;
+      s_status = ch.status;
+    }
+    __syncthreads();
+    if (s_done) {
+      conv = s_status == 1;
+    } else {
+      K = (int)(sl.seq_next - seg) - 1;
+      conv = false;
+      if (K >= 1) {
+        double b;
+        res = relative_increment(canonical_total(sq, b), b);
+        reduced = true;
+        conv = isfinite(res) && res < sl.tol;
+      }
+    }
+  }
+  if (!conv) {
+    if (reduced && bid == 0 && threadIdx.x == 0) record_test(ctrl, sl.hist, sl.hist_cap, K, res, sl.tol, 1);
+    return;
+  }
+  const int iters = K, base = ch.base, uc = ctrl->ucur;
   const size_t nel = (size_t)m.nel;
   const Ld64 ld{((base + iters - lag) & 1) ? s1 : s0, nel};
   const double* __restrict__ u_old = uc ? u1 : u0;
@@ -1206,6 +1352,10 @@ __device__ __forceinline__ void step_mfma_body(MeshDev m, double* s0, double* s1
   if (threadIdx.x == 0) is_last = arrive_last(cnt, bid, nbk) ? 1 : 0;
   __syncthreads();
   if (is_last && threadIdx.x == 0) {
+    if (reduced) {
+      sl.hist[(iters - 1) % sl.hist_cap] = res;
+      ctrl->last_res = res;
+    }
     step_iters[ctrl->steps_done % step_cap] = iters;
     ctrl->steps_done += 1;
     ctrl->base = (base + iters) & 1;
@@ -1213,6 +1363,7 @@ __device__ __forceinline__ void step_mfma_body(MeshDev m, double* s0, double* s1
     ctrl->iters = 0;
     ctrl->done = 0;
     ctrl->status = 0;
+    ctrl->seg_seq = sl.seq_next - 1u;
   }
 }
 
@@ -1220,9 +1371,9 @@ template <class F>
 __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
     MeshDev m, double* s0, double* s1, const double* __restrict__ Mf, double* u0, double* u1,
     const double* __restrict__ w_src, const double* __restrict__ gbe, double* __restrict__ g_out, Ctrl* ctrl,
-    unsigned* cnt, int* step_iters, int step_cap, int lag, int tiles_per_group) {
+    unsigned* cnt, int* step_iters, int step_cap, int lag, int tiles_per_group, StepLag sl) {
   step_mfma_body<F>(m, s0, s1, Mf, u0, u1, w_src, gbe, g_out, ctrl, cnt, step_iters, step_cap, lag, tiles_per_group,
-                    (int)blockIdx.x, (int)gridDim.x);
+                    (int)blockIdx.x, (int)gridDim.x, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1244,8 +1395,8 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma_batch(
   ra.hist_cap = P.hist_cap;
   ra.tol = tol;
   ra.stop = stop;
-  sweep_mfma_body<F, true>(P.mesh, Ld64{P.s0, (size_t)P.mesh.nel}, P.g, P.Tf64, nullptr, ra, P.s0, P.s1,
-                           be.tiles_per_group, be.block, be.nblocks);
+  sweep_mfma_body<F, true, false>(P.mesh, Ld64{P.s0, (size_t)P.mesh.nel}, P.g, P.Tf64, nullptr, ra, P.s0, P.s1,
+                                  be.tiles_per_group, be.block, be.nblocks, LagArgs{0u, 0});
 }
 
 template <class F>
@@ -1256,7 +1407,7 @@ __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma_batch(
   if (P.ctrl->steps_done >= P.steps_target) return;
   step_mfma_body<F>(P.mesh, P.s0, P.s1, P.Mf64, P.u0, P.u1, P.w_src, P.gbe, const_cast<double*>(P.g), P.ctrl,
                     P.counters + kCounterSet, P.step_iters, P.step_cap, lag, be.tiles_per_group, be.block,
-                    be.nblocks);
+                    be.nblocks, StepLag{0, 0u, 0.0, nullptr, 0, 0, nullptr, 1});
 }
 
 // ---------------------------------------------------------------------------
@@ -1328,14 +1479,14 @@ struct Family {
     static const int r = resident_groups(k_refine_mfma<F, LD, ST>, 64 * Tiling64<F::S, F::I>::NW);
     return r;
   }
-  static void sweep64(const DevProblem& dp, double tol, hipStream_t st) {
+  static void sweep64(const DevProblem& dp, double tol, unsigned seq, hipStream_t st) {
     using TL = Tiling64<F::S, F::I>;
     const ResidArgs ra = resid_args(dp, tol, tol >= 0.0 ? 1 : 0);
     int tpg, groups;
     mfma_groups(dp.mesh.nel, TL::TS, res_sweep(), tpg, groups);
     hipLaunchKernelGGL((k_sweep_mfma<F, true>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh,
                        Ld64{dp.s[0], (size_t)dp.mesh.nel}, (const double*)dp.g, dp.Tf64, (double*)nullptr, ra,
-                       dp.s[0], dp.s[1], tpg);
+                       dp.s[0], dp.s[1], tpg, LagArgs{seq, dp.partial_stride});
   }
   static void volume(const DevProblem& dp, const double* s_prev, const double* u_old, double* u_out,
                      hipStream_t st) {
@@ -1373,14 +1524,15 @@ struct Family {
     if (n <= 0) return;
     hipLaunchKernelGGL((k_step_mfma_batch<F>), dim3(n), dim3(64 * TL::NW), 0, st, table, probs, lag);
   }
-  static void step(const DevProblem& dp, int lag, hipStream_t st) {
+  static void step(const DevProblem& dp, int lag, unsigned seq_next, double tol, int lagged, hipStream_t st) {
     using TL = typename StepTiling<F>::TL;
     int tpg, groups;
     mfma_groups(dp.mesh.nel, TL::TS, res_step(), tpg, groups);
+    const StepLag sl{lagged, seq_next, tol, dp.partials, dp.partial_stride, dp.nb_sweep, dp.hist, dp.hist_cap};
     hipLaunchKernelGGL((k_step_mfma<F>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, dp.s[0], dp.s[1],
                        dp.Mf64, dp.u2[0], dp.u2[1], (const double*)(dp.has_src ? dp.w_src : nullptr),
                        (const double*)(dp.has_src ? dp.gbe : nullptr), dp.g, dp.ctrl, dp.counters + kCounterSet,
-                       dp.step_iters, dp.step_cap, lag, tpg);
+                       dp.step_iters, dp.step_cap, lag, tpg, sl);
   }
   static void refine32(const DevProblem& dp, const void* lo_in, void* r_out, double tol, hipStream_t st) {
     const size_t ne = (size_t)dp.mesh.nel;
@@ -1599,9 +1751,10 @@ const KernelSet* find_kernels(int pde, int dim, int na, int p) {
 template <class F>
 __global__ __launch_bounds__(256) void k_sweep_var(MeshDev m, const double* __restrict__ g,
                                                     const double* __restrict__ Tv, ResidArgs ra, double* s0,
-                                                    double* s1) {
+                                                    double* s1, LagArgs lag) {
   constexpr int NRB = var_row_blocks(F::S), RPL = var_rows_per_lane(F::S);
   const CtrlHead ch = ctrl_head(ra.ctrl);
+  const unsigned seg = ra.ctrl->seg_seq;
   const int lane = threadIdx.x & 63, w = wave_id();
   const int item = remap_block(blockIdx.x, gridDim.x) * 4 + w;  // (tile, row block) of this wavefront
   const int tile = item / NRB, rb = item - tile * NRB;
@@ -1619,8 +1772,10 @@ __global__ __launch_bounds__(256) void k_sweep_var(MeshDev m, const double* __re
     row[k] = r < F::S ? r : F::S - 1;
     acc[k] = g[(size_t)row[k] * nel + es];
   }
-  if (ch.done) return;
-  const int parity = (ch.base + ch.iters) & 1;
+  // the stopping test of the previous sweep (lagged, like the matrix-core sweep)
+  const int ks = lagged_begin<4>(ra, lag, (int)gridDim.x, (int)blockIdx.x, ch, seg);
+  if (ks == 0) return;
+  const int parity = (ch.base + ks - 1) & 1;
   const Ld64 ld{parity ? s1 : s0, nel};
   double* out = parity ? s0 : s1;
   Nb nb;
@@ -1644,12 +1799,10 @@ __global__ __launch_bounds__(256) void k_sweep_var(MeshDev m, const double* __re
       n2 += acc[k] * acc[k];
     }
   }
-  // the new state is stored after the arrival, so the arrival does not wait for it
-  const bool last = residual_arrive<4>(d2, n2, ra, (int)blockIdx.x, (int)gridDim.x);
 #pragma unroll
   for (int k = 0; k < RPL; ++k)
     if (live[k]) out[(size_t)row[k] * nel + e] = acc[k];
-  if (last) residual_final<4>(ra, (int)gridDim.x, ch.iters);
+  lagged_end<4>(d2, n2, ra, lag, (int)blockIdx.x);
 }
 
 // in(s) of every element into in[c][e] (recovery of the element solutions)
@@ -1666,11 +1819,11 @@ __global__ __launch_bounds__(kBlock) void k_gather_var(MeshDev m, const double* 
 
 template <class F>
 struct VarFamily {
-  static void sweep64(const DevProblem& dp, double tol, hipStream_t st) {
+  static void sweep64(const DevProblem& dp, double tol, unsigned seq, hipStream_t st) {
     const ResidArgs ra = resid_args(dp, tol, tol >= 0.0 ? 1 : 0);
     const long long groups = var_sweep_groups(dp.mesh.nel, F::S);
     hipLaunchKernelGGL((k_sweep_var<F>), dim3((unsigned)groups), dim3(256), 0, st, dp.mesh, (const double*)dp.g,
-                       dp.Tv, ra, dp.s[0], dp.s[1]);
+                       dp.Tv, ra, dp.s[0], dp.s[1], LagArgs{seq, dp.partial_stride});
   }
   // u_out = w_src + R_e in(s_prev)  (steady only)
   static void volume(const DevProblem& dp, const double* s_prev, const double*, double* u_out, hipStream_t st) {
@@ -1808,28 +1961,33 @@ void launch_fill_bytes(void* p, size_t bytes, hipStream_t st) {
                      (uint32_t*)p, words);
 }
 
-__device__ void ctrl_reset(Ctrl* c, int full) {
+__device__ void ctrl_reset(Ctrl* c, int full, unsigned seq_next) {
   if (full == 1) {
     c->base = 0;
     c->ucur = 0;
     c->steps_done = 0;
     c->last_res = 0.0;
   } else {
-    if (full == 2 && !c->done) return;  // the current segment is still running: continue it
+    if (full == 2 && !c->done) {
+      // the current segment is still running: continue it (the next sweep is number iters + 1)
+      c->seg_seq = seq_next - 1u - (unsigned)c->iters;
+      return;
+    }
     c->base = (c->base + c->iters) & 1;  // the new segment starts from the latest state
   }
   c->done = 0;
   c->iters = 0;
   c->status = 0;
+  c->seg_seq = seq_next - 1u;
 }
 
-__global__ void k_ctrl_reset(Ctrl* c, int full) {
-  if (threadIdx.x == 0) ctrl_reset(c, full);
+__global__ void k_ctrl_reset(Ctrl* c, int full, unsigned seq_next) {
+  if (threadIdx.x == 0) ctrl_reset(c, full, seq_next);
 }
 
 __global__ void k_ctrl_reset_batch(const BatchProblem* probs, int n, int full) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) ctrl_reset(probs[i].ctrl, full);
+  if (i < n) ctrl_reset(probs[i].ctrl, full, 0u);  // batched sweeps take their own tests
 }
 
 __global__ void k_ctrl_gather(const BatchProblem* probs, int n, Ctrl* out) {
@@ -1853,8 +2011,31 @@ void launch_counters_reset(unsigned* counters, hipStream_t st) {
   hipLaunchKernelGGL(k_counters_reset, dim3(1), dim3(64), 0, st, counters);
 }
 
-void launch_ctrl_reset(Ctrl* c, int full, hipStream_t st) {
-  hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, c, full);
+void launch_ctrl_reset(Ctrl* c, int full, unsigned seq_next, hipStream_t st) {
+  hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, c, full, seq_next);
+}
+
+// The stopping test of the sweep before launch number seq, as that launch would take it
+// (one workgroup of four wavefronts: the canonical order needs no particular size).
+__global__ __launch_bounds__(256) void k_reduce_lagged(Ctrl* c, const double* __restrict__ partials, int stride,
+                                                       int nb, double* hist, int hist_cap, double tol, int stop,
+                                                       unsigned seq) {
+  __shared__ double sq[kVirtLanes / 64][2];
+  const CtrlHead ch = ctrl_head(c);
+  const unsigned seg = c->seg_seq;
+  canonical_sums<4, false>(partials + (size_t)((seq - 1u) & 1u) * stride, nb, sq);
+  __syncthreads();
+  if (threadIdx.x != 0 || ch.done) return;
+  const int k = (int)(seq - seg);
+  if (k < 2) return;
+  double b;
+  const double res = relative_increment(canonical_total(sq, b), b);
+  record_test(c, hist, hist_cap, k - 1, res, tol, stop);
+}
+
+void launch_reduce_lagged(const DevProblem& dp, double tol, unsigned seq, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_lagged, dim3(1), dim3(256), 0, st, dp.ctrl, (const double*)dp.partials,
+                     dp.partial_stride, dp.nb_sweep, dp.hist, dp.hist_cap, tol, tol >= 0.0 ? 1 : 0, seq);
 }
 
 __global__ void k_cast(const double* __restrict__ src, void* __restrict__ dst, size_t count, int to_bf16) {
