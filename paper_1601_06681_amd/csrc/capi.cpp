@@ -584,13 +584,17 @@ int ehdg_step(ehdg_handle h, int32_t n_steps, double rel_tol, int32_t max_iters_
   const int first = h->mirror.steps_done, target = first + n_steps;
   Outer o{h};
   int max_seen = 0;
-  // Every step is queued as (predicted outer iterations + 1) followed by the step
-  // kernel.  A step that converges early leaves no-op launches; one that needs more
+  // Every step is queued as (predicted outer iterations + a margin) followed by the
+  // step kernel.  A step that converges early leaves no-op launches; one that needs more
   // borrows the next step's iterations (its step kernel finds it unconverged and does
-  // nothing).  The host synchronizes once per batch.
+  // nothing), which leaves the rest of that step's slot as no-ops and usually costs
+  // another batch.  Counts grow slowly along a run, so the margin (1 + pred / 8) keeps
+  // borrowing rare at the cost of a few no-ops per step.  The host synchronizes once per
+  // batch.
   while (h->mirror.steps_done < target) {
     const int remaining = target - h->mirror.steps_done;
-    const int per = std::min(std::max(1, pred) + 1, max_outer);
+    const int p = std::max(1, pred);
+    const int per = std::min(p + 1 + (p + 7) / 8, max_outer);
     for (int r = 0; r < remaining; ++r) {
       for (int j = 0; j < per; ++j) o.queue(rel_tol);
       h->ks->step(dp, lag, h->seq + 1, rel_tol, mixed(h) ? 0 : 1, h->stream);
