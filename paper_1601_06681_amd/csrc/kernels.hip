@@ -685,19 +685,74 @@ struct LagArgs {
   int stride;       // doubles between the two partial sets
 };
 
-// Start of a lagged sweep, all threads: the previous sweep's partials are summed (their
-// loads overlap the control block's), the control block's done flag is made uniform
-// across the workgroup, and the stopping test of sweep k - 1 is taken.  Returns k (> 0),
-// or 0 if the segment has stopped (then the caller writes nothing).
+// The first kU pairs of each of a wavefront's virtual lanes (the canonical order of
+// canonical_sums), loaded into registers ahead of their use; pairs beyond
+// kVirtLanes * kU are read when consumed.
+template <int NW>
+struct PartialPrefetch {
+  static constexpr int kQ = (kVirtLanes / 64 + NW - 1) / NW;  // virtual wavefronts per wavefront
+  static constexpr int kU = 4;
+  double pa[kQ][kU], pb[kQ][kU];
+  __device__ __forceinline__ void issue(const double* __restrict__ p, int nb) {
+    const int lane = threadIdx.x & 63, w = wave_id();
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int q = w + i * NW, v = 64 * (q < kVirtLanes / 64 ? q : 0) + lane;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int j = v + kVirtLanes * u;
+        const int jc = j < nb ? j : nb - 1;
+        pa[i][u] = p[2 * jc];
+        pb[i][u] = p[2 * jc + 1];
+      }
+    }
+  }
+  __device__ __forceinline__ void consume(const double* __restrict__ p, int nb, double (*sq)[2]) const {
+    const int lane = threadIdx.x & 63, w = wave_id();
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int q = w + i * NW;
+      if (q >= kVirtLanes / 64) break;
+      const int v = 64 * q + lane;
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const bool in = v + kVirtLanes * u < nb;
+        a += in ? pa[i][u] : 0.0;
+        b += in ? pb[i][u] : 0.0;
+      }
+      for (int j = v + kVirtLanes * kU; j < nb; j += kVirtLanes) {
+        a += p[2 * j];
+        b += p[2 * j + 1];
+      }
+      a = wave_sum(a);
+      b = wave_sum(b);
+      if (lane == 0) {
+        sq[q][0] = a;
+        sq[q][1] = b;
+      }
+    }
+  }
+};
+
+// Start of a lagged sweep, all threads: the previous sweep's partials are loaded with the
+// control block, the control block's done flag is made uniform across the workgroup (a
+// launch queued past convergence leaves here, without waiting for the partials), the
+// partials are summed in the canonical order, and the stopping test of sweep k - 1 is
+// taken.  Returns k (> 0), or 0 if the segment has stopped (then the caller writes nothing).
 template <int NW>
 __device__ __forceinline__ int lagged_begin(const ResidArgs& ra, const LagArgs& lag, int nb, int bid,
                                             const CtrlHead& ch, unsigned seg) {
   __shared__ double sq[kVirtLanes / 64][2];
   __shared__ int s_done;
-  canonical_sums<NW, false>(ra.partials + (size_t)((lag.seq - 1u) & 1u) * lag.stride, nb, sq);
+  const double* parts = ra.partials + (size_t)((lag.seq - 1u) & 1u) * lag.stride;
+  PartialPrefetch<NW> pf;
+  pf.issue(parts, nb);
   if (threadIdx.x == 0) s_done = ch.done;
   __syncthreads();
   if (s_done) return 0;
+  pf.consume(parts, nb, sq);
+  __syncthreads();
   const int k = (int)(lag.seq - seg);
   if (k >= 2) {
     double b;
