@@ -480,87 +480,6 @@ __device__ __forceinline__ void stage_inputs(const MeshDev& m, int es, bool vali
   }
 }
 
-// out[r][e] = g[r][e] + sum_c T[r][c] in_e[c]   (r < S, c < I).  T has RowSplit<S>::PAD rows.
-// DEVPAR: the FP64 state buffers are chosen from the control block (s0/s1), else
-// the loader and `out` are used as given.
-template <class F, typename T, class LD, bool RESID, bool DEVPAR>
-__global__ __launch_bounds__(kThreads) void k_sweep(MeshDev m, LD ld, const T* __restrict__ g,
-                                                     const T* __restrict__ Tm, T* out, ResidArgs ra,
-                                                     double* s0, double* s1) {
-  // the control block is read first; the index arithmetic and the g loads, which do
-  // not depend on it, overlap its latency
-  const CtrlHead ch = ctrl_head(ra.ctrl);
-  const int done = ch.done;
-  const int parity = (ch.base + ch.iters) & 1;
-  T* x = reinterpret_cast<T*>(g_smem);
-  const int lane = threadIdx.x & 63, w = wave_id();
-  const int e = remap_block(blockIdx.x, gridDim.x) * kLanes + lane;
-  const bool valid = e < m.nel;
-  const int es = valid ? e : 0;  // stand-in element for lanes past the end: loads stay in bounds
-  const size_t nel = (size_t)m.nel;
-  constexpr int RW = RowSplit<F::S>::RW;
-  const int r0 = w * RW;
-  Nb nb;
-  F::neighbours(m, es, nb);
-  T acc[RW];
-#pragma unroll
-  for (int i = 0; i < RW; ++i) {
-    const int r = r0 + i;
-    const T gv = g[(size_t)(r < F::S ? r : F::S - 1) * nel + es];
-    acc[i] = (valid && r < F::S) ? gv : T(0);
-  }
-  if (done) return;
-  if constexpr (DEVPAR) {
-    set_state(ld, parity ? s1 : s0, 0);
-    out = parity ? s0 : s1;
-  }
-  using V = decltype(ld(0, 0));
-  V own[F::kSelfSum ? RW : 1];
-  if constexpr (F::kSelfSum) {
-    // S == I: each wavefront gathers the rows it will produce and keeps the old
-    // state values of those rows for the increment
-#pragma unroll
-    for (int i = 0; i < RW; ++i) {
-      const int c = r0 + i;
-      V o;
-      const T v = (T)F::row_parts(m, es, nb, ld, c < F::I ? c : F::I - 1, o);
-      own[i] = o;
-      if (c < F::I) x[c * kLanes + lane] = valid ? v : T(0);
-    }
-  } else {
-    stage_inputs<F, T>(m, es, valid, nb, ld, x, 0);
-  }
-  __syncthreads();
-  const T* __restrict__ Trow = Tm + (size_t)uniform(r0 * F::I);
-#pragma unroll 4
-  for (int c = 0; c < F::I; ++c) {
-    const T xc = x[c * kLanes + lane];
-#pragma unroll
-    for (int i = 0; i < RW; ++i) acc[i] = fmadd(Trow[i * F::I + c], xc, acc[i]);
-  }
-  double d2 = 0.0, n2 = 0.0;
-  if (valid) {
-#pragma unroll
-    for (int i = 0; i < RW; ++i) {
-      const int r = r0 + i;
-      if (r < F::S) {
-        out[(size_t)r * nel + e] = acc[i];
-        if (RESID) {
-          double old;
-          if constexpr (F::kSelfSum)
-            old = (double)own[i];
-          else
-            old = (double)x[F::own_row(r) * kLanes + lane];
-          const double dd = (double)acc[i] - old;
-          d2 += dd * dd;
-          n2 += (double)acc[i] * (double)acc[i];
-        }
-      }
-    }
-  }
-  if (RESID) finish_residual(d2, n2, ra, ch.iters);
-}
-
 // ---------------------------------------------------------------------------
 // the FP64 sweep on the matrix cores
 // ---------------------------------------------------------------------------
@@ -928,75 +847,6 @@ struct StAos16 {  // BF16, element-major
   }
 };
 
-template <class F, class LD, class ST>
-__global__ __launch_bounds__(kThreads) void k_refine(MeshDev m, LD ld, const double* __restrict__ g,
-                                                      const double* __restrict__ Tm, double* s0, double* s1,
-                                                      ST r_lo, ResidArgs ra) {
-  const CtrlHead ch = ctrl_head(ra.ctrl);
-  if (ch.done) return;
-  // s^k from the control block; the correction is applied from the segment's second refinement on
-  const int b = (ch.base + ch.iters) & 1;
-  set_state(ld, b ? s1 : s0, ch.iters > 0 ? 1 : 0);
-  double* s_out = b ? s0 : s1;
-  double* x = reinterpret_cast<double*>(g_smem);
-  const int lane = threadIdx.x & 63, w = wave_id();
-  const int e = remap_block(blockIdx.x, gridDim.x) * kLanes + lane;
-  const bool valid = e < m.nel;
-  const int es = valid ? e : 0;
-  const size_t nel = (size_t)m.nel;
-  constexpr int RW = RowSplit<F::S>::RW;
-  const int r0 = w * RW;
-  Nb nb;
-  F::neighbours(m, es, nb);
-  double acc[RW];
-#pragma unroll
-  for (int i = 0; i < RW; ++i) {
-    const int r = r0 + i;
-    const double gv = g[(size_t)(r < F::S ? r : F::S - 1) * nel + es];
-    acc[i] = (valid && r < F::S) ? gv : 0.0;
-  }
-  // s' (the refined iterate) of the rows this wavefront produces
-  double own[RW];
-  if constexpr (F::kSelfSum) {
-#pragma unroll
-    for (int i = 0; i < RW; ++i) {
-      const int c = r0 + i;
-      double o;
-      const double v = F::row_parts(m, es, nb, ld, c < F::I ? c : F::I - 1, o);
-      own[i] = o;
-      if (c < F::I) x[c * kLanes + lane] = valid ? v : 0.0;
-    }
-    __syncthreads();
-  } else {
-    stage_inputs<F, double>(m, es, valid, nb, ld, x, 0);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < RW; ++i) own[i] = r0 + i < F::S ? x[F::own_row(r0 + i) * kLanes + lane] : 0.0;
-  }
-  const double* __restrict__ Trow = Tm + (size_t)uniform(r0 * F::I);
-#pragma unroll 4
-  for (int c = 0; c < F::I; ++c) {
-    const double xc = x[c * kLanes + lane];
-#pragma unroll
-    for (int i = 0; i < RW; ++i) acc[i] = fma(Trow[i * F::I + c], xc, acc[i]);
-  }
-  double d2 = 0.0, n2 = 0.0;
-  if (valid) {
-#pragma unroll
-    for (int i = 0; i < RW; ++i) {
-      const int r = r0 + i;
-      if (r < F::S) {
-        const double res = acc[i] - own[i];
-        s_out[(size_t)r * nel + e] = own[i];
-        r_lo(r, e, res);
-        d2 += res * res;
-        n2 += acc[i] * acc[i];
-      }
-    }
-  }
-  finish_residual(d2, n2, ra, ch.iters);
-}
-
 // Element solution from the traces of the last local solve, as one stacked contraction
 //   steady:          u_new = w_src + R in(s_prev)
 //   backward Euler:  [u_new; g_next] = [w_src; gbe] + [[P, R], [G P, G R]] [u_old; in(s_prev)]
@@ -1067,40 +917,10 @@ __global__ __launch_bounds__(kThreads) void k_volume(MeshDev m, const double* __
   volume_body<F, BE>(m, s_prev, Mv, u_old, w_src, gbe, u_new, nullptr);
 }
 
-// Completion of a backward-Euler step, queued after the step's sweeps.  Runs only if
-// the step converged; then u[ucur^1] = u^{m+1}, g = the next step's g, and the last
-// workgroup to finish advances the control block (every workgroup has read it by then).
-template <class F>
-__global__ __launch_bounds__(kThreads) void k_step(MeshDev m, double* s0, double* s1, const double* __restrict__ Mv,
-                                                    double* u0, double* u1, const double* __restrict__ w_src,
-                                                    const double* __restrict__ gbe, double* __restrict__ g_out,
-                                                    Ctrl* ctrl, unsigned* cnt, int* step_iters, int step_cap,
-                                                    int lag) {
-  if (ctrl->status != 1) return;
-  const int iters = ctrl->iters, base = ctrl->base, uc = ctrl->ucur;
-  const double* s_prev = ((base + iters - lag) & 1) ? s1 : s0;
-  volume_body<F, true>(m, s_prev, Mv, uc ? u1 : u0, w_src, gbe, uc ? u0 : u1, g_out);
-  __shared__ int is_last;
-  __syncthreads();
-  // the control block was read by every workgroup before it arrives here, and nothing
-  // this kernel writes is read by the last workgroup: no fence is needed
-  if (threadIdx.x == 0) is_last = arrive_last(cnt, blockIdx.x, gridDim.x) ? 1 : 0;
-  __syncthreads();
-  if (is_last && threadIdx.x == 0) {
-    step_iters[ctrl->steps_done % step_cap] = iters;
-    ctrl->steps_done += 1;
-    ctrl->base = (base + iters) & 1;
-    ctrl->ucur = uc ^ 1;
-    ctrl->iters = 0;
-    ctrl->done = 0;
-    ctrl->status = 0;
-  }
-}
-
-// Mixed-precision refinement on the matrix cores (the k_refine contract): s' = s^k (+ the
-// low-precision correction from the segment's second refinement on); r = g + T in(s') - s'
-// in FP64, stored in the low precision; s' stored as s^{k+1}; reduction of ||r|| and
-// ||s' + r||.
+// Mixed-precision refinement on the matrix cores: s' = s^k (+ the low-precision
+// correction from the segment's second refinement on); r = g + T in(s') - s' in FP64,
+// stored in the low precision (r_lo); s' stored as s^{k+1}; the stopping test on
+// ||r|| / ||s' + r|| (the increment of the refined iterate).
 template <class F, class LD, class ST>
 __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
     MeshDev m, LD ld, const double* __restrict__ g, const double* __restrict__ Tf, double* s0, double* s1, ST r_lo,
