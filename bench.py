@@ -1,7 +1,7 @@
 """Benchmark of the eHDG hot path on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-forms]
-                [--no-3d] [--no-variable] [--no-batch] [--no-serving]
+                [--no-3d] [--no-control] [--no-variable] [--no-batch] [--no-serving]
 
 A step is one backward-Euler time step of the linearized shallow-water workload
 (256 x 256 periodic quads, degree 4, 3 fields, 4 915 200 DOFs): build the step's
@@ -12,7 +12,8 @@ workload.  The printed value is whole-job throughput: DOFs x sweeps / wall time 
 the K timed steps, inputs resident in HBM.
 
 Further sections of the same JSON line (each can be switched off): 64^3 steady
-transport in FP64 and the mixed-precision forms, Section 4.1 / 4.3 variable-velocity
+transport in FP64 and the mixed-precision forms, the same at 128^3 as a control whose
+traces cannot stay in the Infinity Cache, Section 4.1 / 4.3 variable-velocity
 transport (per-element operators), a batch of 512 mixed problems, and a serving run.
 
 One JSON line on stdout; progress on stderr.
@@ -174,12 +175,13 @@ def run_swe(args, torch):
     return out
 
 
-def run_transport3d(torch, args):
-    """64^3 hexes, degree 3, steady transport: time to a relative trace increment of 1e-8,
-    plain FP64 vs FP32- and BF16-MFMA-correction forms with FP64 refinement."""
+def run_transport3d(torch, args, cfg=None):
+    """64^3 hexes (or cfg's mesh), degree 3, steady transport: time to a relative trace
+    increment of 1e-8, plain FP64 vs FP32- and BF16-MFMA-correction forms with FP64
+    refinement."""
     from paper_1601_06681_amd import workloads as W
     from paper_1601_06681_amd.ehdg import EHDG_TRANSPORT, Problem
-    cfg = W.TRANSPORT3D
+    cfg = cfg or W.TRANSPORT3D
     ue, f = W.transport_manufactured_3d(cfg["beta"], cfg["sigma"])
 
     def make(precision=0, inner=1):
@@ -210,9 +212,10 @@ def run_transport3d(torch, args):
     out = {"workload": cfg["name"], "dofs": dofs, "rel_tol": cfg["tol"],
            "fp64": {"time_to_tol_ms": t64 * 1e3, "sweeps": it64, "rel_res": res64,
                     "dof_updates_per_s": dofs * it64 / t64, "max_err_vs_manufactured": err_exact,
-                    "sweep_us": t_sweep * 1e6, "sweep_hbm_frac": alg_bytes / t_sweep / HBM_PEAK,
+                    "sweep_us": t_sweep * 1e6, "sweep_alg_bytes": alg_bytes,
+                    "sweep_hbm_frac": alg_bytes / t_sweep / HBM_PEAK,
                     "sweep_fp64_frac": flops / t_sweep / FP64_PEAK}}
-    log(f"[bench] 3d fp64: {it64} sweeps in {t64 * 1e3:.2f} ms; sweep {t_sweep * 1e6:.1f} us "
+    log(f"[bench] 3d {cfg['name']} fp64: {it64} sweeps in {t64 * 1e3:.2f} ms; sweep {t_sweep * 1e6:.1f} us "
         f"({alg_bytes / t_sweep / 1e9:.0f} GB/s, {flops / t_sweep / 1e12:.1f} TF/s)")
     p64.close()
     for name, prec, inner in (("fp32_refine_s8", 1, 8), ("bf16_mfma_refine_s8", 2, 8)):
@@ -222,7 +225,7 @@ def run_transport3d(torch, args):
         err = float(((u - u64).abs().max() / u64.abs().max()).item())
         out[name] = {"time_to_tol_ms": t * 1e3, "equivalent_sweeps": it, "rel_res": res,
                      "rel_err_vs_fp64_form": err, "speedup_vs_fp64_form": t64 / t}
-        log(f"[bench] 3d {name}: {t * 1e3:.2f} ms, {it} equivalent sweeps, err vs fp64 {err:.2e}")
+        log(f"[bench] 3d {cfg['name']} {name}: {t * 1e3:.2f} ms, {it} equivalent sweeps, err vs fp64 {err:.2e}")
         pr.close()
     return out
 
@@ -516,6 +519,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-control", action="store_true",
+                    help="skip the 128^3 transport control (traces far larger than the Infinity Cache)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-variable", action="store_true")
     ap.add_argument("--batch-size", type=int, default=512)
@@ -551,6 +556,9 @@ def main():
     out = run_swe(args, torch)
     if not args.no_3d:
         out["transport3d"] = run_transport3d(torch, args)
+    if not args.no_control:
+        from paper_1601_06681_amd import workloads as W
+        out["transport3d_control"] = run_transport3d(torch, args, W.TRANSPORT3D_CONTROL)
     if not args.no_variable:
         out["variable_velocity"] = run_variable(torch, args)
     if not args.no_batch:

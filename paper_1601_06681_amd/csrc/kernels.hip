@@ -1012,11 +1012,23 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
 // FP32 correction sweep on the matrix cores: lo_out = r_lo + T in(lo_in) with
 // v_mfma_f32_16x16x4f32 (same fragments as the FP64 sweep, in FP32; the FP32 result
 // fragment holds D[4 (l / 16) + r][l % 16]).
+// The FP32 correction sweep's tiling: FP32 fragments take half the registers of FP64
+// ones, so the same register budget holds twice as many (96 per lane), and a wavefront
+// can take every row tile of an element tile itself.  (With the FP64 budget the 64^3
+// transport family split its 3 row tiles over 3 wavefronts, each gathering the whole
+// B tile again.)
+constexpr int kMfmaMaxA32 = 2 * kMfmaMaxA;
 template <class F>
-__global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_inner32_mfma(
+struct Inner32Tiling {
+  using TL = Tiling64<F::S, F::I, kMfmaMaxA32>;
+  static constexpr int value = TL::NW;
+};
+
+template <class F>
+__global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_inner32_mfma(
     MeshDev m, Ld32 ld, const float* __restrict__ r_lo, const float* __restrict__ Tf, float* __restrict__ out,
     const Ctrl* ctrl, int tiles_per_group) {
-  using TL = Tiling64<F::S, F::I>;
+  using TL = typename Inner32Tiling<F>::TL;
   constexpr int MTW = TL::MTW, KT = TL::KT;
   const int done = ctrl->done;
   const int lane = threadIdx.x & 63, wave = wave_id();
@@ -1346,7 +1358,7 @@ struct Family {
     return r;
   }
   static int res_inner32() {
-    static const int r = resident_groups(k_inner32_mfma<F>, 64 * Tiling64<F::S, F::I>::NW);
+    static const int r = resident_groups(k_inner32_mfma<F>, 64 * Inner32Tiling<F>::value);
     return r;
   }
   template <class LD, class ST>
@@ -1427,7 +1439,7 @@ struct Family {
                        (const double*)dp.g, dp.Tf64, dp.s[0], dp.s[1], store, ra, tpg);
   }
   static void inner32(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
-    using TL = Tiling64<F::S, F::I>;
+    using TL = typename Inner32Tiling<F>::TL;
     int tpg, groups;
     mfma_groups(dp.mesh.nel, TL::TS, res_inner32(), tpg, groups);
     hipLaunchKernelGGL((k_inner32_mfma<F>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh,

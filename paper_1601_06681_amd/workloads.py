@@ -55,6 +55,10 @@ TRANSPORT2D = dict(name="transport2d_8x8_p2", dim=2, n=(8, 8), L=(1.0, 1.0), per
                    beta=(1.0, 0.5), sigma=1.0, dt=0.0, tol=1e-10)
 TRANSPORT3D = dict(name="transport3d_64c_p3", dim=3, n=(64, 64, 64), L=(1.0, 1.0, 1.0), periodic=(0, 0, 0),
                    degree=3, beta=(1.0, 0.7, 0.3), sigma=1.0, dt=0.0, tol=1e-8)
+# The same problem at 128^3: 2.1 M elements, 134 M DOFs.  Its traces (2.4 GB per FP64
+# sweep, 1.2 GB per FP32 correction sweep) are far larger than the 256 MB Infinity Cache, so
+# its bandwidth figures are HBM figures.
+TRANSPORT3D_CONTROL = dict(TRANSPORT3D, name="transport3d_128c_p3_control", n=(128, 128, 128))
 
 
 # ---------------------------------------------------------------------------- shallow water
