@@ -917,11 +917,36 @@ __global__ __launch_bounds__(kThreads) void k_volume(MeshDev m, const double* __
   volume_body<F, BE>(m, s_prev, Mv, u_old, w_src, gbe, u_new, nullptr);
 }
 
+// s' = s^k + the low-precision correction (from the segment's second refinement on;
+// before that a copy of s^k), written to the buffer the refinement writes s^{k+1} to.
+// One thread per element: the FP64 state is component-major (coalesced per row), the
+// correction either component-major (FP32) or element-major (BF16, S values per element).
+template <class F, class LDD>
+__global__ __launch_bounds__(256) void k_apply_correction(const Ctrl* ctrl, double* s0, double* s1, LDD d, int nel) {
+  const CtrlHead ch = ctrl_head(ctrl);
+  if (ch.done) return;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nel) return;
+  const int parity = (ch.base + ch.iters) & 1;
+  const double* __restrict__ s = parity ? s1 : s0;
+  double* __restrict__ out = parity ? s0 : s1;
+  const bool use = ch.iters > 0;
+#pragma unroll 8
+  for (int r = 0; r < F::S; ++r) {
+    const size_t i = (size_t)r * nel + e;
+    const double v = s[i];
+    out[i] = use ? v + (double)d(r, e) : v;
+  }
+}
+
 // Mixed-precision refinement on the matrix cores: s' = s^k (+ the low-precision
 // correction from the segment's second refinement on); r = g + T in(s') - s' in FP64,
 // stored in the low precision (r_lo); s' stored as s^{k+1}; the stopping test on
 // ||r|| / ||s' + r|| (the increment of the refined iterate).
-template <class F, class LD, class ST>
+// With APPLIED (LD = Ld64) s' is already in the buffer s^{k+1} goes to (k_apply_correction
+// wrote it): the gather reads one FP64 value per input instead of a state value and a
+// correction value, and s' is not stored again.
+template <class F, class LD, class ST, bool APPLIED = false>
 __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
     MeshDev m, LD ld, const double* __restrict__ g, const double* __restrict__ Tf, double* s0, double* s1, ST r_lo,
     ResidArgs ra, int tiles_per_group) {
@@ -938,7 +963,10 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
     for (int kt = 0; kt < KT; ++kt) a[u][kt] = Tf[((w * MTW + u) * KT + kt) * 64 + lane];
   if (ch.done) return;
   const int parity = (ch.base + ch.iters) & 1;
-  set_state(ld, parity ? s1 : s0, ch.iters > 0 ? 1 : 0);
+  if constexpr (APPLIED)
+    ld.p = parity ? s0 : s1;
+  else
+    set_state(ld, parity ? s1 : s0, ch.iters > 0 ? 1 : 0);
   double* s_out = parity ? s0 : s1;
   const size_t nel = (size_t)m.nel;
   const int ntiles = (m.nel + 15) >> 4;
@@ -955,7 +983,7 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
         },
         [&](int row, int e, double v, double own) {
           const double res = v - own;
-          s_out[(size_t)row * nel + e] = own;
+          if constexpr (!APPLIED) s_out[(size_t)row * nel + e] = own;
           r_lo(row, e, res);
           d2 += res * res;
           n2 += v * v;
@@ -999,7 +1027,7 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
         const int row = 16 * (w * MTW + u) + kq + 4 * r;
         if (valid && row < F::S) {
           const double v = acc[u][r], res = v - own[u][r];
-          s_out[(size_t)row * nel + e] = own[u][r];
+          if constexpr (!APPLIED) s_out[(size_t)row * nel + e] = own[u][r];
           r_lo(row, e, res);
           d2 += res * res;
           n2 += v * v;
@@ -1361,9 +1389,9 @@ struct Family {
     static const int r = resident_groups(k_inner32_mfma<F>, 64 * Inner32Tiling<F>::value);
     return r;
   }
-  template <class LD, class ST>
+  template <class LD, class ST, bool APPLIED = false>
   static int res_refine() {
-    static const int r = resident_groups(k_refine_mfma<F, LD, ST>, 64 * Tiling64<F::S, F::I>::NW);
+    static const int r = resident_groups(k_refine_mfma<F, LD, ST, APPLIED>, 64 * Tiling64<F::S, F::I>::NW);
     return r;
   }
   static void sweep64(const DevProblem& dp, double tol, unsigned seq, hipStream_t st) {
@@ -1425,18 +1453,33 @@ struct Family {
     const size_t ne = (size_t)dp.mesh.nel;
     const StSoa32 store{(float*)r_out, ne};
     if (lo_in)
-      refine_mfma(dp, LdSum<Ld32>{Ld64{dp.s[0], ne}, Ld32{(const float*)lo_in, ne}, 1}, store, tol, st);
+      refine_corrected(dp, Ld32{(const float*)lo_in, ne}, store, tol, st);
     else
       refine_mfma(dp, Ld64{dp.s[0], ne}, store, tol, st);
   }
-  template <class LD, class ST>
+  template <class LD, class ST, bool APPLIED = false>
   static void refine_mfma(const DevProblem& dp, const LD& ld, const ST& store, double tol, hipStream_t st) {
     using TL = Tiling64<F::S, F::I>;
     const ResidArgs ra = resid_args(dp, tol, 1);
     int tpg, groups;
-    mfma_groups(dp.mesh.nel, TL::TS, res_refine<LD, ST>(), tpg, groups);
-    hipLaunchKernelGGL((k_refine_mfma<F, LD, ST>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, ld,
+    mfma_groups(dp.mesh.nel, TL::TS, res_refine<LD, ST, APPLIED>(), tpg, groups);
+    hipLaunchKernelGGL((k_refine_mfma<F, LD, ST, APPLIED>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, ld,
                        (const double*)dp.g, dp.Tf64, dp.s[0], dp.s[1], store, ra, tpg);
+  }
+  // A refinement after the segment's first: where the refinement shares element tiles
+  // among wavefronts (the wide families), s' = s + correction is applied by a streaming
+  // kernel first and the refinement gathers s' alone; elsewhere the refinement gathers
+  // both and adds them itself.
+  template <class LDD, class ST>
+  static void refine_corrected(const DevProblem& dp, const LDD& d, const ST& store, double tol, hipStream_t st) {
+    const size_t ne = (size_t)dp.mesh.nel;
+    if constexpr (Tiling64<F::S, F::I>::WPG > 1) {
+      hipLaunchKernelGGL((k_apply_correction<F, LDD>), dim3((dp.mesh.nel + 255) / 256), dim3(256), 0, st,
+                         (const Ctrl*)dp.ctrl, dp.s[0], dp.s[1], d, dp.mesh.nel);
+      refine_mfma<Ld64, ST, true>(dp, Ld64{dp.s[0], ne}, store, tol, st);
+    } else {
+      refine_mfma(dp, LdSum<LDD>{Ld64{dp.s[0], ne}, d, 1}, store, tol, st);
+    }
   }
   static void inner32(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
     using TL = typename Inner32Tiling<F>::TL;
@@ -1530,8 +1573,7 @@ struct Bf16Ops<F, true> {
     const size_t ne = (size_t)dp.mesh.nel;
     const StAos16<F::S> store{(uint16_t*)r_out};
     if (lo_in)
-      Family<F>::refine_mfma(dp, LdSum<Ld16Aos<F::S>>{Ld64{dp.s[0], ne}, Ld16Aos<F::S>{(const uint16_t*)lo_in}, 1},
-                             store, tol, st);
+      Family<F>::refine_corrected(dp, Ld16Aos<F::S>{(const uint16_t*)lo_in}, store, tol, st);
     else
       Family<F>::refine_mfma(dp, Ld64{dp.s[0], ne}, store, tol, st);
   }
