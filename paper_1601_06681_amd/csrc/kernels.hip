@@ -931,11 +931,29 @@ __global__ __launch_bounds__(256) void k_apply_correction(const Ctrl* ctrl, doub
   const double* __restrict__ s = parity ? s1 : s0;
   double* __restrict__ out = parity ? s0 : s1;
   const bool use = ch.iters > 0;
+  if constexpr (std::is_same_v<LDD, Ld16Aos<F::S>> && F::S % 8 == 0) {
+    // the element's S BF16 values are contiguous and 16-byte aligned (S * 2 bytes per
+    // element, 256-byte aligned buffer): 16-byte loads of 8 values each
+    const uint4* __restrict__ q = reinterpret_cast<const uint4*>(d.p + (size_t)e * F::S);
+#pragma unroll 2
+    for (int c = 0; c < F::S / 8; ++c) {
+      const uint4 v4 = q[c];
+      const uint32_t wd[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const size_t i = (size_t)(8 * c + h) * nel + e;
+        const double v = s[i];
+        const uint16_t b = (uint16_t)(wd[h >> 1] >> (16 * (h & 1)));
+        out[i] = use ? v + (double)bf16_to_f32(b) : v;
+      }
+    }
+  } else {
 #pragma unroll 8
-  for (int r = 0; r < F::S; ++r) {
-    const size_t i = (size_t)r * nel + e;
-    const double v = s[i];
-    out[i] = use ? v + (double)d(r, e) : v;
+    for (int r = 0; r < F::S; ++r) {
+      const size_t i = (size_t)r * nel + e;
+      const double v = s[i];
+      out[i] = use ? v + (double)d(r, e) : v;
+    }
   }
 }
 
