@@ -271,6 +271,20 @@ def test_bf16_mfma_refine_negative_beta_ragged():
     assert rel_err(_gpu_u(prob), ref["u"]) < 1e-8
 
 
+@pytest.mark.parametrize("n,p,beta", [((7, 5, 3), 3, (-0.6, 0.8, -1.0)), ((6, 5, 4), 2, (1.0, -0.5, 0.25))])
+def test_fp32_refine_transport3d_ragged(n, p, beta):
+    """3D FP32 correction form reaches the FP64 fixed point within 1e-8 relative: degree 3
+    (the refinement after a segment's first applies the correction in its own kernel and
+    gathers the corrected state) and degree 2 (the refinement adds the correction in its
+    gather); element counts not a multiple of 16."""
+    op, F, _, _ = oracle_transport(n, (1.0, 0.9, 0.8), p, beta, 0.5)
+    ref = O.solve(op, F, np.zeros((op.mesh.nel, op.ref.Np)), tol=1e-14, max_iter=20000)
+    prob = gpu_transport(n, (1.0, 0.9, 0.8), p, beta, 0.5, precision=1, inner=4)
+    rc, iters, res = prob.solve(1e-11, 50000)
+    assert res < 1e-11
+    assert rel_err(_gpu_u(prob), ref["u"]) < 1e-8
+
+
 def test_bf16_refine_unsupported_elsewhere():
     from paper_1601_06681_amd import ehdg as E
     with pytest.raises(E.EhdgError) as ei:
