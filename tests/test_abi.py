@@ -93,3 +93,24 @@ def test_variable_workspace_bytes():
     with pytest.raises(E.EhdgError) as ei:
         E.ehdg_variable_workspace_bytes(E.make_desc(E.EHDG_SWE, 2, (8, 8), degree=2, dt=1e-3))
     assert ei.value.code == 2
+
+
+@pytest.mark.parametrize("pde,dim,n,kw,code", [
+    (0, 2, (0, 4), dict(degree=2, beta=(1, 0.5)), 1),                  # empty mesh
+    (0, 2, (-3, 4), dict(degree=2, beta=(1, 0.5)), 1),                 # negative size
+    (0, 3, (2048, 2048, 2048), dict(degree=3, beta=(1, 0.5, 0.2)), 1),  # element index past 32 bits
+    (0, 2, (4, 4), dict(degree=2, beta=(1, 0.5), precision=7), 1),     # unknown precision code
+    (0, 2, (4, 4), dict(degree=2, beta=(1, 0.5), precision=1, inner_sweeps=0), 1),
+    (0, 2, (4, 4), dict(degree=0, beta=(1, 0.5)), 2),                  # degree below 1
+    (9, 2, (4, 4), dict(degree=2, beta=(1, 0.5)), 2),                  # unknown problem family
+    (1, 3, (4, 4, 4), dict(degree=2, Phi=1.0, dt=1e-3), 2),            # shallow water is 2D
+    (0, 2, (4, 4), dict(degree=2, beta=(1, 0.5), sigma=-1.0), 2),      # negative reaction
+])
+def test_descriptor_edge_cases_are_rejected(pde, dim, n, kw, code):
+    """Malformed sizes and codes are INVALID_ARG (1); well-formed problems outside the
+    supported set are UNSUPPORTED (2).  Nothing is allocated or launched."""
+    from paper_1601_06681_amd import ehdg as E
+    assert (E.EHDG_TRANSPORT, E.EHDG_SWE) == (0, 1)
+    with pytest.raises(E.EhdgError) as ei:
+        E.ehdg_workspace_bytes(E.make_desc(pde, dim, n, **kw))
+    assert ei.value.code == code
