@@ -75,7 +75,10 @@ typedef struct {
   double L[3];          /* domain [0, L_a] per axis, L_a > 0                          */
   int32_t periodic[3];  /* 1 = periodic axis; 0 = boundary: transport inflow data /
                            outflow; SWE reflecting wall; Euler no incoming waves     */
-  int32_t degree;       /* p: transport 2D 1..6, 3D 1..4; SWE 1..6; Euler 1..5        */
+  int32_t degree;       /* p: transport 2D 1..6, 3D 1..4; SWE 1..6; Euler 1..5.
+                           2D transport of degree 1 with both velocity components
+                           non-zero returns UNSUPPORTED: its kernels are switched off
+                           while a device failure recorded against them is unexplained */
   double beta[3];       /* transport velocity (components may be 0)                  */
   double sigma;         /* transport reaction coefficient, >= 0                       */
   double Phi;           /* SWE mean geopotential, > 0                                 */
@@ -162,21 +165,35 @@ int ehdg_set_initial(ehdg_handle h, const double* d_u0);
  * ||s^{k+1} - s^k||_2 / ||s^{k+1}||_2 is recorded (ehdg_get_residuals). */
 int ehdg_iterate(ehdg_handle h, int32_t n_iters);
 
-/* Synchronous: sweeps until the relative trace increment is below rel_tol (checked
- * after every sweep on the device), then recovers the element solution from the
- * last local solve.  *iters = local solves performed in this call; *rel_res = the
- * last increment.  Returns EHDG_ERR_NOT_CONVERGED after max_iters sweeps,
- * EHDG_ERR_DIVERGED if the increment became non-finite.  Backward-Euler handles:
- * solves the current step's system (use ehdg_step to advance in time). */
+/* Synchronous: Algorithm 1 run to convergence.  Sweeps (step 2: the local equations
+ * eq. transportLocalk1 / the shallow-water local solver; step 3: new traces by eq.
+ * transportLocale / the shallow-water trace formula) until the convergence check of
+ * step 4 holds: the relative trace increment ||s^{k+1} - s^k||_2 / ||s^{k+1}||_2 is
+ * below rel_tol (the paper leaves the check's norm open; this one is evaluated on the
+ * device after every sweep).  Then recovers the element solution from the last local
+ * solve.  *iters = local solves performed in this call (the initial trace of the
+ * algorithm's first line is not counted); *rel_res = the last increment.  Returns
+ * EHDG_ERR_NOT_CONVERGED after max_iters sweeps (outputs valid), EHDG_ERR_DIVERGED if
+ * the increment became non-finite.  Backward-Euler handles: solves the current step's
+ * system (use ehdg_step to advance in time). */
 int ehdg_solve(ehdg_handle h, double rel_tol, int32_t max_iters, int32_t* iters, double* rel_res);
 
-/* Synchronous: n_steps backward-Euler steps, each solved to rel_tol from the
- * previous step's traces (warm start).  iters_per_step: host int32_t[n_steps] or NULL. */
+/* Synchronous: n_steps backward-Euler steps.  Each step is the steady iteration with the
+ * extra L2 term of the time-dependent paragraph of Section 3 (M/dt in the local operator,
+ * M u^m / dt in the right-hand side), solved to rel_tol as in ehdg_solve, starting from
+ * the previous step's traces: the warm start of Section 4.4, which keeps the count per
+ * step small.  After a step converges its element solution becomes u^{m+1}.
+ * iters_per_step: host int32_t[n_steps] or NULL; entries of steps not completed are 0.
+ * Returns EHDG_ERR_NOT_CONVERGED if a step reached max_iters_per_step (the completed
+ * steps stand), EHDG_ERR_DIVERGED on a non-finite increment.  Any n_steps >= 0 is
+ * accepted (counts are read back batch by batch, so none is lost to the device ring). */
 int ehdg_step(ehdg_handle h, int32_t n_steps, double rel_tol, int32_t max_iters_per_step,
               int32_t* iters_per_step);
 
-/* Asynchronous: the element solution of the current iterate (the last local solve,
- * or the initial / previous-step state if no sweep ran since) into d_u [n_el][m][N_p]. */
+/* Asynchronous: the element solution of the current iterate into d_u [n_el][m][N_p]:
+ * u^{k+1} of Algorithm 1, i.e. the last local solve (eq. transportLocalk1 with the
+ * traces it read), or the initial / current time level's state if no sweep ran since.
+ * Recovering it costs one element-local solve; the sweeps themselves only carry traces. */
 int ehdg_get_solution(ehdg_handle h, double* d_u);
 
 /* Synchronous: residual history of sweeps [first, first+count) since the last
