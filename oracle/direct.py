@@ -14,6 +14,8 @@ sparse LU (scipy.sparse.linalg.spsolve):
   the upwind flux beta.n u^upwind for transport and the exact Riemann (Godunov)
   flux for shallow water.  It is built from textbook fluxes, not from the HDG
   formulas, so agreement with the eHDG limit checks the trace formulas themselves.
+  For a velocity field beta(x) (dg_transport_variable) the DG form is the strong one,
+  with no div(beta) term, so agreement also checks the HDG operator's volume term.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -274,3 +276,81 @@ def dg_swe(op, F):
                 add(e * n, el * n, B)
     Amat = sp.csr_matrix((vals, (rows, cols)), shape=(mesh.nel * n,) * 2)
     return spla.spsolve(Amat.tocsc(), F.reshape(-1)).reshape(mesh.nel, n)
+
+
+# --------------------------------------------------------------------------------
+# transport (variable beta): classical upwind DG in strong form
+# --------------------------------------------------------------------------------
+def dg_transport_variable(op, F):
+    """Classical upwind DG for beta.grad u + react u = f with a velocity field beta(x).
+
+    Strong (non-integrated) form of Lesaint-Raviart / Johnson-Pitkaranta type: on every
+    element K and for every test function v,
+
+        (beta.grad u + react u, v)_K + sum over inflow points of dK of
+            |beta.n| (u^- - u^ext) v  =  (f, v)_K,
+
+    where a face quadrature point is an inflow point of K when beta(x).n^- < 0 there,
+    u^ext is the upwind neighbour's polynomial at the same physical point, or on the
+    domain boundary the L2 projection of g onto the face polynomials (the same data
+    the HDG trace carries).  Nothing here uses div(beta), the HDG lifts or a trace
+    unknown: the paper's local equation eq. transportLocal integrates by parts to this
+    form pointwise (its volume term -(u, div(beta v)) becomes (beta.grad u, v) minus
+    <beta.n u, v> on dK), so where the quadrature integrates both forms exactly
+    (polynomial beta of low degree) the eHDG fixed point equals this solve to rounding,
+    and a wrong sign or factor on the div(beta) term of the HDG operator shows up as a
+    mismatch.  op: a variable-beta Transport (its mesh, reference element, beta, react,
+    boundary data g).  Returns U (nel, Np).
+    """
+    mesh, ref, d = op.mesh, op.ref, op.d
+    Np = ref.Np
+    nel = mesh.nel
+    h = mesh.h
+    Psi = ref.basis(ref.xi_q)                                   # (Nq, Np)
+    G = ref.grad_basis(ref.xi_q)                                # d x (Nq, Np)
+    wq = ref.w_q * op.J
+    Xq = mesh.physical(np.arange(nel), ref.xi_q)                # (nel, Nq, d)
+    B = op.beta(Xq)                                             # (nel, Nq, d)
+    # (beta.grad psi_j, psi_i)_K + react (psi_j, psi_i)_K per element
+    dpsi = np.stack([G[a] * (2.0 / h[a]) for a in range(d)], axis=-1)      # (Nq, Np, d)
+    bgrad = np.einsum("eqa,qja->eqj", B, dpsi)                            # beta.grad psi_j
+    Avol = np.einsum("q,eqj,qi->eij", wq, bgrad, Psi) + op.react * np.einsum("q,qj,qi->ij", wq, Psi, Psi)[None]
+    nbr = [mesh.neighbour(f) for f in range(2 * d)]
+    rows, cols, vals = [], [], []
+    rhs = F.reshape(-1).copy()
+
+    def add(r0, c0, M):
+        ii, jj = np.nonzero(M)
+        rows.extend(r0 + ii)
+        cols.extend(c0 + jj)
+        vals.extend(M[ii, jj])
+
+    for e in range(nel):
+        add(e * Np, e * Np, Avol[e])
+    for f in range(2 * d):
+        pts, w = ref.face_quadrature(f)
+        Jf = np.prod([h[a] / 2.0 for a in range(d) if a != f // 2]) if d > 1 else 1.0
+        wf = w * Jf
+        Pm = ref.basis(pts)                                     # own basis at the face points
+        pts_o = pts.copy()
+        pts_o[:, f // 2] = -pts[:, f // 2]
+        Po = ref.basis(pts_o)                                   # neighbour's basis, same points
+        Mu = ref.face_trace_basis(f, pts)                       # face polynomials (for g's projection)
+        Mf = np.einsum("q,qa,qb->ab", wf, Mu, Mu)
+        nvec = mesh.normal(f)
+        Xf = mesh.physical(np.arange(nel), pts)                 # (nel, nqf, d)
+        bn = op.beta(Xf) @ nvec                                 # (nel, nqf)
+        wt = np.where(bn < 0, -bn, 0.0) * wf[None]              # |beta.n| w at inflow points
+        for e in range(nel):
+            if not np.any(wt[e]):
+                continue
+            add(e * Np, e * Np, np.einsum("q,qi,qj->ij", wt[e], Pm, Pm))
+            nb = nbr[f][e]
+            if nb >= 0:
+                add(e * Np, nb * Np, -np.einsum("q,qi,qj->ij", wt[e], Pm, Po))
+            elif op.g is not None:
+                gq = op.g(Xf[e:e + 1])[0]                       # g at the face points
+                coef = np.linalg.solve(Mf, Mu.T @ (wf * gq))    # L2 projection onto the face space
+                rhs[e * Np:(e + 1) * Np] += np.einsum("q,qi,q->i", wt[e], Pm, Mu @ coef)
+    Amat = sp.csr_matrix((vals, (rows, cols)), shape=(nel * Np,) * 2)
+    return spla.spsolve(Amat.tocsc(), rhs).reshape(nel, Np)
