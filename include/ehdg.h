@@ -63,10 +63,18 @@ enum { EHDG_TRANSPORT = 0, EHDG_SWE = 1, EHDG_EULER = 2 };
  *                      an FP64 residual of the fixed-point equation, its norm and
  *                      the update of the iterate stay in FP64 on the GPU.
  *   EHDG_BF16_REFINE   as above with BF16 operands on MFMA (FP32 accumulation).
+ *   EHDG_FP32          plain sweeps in FP32: traces, g and the condensed operator in
+ *                      FP32 (matrix cores, FP32 accumulation); only the increment norms
+ *                      of the stopping test are accumulated in FP64.  The element
+ *                      solution is recovered in FP64 from the FP32 traces.  Its result
+ *                      differs from the FP64 fixed point by FP32 rounding of the operator,
+ *                      data and traces (about 1e-6 relative): a rel_tol below about 1e-7
+ *                      buys no accuracy (the rounded iteration stalls there, or reaches an
+ *                      exact fixed point of the rounded map).  Not in batches.
  * With s inner sweeps per refinement and exact arithmetic, one refinement equals
  * s plain sweeps (the method is linear; Section 3, reduction to the homogeneous
  * problem). */
-enum { EHDG_FP64 = 0, EHDG_FP32_REFINE = 1, EHDG_BF16_REFINE = 2 };
+enum { EHDG_FP64 = 0, EHDG_FP32_REFINE = 1, EHDG_BF16_REFINE = 2, EHDG_FP32 = 3 };
 
 typedef struct {
   int32_t pde;          /* EHDG_TRANSPORT, EHDG_SWE or EHDG_EULER                     */
@@ -87,7 +95,7 @@ typedef struct {
   double c0;            /* Euler sound speed, > 0                                     */
   double rho0;          /* Euler mean density, > 0                                    */
   double dt;            /* backward-Euler step; 0 = steady (transport only)           */
-  int32_t precision;    /* EHDG_FP64 / EHDG_FP32_REFINE / EHDG_BF16_REFINE            */
+  int32_t precision;    /* EHDG_FP64 / EHDG_FP32_REFINE / EHDG_BF16_REFINE / EHDG_FP32 */
   int32_t inner_sweeps; /* low-precision sweeps per FP64 refinement (refine modes)    */
 } ehdg_desc;
 

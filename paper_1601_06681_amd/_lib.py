@@ -23,6 +23,7 @@ EHDG_EULER = 2
 EHDG_FP64 = 0
 EHDG_FP32_REFINE = 1
 EHDG_BF16_REFINE = 2
+EHDG_FP32 = 3
 
 EXPORTED = [
     "ehdg_reference_points", "ehdg_workspace_bytes", "ehdg_setup", "ehdg_set_forcing", "ehdg_set_initial",

@@ -85,13 +85,16 @@ struct Layout {
   size_t off_ctrl, off_counters, off_Mf64, off_Tf32, off_partials, off_hist, off_steps, off_T64, off_Tf64, off_T32, off_T16, off_R, off_Q, off_W, off_P,
       off_G,
       off_B, off_Mv, off_gbe;
-  size_t off_s0, off_s1, off_g, off_gsrc, off_wsrc, off_u0, off_u1, off_lo0, off_lo1, off_rlo0, off_rlo1, off_scratch;
+  size_t off_s0, off_s1, off_g, off_g32, off_gsrc, off_wsrc, off_u0, off_u1, off_lo0, off_lo1, off_rlo0, off_rlo1,
+      off_scratch;
   size_t off_Tv, off_Rv, off_Wv;
   size_t total;
 };
 
-// var: room for the per-element operators of a variable velocity
-Layout layout_for(const Operators& o, long long nel, bool lowp, bool var = false) {
+// lowp: room for the correction and residual of the refinement forms; plain32: g in FP32
+// (the FP32 state lives in the first half of the FP64 state buffers); var: room for the
+// per-element operators of a variable velocity
+Layout layout_for(const Operators& o, long long nel, bool lowp, bool plain32 = false, bool var = false) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -127,6 +130,7 @@ Layout layout_for(const Operators& o, long long nel, bool lowp, bool var = false
   L.off_s0 = take(S * ne * 8);
   L.off_s1 = take(S * ne * 8);
   L.off_g = take(S * ne * 8);
+  L.off_g32 = take(plain32 ? S * ne * 4 : 8);
   L.off_gsrc = take(S * ne * 8);
   L.off_wsrc = take(n * ne * 8);
   L.off_u0 = take(n * ne * 8);
@@ -161,8 +165,9 @@ std::string validate(const ehdg_desc* d) {
   for (int a = 0; a < d->dim; ++a)
     if (d->n[a] < 1) return "n[a] must be >= 1";
   if (nel_of(d) > (1LL << 31) - 1024) return "too many elements";
-  if (d->precision < EHDG_FP64 || d->precision > EHDG_BF16_REFINE) return "unknown precision";
-  if (d->precision != EHDG_FP64 && d->inner_sweeps < 1) return "inner_sweeps must be >= 1";
+  if (d->precision < EHDG_FP64 || d->precision > EHDG_FP32) return "unknown precision";
+  if ((d->precision == EHDG_FP32_REFINE || d->precision == EHDG_BF16_REFINE) && d->inner_sweeps < 1)
+    return "inner_sweeps must be >= 1";
   return "";
 }
 
@@ -210,15 +215,31 @@ int sync_ctrl(ehdg_problem* h) {
 double* u_cur(ehdg_problem* h) { return h->dp.u2[h->mirror.ucur & 1]; }
 double* u_other(ehdg_problem* h) { return h->dp.u2[(h->mirror.ucur & 1) ^ 1]; }
 
-// g for the current time level: steady g = g_src; backward Euler g = g_src + G u
+// g for the current time level: steady g = g_src; backward Euler g = g_src + G u (and
+// its FP32 copy in the plain FP32 form)
 void rebuild_g(ehdg_problem* h) {
   DevProblem& dp = h->dp;
   const size_t cnt = (size_t)dp.S * dp.mesh.nel;
   hipMemcpyAsync(dp.g, dp.g_src, cnt * 8, hipMemcpyDeviceToDevice, h->stream);
   if (dp.be) launch_matvec(dp.G, dp.S, dp.n, u_cur(h), dp.g, dp.mesh.nel, true, h->stream);
+  if (dp.g32) launch_cast(dp.g, dp.g32, cnt, 0, h->stream);
 }
 
-bool mixed(const ehdg_problem* h) { return h->desc.precision != EHDG_FP64; }
+// refinement forms (low-precision correction sweeps inside FP64 refinements)
+bool mixed(const ehdg_problem* h) {
+  return h->desc.precision == EHDG_FP32_REFINE || h->desc.precision == EHDG_BF16_REFINE;
+}
+// plain FP32 form: FP32 state, g and sweeps, FP64 stopping test and recovery
+bool plain32(const ehdg_problem* h) { return h->desc.precision == EHDG_FP32; }
+
+// element solution of the local solve that read state buffer `buf` into u_other
+void recover(ehdg_problem* h, int buf) {
+  DevProblem& dp = h->dp;
+  if (plain32(h))
+    h->ks->volume32(dp, (const float*)dp.s[buf & 1], u_cur(h), u_other(h), h->stream);
+  else
+    h->ks->volume(dp, dp.s[buf & 1], u_cur(h), u_other(h), h->stream);
+}
 
 // queues one outer iteration: a plain sweep, or a refinement with its inner sweeps
 struct Outer {
@@ -228,7 +249,7 @@ struct Outer {
   void queue(double tol) {
     DevProblem& dp = h->dp;
     if (!mixed(h)) {
-      h->ks->sweep64(dp, tol, ++h->seq, h->stream);
+      (plain32(h) ? h->ks->sweep32 : h->ks->sweep64)(dp, tol, ++h->seq, h->stream);
       return;
     }
     const bool bf = h->desc.precision == EHDG_BF16_REFINE;
@@ -261,7 +282,7 @@ int run_segment(ehdg_problem* h, double tol, int max_outer) {
     const int n = std::min(chunk, max_outer - launched);
     for (int j = 0; j < n; ++j) o.queue(tol);
     launched += n;
-    // FP64 sweeps leave their own stopping test to the next launch: take the last one
+    // plain sweeps leave their own stopping test to the next launch: take the last one
     if (!mixed(h)) launch_reduce_lagged(h->dp, tol, h->seq + 1, h->stream);
     int rc = check_launch(h);
     if (rc) return rc;
@@ -302,7 +323,8 @@ int ehdg_workspace_bytes(const ehdg_desc* desc, size_t* bytes) {
   Operators ops;
   std::string e = build_operators(to_desc(desc), ops);
   if (!e.empty() || held_family(desc, ops.na)) return EHDG_ERR_UNSUPPORTED;
-  *bytes = layout_for(ops, nel_of(desc), desc->precision != EHDG_FP64).total;
+  const bool lowp = desc->precision == EHDG_FP32_REFINE || desc->precision == EHDG_BF16_REFINE;
+  *bytes = layout_for(ops, nel_of(desc), lowp, desc->precision == EHDG_FP32).total;
   return EHDG_OK;
 }
 
@@ -329,14 +351,14 @@ static int setup_impl(const ehdg_desc* desc, const VarSamples* smp, void* d_work
   const Operators& o = h->ops;
   h->ks = smp ? find_var_kernels(desc->dim, o.na, desc->degree)
               : find_kernels(desc->pde, desc->dim, desc->pde == 0 ? o.na : 0, desc->degree);
-  const bool lowp = desc->precision != EHDG_FP64;
+  const bool lowp = desc->precision == EHDG_FP32_REFINE || desc->precision == EHDG_BF16_REFINE;
   if (!h->ks || (desc->precision == EHDG_BF16_REFINE && !h->ks->refine16) ||
-      (desc->precision == EHDG_FP32_REFINE && !h->ks->refine32)) {
+      (desc->precision == EHDG_FP32_REFINE && !h->ks->refine32) || (desc->precision == EHDG_FP32 && !h->ks->sweep32)) {
     delete h;
     return EHDG_ERR_UNSUPPORTED;
   }
   const long long nel = nel_of(desc);
-  Layout L = layout_for(o, nel, lowp, h->var);
+  Layout L = layout_for(o, nel, lowp, desc->precision == EHDG_FP32, h->var);
   if (workspace_bytes < L.total) {
     delete h;
     return EHDG_ERR_WORKSPACE_TOO_SMALL;
@@ -369,7 +391,7 @@ static int setup_impl(const ehdg_desc* desc, const VarSamples* smp, void* d_work
   dp.partial_stride = (int)((L.off_hist - L.off_partials) / sizeof(double) / 2);
   if (h->ks->sweep_groups) {
     int tpg = 0, groups = 0;
-    h->ks->sweep_groups((int)nel, &tpg, &groups);
+    (desc->precision == EHDG_FP32 ? h->ks->sweep32_groups : h->ks->sweep_groups)((int)nel, &tpg, &groups);
     dp.nb_sweep = groups;
   } else {
     dp.nb_sweep = (int)var_sweep_groups(nel, o.S);
@@ -397,6 +419,7 @@ static int setup_impl(const ehdg_desc* desc, const VarSamples* smp, void* d_work
   dp.s[0] = (double*)(ws + L.off_s0);
   dp.s[1] = (double*)(ws + L.off_s1);
   dp.g = (double*)(ws + L.off_g);
+  dp.g32 = desc->precision == EHDG_FP32 ? (float*)(ws + L.off_g32) : nullptr;
   dp.g_src = (double*)(ws + L.off_gsrc);
   dp.w_src = (double*)(ws + L.off_wsrc);
   dp.u2[0] = (double*)(ws + L.off_u0);
@@ -478,7 +501,7 @@ int ehdg_variable_workspace_bytes(const ehdg_desc* desc, size_t* bytes) {
   Operators ops;
   std::string e = build_variable_operators(to_desc(desc), nullptr, ops, nullptr);
   if (!e.empty() || held_family(desc, ops.na)) return EHDG_ERR_UNSUPPORTED;
-  *bytes = layout_for(ops, nel_of(desc), false, true).total;
+  *bytes = layout_for(ops, nel_of(desc), false, false, true).total;
   return EHDG_OK;
 }
 
@@ -541,7 +564,13 @@ int ehdg_set_initial(ehdg_handle h, const double* d_u0) {
     launch_ext_to_soa(d_u0, dp.u2[0], dp.n, nel, h->stream);
   else
     launch_fill(dp.u2[0], 0.0, (size_t)dp.n * nel, h->stream);
-  launch_matvec(h->Q, dp.S, dp.n, dp.u2[0], dp.s[0], nel, false, h->stream);
+  if (dp.g32) {
+    // plain FP32 form: the initial trace in FP32, in the first half of state buffer 0
+    launch_matvec(h->Q, dp.S, dp.n, dp.u2[0], h->scratch, nel, false, h->stream);
+    launch_cast(h->scratch, (float*)dp.s[0], (size_t)dp.S * nel, 0, h->stream);
+  } else {
+    launch_matvec(h->Q, dp.S, dp.n, dp.u2[0], dp.s[0], nel, false, h->stream);
+  }
   rebuild_g(h);
   h->recovered = -1;
   return check_launch(h);
@@ -549,10 +578,11 @@ int ehdg_set_initial(ehdg_handle h, const double* d_u0) {
 
 int ehdg_iterate(ehdg_handle h, int32_t n_iters) {
   if (!h || n_iters < 0) return EHDG_ERR_INVALID_ARG;
-  if (mixed(h)) return fail(h, EHDG_ERR_UNSUPPORTED, "iterate runs the FP64 sweep");
+  if (mixed(h)) return fail(h, EHDG_ERR_UNSUPPORTED, "iterate runs the plain (FP64 or FP32) sweep");
   // a finished solve is continued in a new segment from its last iterate (on the device)
   launch_ctrl_reset(h->dp.ctrl, 2, h->seq + 1, h->stream);
-  for (int j = 0; j < n_iters; ++j) h->ks->sweep64(h->dp, -1.0, ++h->seq, h->stream);
+  auto sweep = plain32(h) ? h->ks->sweep32 : h->ks->sweep64;
+  for (int j = 0; j < n_iters; ++j) sweep(h->dp, -1.0, ++h->seq, h->stream);
   // the last sweep's increment is recorded by the next launch: take it now
   if (n_iters > 0) launch_reduce_lagged(h->dp, -1.0, h->seq + 1, h->stream);
   h->recovered = -1;
@@ -575,7 +605,7 @@ int ehdg_solve(ehdg_handle h, double rel_tol, int32_t max_iters, int32_t* iters,
   if (c.iters > 0 && c.status != 2) {
     // plain: u^K is the local solve that read s^{K-1}; refinement: the refined iterate s^K
     const int lag = mixed(h) ? 0 : 1;
-    h->ks->volume(dp, dp.s[(c.base + c.iters - lag) & 1], u_cur(h), u_other(h), h->stream);
+    recover(h, (c.base + c.iters - lag) & 1);
     int rc2 = check_launch(h);
     if (rc2) return rc2;
     h->recovered = 1;
@@ -616,7 +646,7 @@ int ehdg_step(ehdg_handle h, int32_t n_steps, double rel_tol, int32_t max_iters_
     const int per = std::min(p + 1 + (p + 7) / 8, max_outer);
     for (int r = 0; r < remaining; ++r) {
       for (int j = 0; j < per; ++j) o.queue(rel_tol);
-      h->ks->step(dp, lag, h->seq + 1, rel_tol, mixed(h) ? 0 : 1, h->stream);
+      (plain32(h) ? h->ks->step32 : h->ks->step)(dp, lag, h->seq + 1, rel_tol, mixed(h) ? 0 : 1, h->stream);
     }
     rc = check_launch(h);
     if (rc) return rc;
@@ -655,7 +685,7 @@ int ehdg_get_solution(ehdg_handle h, double* d_u) {
   if (h->recovered == 1) {
     src = u_other(h);
   } else if (c.iters > 0 && !mixed(h)) {
-    h->ks->volume(dp, dp.s[(c.base + c.iters - 1) & 1], u_cur(h), u_other(h), h->stream);
+    recover(h, (c.base + c.iters - 1) & 1);
     h->recovered = 1;
     src = u_other(h);
   }
@@ -827,7 +857,7 @@ int batch_check(const ehdg_handle* handles, int32_t n, std::vector<ehdg_problem*
   for (int i = 0; i < n; ++i) {
     if (!handles[i]) return EHDG_ERR_INVALID_ARG;
     if (std::find(hs.begin(), hs.end(), handles[i]) != hs.end()) return EHDG_ERR_INVALID_ARG;
-    if (mixed(handles[i]) || handles[i]->var) return EHDG_ERR_UNSUPPORTED;
+    if (handles[i]->desc.precision != EHDG_FP64 || handles[i]->var) return EHDG_ERR_UNSUPPORTED;
     hs.push_back(handles[i]);
   }
   return EHDG_OK;

@@ -78,6 +78,7 @@ struct DevProblem {
   bool has_src;            // forcing or boundary data present (w_src, g_src nonzero)
   double* s[2];            // trace state, double buffered
   double* g;               // S
+  float* g32;              // S: g in FP32 (plain FP32 precision only)
   double* g_src;           // S
   double* w_src;           // n
   double* u2[2];           // n: solution buffers; u2[ucur] is the current time level
@@ -161,6 +162,15 @@ struct KernelSet {
   // family: n entries of table, problems in probs (device memory)
   void (*sweep64_batch)(const BatchEntry* table, int n, const BatchProblem* probs, double tol, hipStream_t);
   void (*step_batch)(const BatchEntry* table, int n, const BatchProblem* probs, int lag, hipStream_t);
+  // plain FP32 form: the sweep s^{k+1} = g + T in(s^k) on FP32 state and g (FP32
+  // matrix cores), with the FP64 increment norms and the lagged stopping test of the
+  // FP64 sweep (same partial sets and launch numbering; the state buffers s[0], s[1]
+  // hold floats); recovery and step completion read the FP32 state (FP64 arithmetic,
+  // the next g written in FP32 to g32)
+  void (*sweep32)(const DevProblem&, double tol, unsigned seq, hipStream_t);
+  void (*volume32)(const DevProblem&, const float* s_prev, const double* u_old, double* u_out, hipStream_t);
+  void (*step32)(const DevProblem&, int lag, unsigned seq_next, double tol, int lagged, hipStream_t);
+  void (*sweep32_groups)(int nel, int* tiles_per_group, int* groups);
 };
 
 const KernelSet* find_kernels(int pde, int dim, int na, int nf);

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace ehdg {
 
@@ -110,6 +111,10 @@ struct Ld16Aos {  // BF16, element-major: the S values of an element are contigu
   const uint16_t* p;
   __device__ __forceinline__ float operator()(int r, int e) const { return bf16_to_f32(p[(size_t)e * S + r]); }
 };
+// loader of a component-major state of element type ST (double or float)
+template <typename ST>
+using LdOf = std::conditional_t<std::is_same_v<ST, float>, Ld32, Ld64>;
+
 // FP64 iterate plus a low-precision correction: s + delta (delta ignored unless use)
 template <class LD>
 struct LdSum {
@@ -851,8 +856,8 @@ struct StAos16 {  // BF16, element-major
 //   steady:          u_new = w_src + R in(s_prev)
 //   backward Euler:  [u_new; g_next] = [w_src; gbe] + [[P, R], [G P, G R]] [u_old; in(s_prev)]
 // (u_new = A^{-1}(F_src + Mbt u_old + L in) and g_next = Q A^{-1}(F_src + Mbt u_new)).
-template <class F, bool BE>
-__device__ __forceinline__ void volume_body(const MeshDev& m, const double* __restrict__ s_prev,
+template <class F, bool BE, typename ST = double>
+__device__ __forceinline__ void volume_body(const MeshDev& m, const ST* __restrict__ s_prev,
                                             const double* __restrict__ Mv, const double* __restrict__ u_old,
                                             const double* __restrict__ w_src, const double* __restrict__ gbe,
                                             double* __restrict__ u_new, double* __restrict__ g_out) {
@@ -882,7 +887,7 @@ __device__ __forceinline__ void volume_body(const MeshDev& m, const double* __re
       if (c < F::N) x[c * kLanes + lane] = v[j];
     }
   }
-  stage_inputs<F, double>(m, es, valid, nb, Ld64{s_prev, nel}, x, BE ? F::N : 0);
+  stage_inputs<F, double>(m, es, valid, nb, LdOf<ST>{s_prev, nel}, x, BE ? F::N : 0);
   __syncthreads();
   const int r0 = w * RW;
   double acc[RW];
@@ -908,13 +913,13 @@ __device__ __forceinline__ void volume_body(const MeshDev& m, const double* __re
   }
 }
 
-template <class F, bool BE>
-__global__ __launch_bounds__(kThreads) void k_volume(MeshDev m, const double* __restrict__ s_prev,
+template <class F, bool BE, typename ST = double>
+__global__ __launch_bounds__(kThreads) void k_volume(MeshDev m, const ST* __restrict__ s_prev,
                                                       const double* __restrict__ Mv,
                                                       const double* __restrict__ u_old,
                                                       const double* __restrict__ w_src,
                                                       const double* __restrict__ gbe, double* __restrict__ u_new) {
-  volume_body<F, BE>(m, s_prev, Mv, u_old, w_src, gbe, u_new, nullptr);
+  volume_body<F, BE, ST>(m, s_prev, Mv, u_old, w_src, gbe, u_new, nullptr);
 }
 
 // s' = s^k + the low-precision correction (from the segment's second refinement on;
@@ -1128,6 +1133,84 @@ __global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_inner32_mfma(
   }
 }
 
+// Plain FP32 sweep on the matrix cores: s_out = g + T in(s_in) with FP32 state, g and
+// operator fragments (v_mfma_f32_16x16x4f32, the correction sweep's tiling), and the
+// stopping test of the FP64 sweep: the increment norms ||s_out - s_in||^2 and
+// ||s_out||^2 are accumulated in FP64 from the FP32 values, left as per-workgroup
+// partial sums for the next launch (lagged test, canonical order), and the previous
+// sweep's test is taken at the start.  Buffers come from the control block and the
+// launch number, as in the FP64 sweep.
+template <class F>
+__global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_sweep32_mfma(
+    MeshDev m, const float* __restrict__ g, const float* __restrict__ Tf, ResidArgs ra, float* s0, float* s1,
+    int tiles_per_group, LagArgs lag) {
+  using TL = typename Inner32Tiling<F>::TL;
+  constexpr int MTW = TL::MTW, KT = TL::KT;
+  const CtrlHead ch = ctrl_head(ra.ctrl);
+  const unsigned seg = ra.ctrl->seg_seq;
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  const int w = wave % TL::WPG, slot = wave / TL::WPG;
+  const int j = lane & 15, kq = lane >> 4;
+  const int bid = (int)blockIdx.x, nbk = (int)gridDim.x;
+  float a[MTW][KT];
+#pragma unroll
+  for (int u = 0; u < MTW; ++u)
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) a[u][kt] = Tf[((w * MTW + u) * KT + kt) * 64 + lane];
+  const int k = lagged_begin<TL::NW>(ra, lag, nbk, bid, ch, seg);
+  if (k == 0) return;
+  const int parity = (ch.base + k - 1) & 1;  // s^(k-1) of the segment
+  const size_t nel = (size_t)m.nel;
+  const Ld32 ld{parity ? s1 : s0, nel};
+  float* __restrict__ out = parity ? s0 : s1;
+  const int ntiles = (m.nel + 15) >> 4;
+  const int t0 = remap_block(bid, nbk) * tiles_per_group;
+  const int t1 = min(t0 + tiles_per_group, ntiles);
+  double d2 = 0.0, n2 = 0.0;
+  for (int t = t0 + slot; t < t1; t += TL::TS) {
+    const int e = t * 16 + j;
+    const bool valid = e < m.nel;
+    const int es = valid ? e : 0;
+    Nb nb;
+    F::neighbours(m, es, nb);
+    float b[KT];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      const int c = 4 * kt + kq;
+      const float v = F::row(m, es, nb, ld, c < F::I ? c : F::I - 1);
+      b[kt] = (valid && c < F::I) ? v : 0.0f;
+    }
+    floatx4_t acc[MTW];
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (w * MTW + u) + 4 * kq + r;
+        const float gv = g[(size_t)(row < F::S ? row : F::S - 1) * nel + es];
+        acc[u][r] = (valid && row < F::S) ? gv : 0.0f;
+      }
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+      for (int u = 0; u < MTW; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][kt], b[kt], acc[u], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (w * MTW + u) + 4 * kq + r;
+        const float old = ld(row < F::S ? row : F::S - 1, es);
+        if (valid && row < F::S) {
+          const float v = acc[u][r];
+          const double dd = (double)v - (double)old;
+          d2 += dd * dd;
+          n2 += (double)v * (double)v;
+          out[(size_t)row * nel + e] = v;
+        }
+      }
+  }
+  lagged_end<TL::NW>(d2, n2, ra, lag, bid);
+}
+
 // The same step completion on the matrix cores: [u_new; g_next] = [w_src; gbe] + M
 // [u_old; in(s_prev)] with the stacked operator M of (N + S) x (N + I) held as
 // fragments (fragment-major copy Mf, laid out like the sweep operator's).
@@ -1154,10 +1237,12 @@ struct StepLag {
   int hist_cap;
 };
 
-template <class F>
-__device__ __forceinline__ void step_mfma_body(MeshDev m, double* s0, double* s1, const double* __restrict__ Mf,
+// ST: element type of the trace state and of g (FP64, or FP32 in the plain FP32 form;
+// the contraction itself is FP64 either way).
+template <class F, typename ST = double>
+__device__ __forceinline__ void step_mfma_body(MeshDev m, ST* s0, ST* s1, const double* __restrict__ Mf,
                                                double* u0, double* u1, const double* __restrict__ w_src,
-                                               const double* __restrict__ gbe, double* __restrict__ g_out,
+                                               const double* __restrict__ gbe, ST* __restrict__ g_out,
                                                Ctrl* ctrl, unsigned* cnt, int* step_iters, int step_cap, int lag,
                                                int tiles_per_group, int bid, int nbk, const StepLag& sl) {
   using TL = typename StepTiling<F>::TL;
@@ -1204,7 +1289,7 @@ __device__ __forceinline__ void step_mfma_body(MeshDev m, double* s0, double* s1
   }
   const int iters = K, base = ch.base, uc = ctrl->ucur;
   const size_t nel = (size_t)m.nel;
-  const Ld64 ld{((base + iters - lag) & 1) ? s1 : s0, nel};
+  const LdOf<ST> ld{((base + iters - lag) & 1) ? s1 : s0, nel};
   const double* __restrict__ u_old = uc ? u1 : u0;
   double* __restrict__ u_new = uc ? u0 : u1;
   const int ntiles = (m.nel + 15) >> 4;
@@ -1233,7 +1318,7 @@ __device__ __forceinline__ void step_mfma_body(MeshDev m, double* s0, double* s1
     if (q < N)
       u_new[(size_t)q * nel + e] = v;
     else if (g_out)
-      g_out[(size_t)(q - N) * nel + e] = v;
+      g_out[(size_t)(q - N) * nel + e] = (ST)v;
   };
   if constexpr (TL::WPG > 1) {
     __shared__ double bt[2 * KT * 4 * 16];
@@ -1300,13 +1385,13 @@ __device__ __forceinline__ void step_mfma_body(MeshDev m, double* s0, double* s1
   }
 }
 
-template <class F>
+template <class F, typename ST = double>
 __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
-    MeshDev m, double* s0, double* s1, const double* __restrict__ Mf, double* u0, double* u1,
-    const double* __restrict__ w_src, const double* __restrict__ gbe, double* __restrict__ g_out, Ctrl* ctrl,
+    MeshDev m, ST* s0, ST* s1, const double* __restrict__ Mf, double* u0, double* u1,
+    const double* __restrict__ w_src, const double* __restrict__ gbe, ST* __restrict__ g_out, Ctrl* ctrl,
     unsigned* cnt, int* step_iters, int step_cap, int lag, int tiles_per_group, StepLag sl) {
-  step_mfma_body<F>(m, s0, s1, Mf, u0, u1, w_src, gbe, g_out, ctrl, cnt, step_iters, step_cap, lag, tiles_per_group,
-                    (int)blockIdx.x, (int)gridDim.x, sl);
+  step_mfma_body<F, ST>(m, s0, s1, Mf, u0, u1, w_src, gbe, g_out, ctrl, cnt, step_iters, step_cap, lag,
+                        tiles_per_group, (int)blockIdx.x, (int)gridDim.x, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1407,6 +1492,14 @@ struct Family {
     static const int r = resident_groups(k_inner32_mfma<F>, 64 * Inner32Tiling<F>::value);
     return r;
   }
+  static int res_sweep32() {
+    static const int r = resident_groups(k_sweep32_mfma<F>, 64 * Inner32Tiling<F>::value);
+    return r;
+  }
+  static int res_step32() {
+    static const int r = resident_groups(k_step_mfma<F, float>, 64 * StepTiling<F>::value);
+    return r;
+  }
   template <class LD, class ST, bool APPLIED = false>
   static int res_refine() {
     static const int r = resident_groups(k_refine_mfma<F, LD, ST, APPLIED>, 64 * Tiling64<F::S, F::I>::NW);
@@ -1421,22 +1514,52 @@ struct Family {
                        Ld64{dp.s[0], (size_t)dp.mesh.nel}, (const double*)dp.g, dp.Tf64, (double*)nullptr, ra,
                        dp.s[0], dp.s[1], tpg, LagArgs{seq, dp.partial_stride});
   }
-  static void volume(const DevProblem& dp, const double* s_prev, const double* u_old, double* u_out,
-                     hipStream_t st) {
+  template <typename ST>
+  static void volume_t(const DevProblem& dp, const ST* s_prev, const double* u_old, double* u_out, hipStream_t st) {
     const dim3 grid(ngroups(dp.mesh.nel)), block(kThreads);
     const double* wsrc = dp.has_src ? dp.w_src : nullptr;
     if (dp.be) {
       const size_t lds = (size_t)(F::N + F::I) * kLanes * 8;
-      auto kern = k_volume<F, true>;
+      auto kern = k_volume<F, true, ST>;
       allow_lds(kern, lds);
       hipLaunchKernelGGL(kern, grid, block, lds, st, dp.mesh, s_prev, dp.Mvol, u_old, wsrc, (const double*)nullptr,
                          u_out);
     } else {
-      auto kern = k_volume<F, false>;
+      auto kern = k_volume<F, false, ST>;
       allow_lds(kern, lds_in64);
       hipLaunchKernelGGL(kern, grid, block, lds_in64, st, dp.mesh, s_prev, dp.Mvol, (const double*)nullptr, wsrc,
                          (const double*)nullptr, u_out);
     }
+  }
+  static void volume(const DevProblem& dp, const double* s_prev, const double* u_old, double* u_out,
+                     hipStream_t st) {
+    volume_t<double>(dp, s_prev, u_old, u_out, st);
+  }
+  static void volume32(const DevProblem& dp, const float* s_prev, const double* u_old, double* u_out,
+                       hipStream_t st) {
+    volume_t<float>(dp, s_prev, u_old, u_out, st);
+  }
+  static void sweep32(const DevProblem& dp, double tol, unsigned seq, hipStream_t st) {
+    using TL = typename Inner32Tiling<F>::TL;
+    const ResidArgs ra = resid_args(dp, tol, tol >= 0.0 ? 1 : 0);
+    int tpg, groups;
+    mfma_groups(dp.mesh.nel, TL::TS, res_sweep32(), tpg, groups);
+    hipLaunchKernelGGL((k_sweep32_mfma<F>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, (const float*)dp.g32,
+                       dp.Tf32, ra, (float*)dp.s[0], (float*)dp.s[1], tpg, LagArgs{seq, dp.partial_stride});
+  }
+  static void sweep32_groups(int nel, int* tpg, int* groups) {
+    using TL = typename Inner32Tiling<F>::TL;
+    mfma_groups(nel, TL::TS, res_sweep32(), *tpg, *groups);
+  }
+  static void step32(const DevProblem& dp, int lag, unsigned seq_next, double tol, int lagged, hipStream_t st) {
+    using TL = typename StepTiling<F>::TL;
+    int tpg, groups;
+    mfma_groups(dp.mesh.nel, TL::TS, res_step32(), tpg, groups);
+    const StepLag sl{lagged, seq_next, tol, dp.partials, dp.partial_stride, dp.nb_sweep, dp.hist, dp.hist_cap};
+    hipLaunchKernelGGL((k_step_mfma<F, float>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, (float*)dp.s[0],
+                       (float*)dp.s[1], dp.Mf64, dp.u2[0], dp.u2[1], (const double*)(dp.has_src ? dp.w_src : nullptr),
+                       (const double*)(dp.has_src ? dp.gbe : nullptr), dp.g32, dp.ctrl, dp.counters + kCounterSet,
+                       dp.step_iters, dp.step_cap, lag, tpg, sl);
   }
   static void sweep_groups(int nel, int* tpg, int* groups) {
     using TL = Tiling64<F::S, F::I>;
@@ -1623,7 +1746,9 @@ static const KernelSet* set_of() {
                                &Family<F>::inner32,       Bf16Ops<F, HasMfmaTiling<F>::value>::refine,
                                Bf16Ops<F, HasMfmaTiling<F>::value>::inner,
                                &Family<F>::sweep_groups,  &Family<F>::step_groups,
-                               &Family<F>::sweep64_batch, &Family<F>::step_batch};
+                               &Family<F>::sweep64_batch, &Family<F>::step_batch,
+                               &Family<F>::sweep32,       &Family<F>::volume32,
+                               &Family<F>::step32,        &Family<F>::sweep32_groups};
   return &ks;
 }
 

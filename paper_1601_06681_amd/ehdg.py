@@ -11,12 +11,12 @@ import numpy as np
 
 from . import _lib
 from ._lib import (EHDG_BF16_REFINE, EHDG_ERR_DIVERGED, EHDG_ERR_HIP, EHDG_ERR_INVALID_ARG, EHDG_ERR_NOT_CONVERGED,
-                   EHDG_ERR_UNSUPPORTED, EHDG_ERR_WORKSPACE_TOO_SMALL, EHDG_FP32_REFINE, EHDG_FP64, EHDG_EULER, EHDG_OK,
+                   EHDG_ERR_UNSUPPORTED, EHDG_ERR_WORKSPACE_TOO_SMALL, EHDG_FP32, EHDG_FP32_REFINE, EHDG_FP64, EHDG_EULER, EHDG_OK,
                    EHDG_SWE, EHDG_TRANSPORT, ehdg_desc)
 
 __all__ = [
     "EhdgError", "Problem", "Batch", "make_desc", *_lib.EXPORTED,
-    "EHDG_TRANSPORT", "EHDG_SWE", "EHDG_EULER", "EHDG_FP64", "EHDG_FP32_REFINE", "EHDG_BF16_REFINE",
+    "EHDG_TRANSPORT", "EHDG_SWE", "EHDG_EULER", "EHDG_FP64", "EHDG_FP32_REFINE", "EHDG_BF16_REFINE", "EHDG_FP32",
 ]
 
 
