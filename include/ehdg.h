@@ -244,6 +244,21 @@ int ehdg_batch_workspace_bytes(const ehdg_handle* handles, int32_t n, size_t* by
 int ehdg_batch_create(const ehdg_handle* handles, int32_t n, void* d_workspace, size_t workspace_bytes,
                       void* stream, ehdg_batch* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops that rebuild batches as members come and go, harnesses that forbid
+ * hipMalloc): ehdg_batch_create without a workspace.  The batch's tables (problem
+ * descriptors, workgroup table, control-block copies: what ehdg_batch_workspace_bytes
+ * sizes) go into a static device array of the library, 8 MiB per GPU, held until the
+ * process ends; the call allocates no device memory.  The array of the current device is
+ * used (call with the members' device current).  Returns EHDG_ERR_WORKSPACE_TOO_SMALL if
+ * the tables need more than 8 MiB (ehdg_batch_workspace_bytes > 8 MiB; use
+ * ehdg_batch_create then), else as ehdg_batch_create.  One array per device means one
+ * static batch per device at a time: creating a static batch replaces the tables of
+ * the previous static batch on that device, whose later calls return
+ * EHDG_ERR_INVALID_ARG (destroy it as usual).  Calls that overlap on one device race on
+ * the array. */
+int ehdg_batch_create_static(const ehdg_handle* handles, int32_t n, void* stream, ehdg_batch* out);
+
 /* Synchronous: ehdg_solve for every member (each to rel_tol, at most max_iters sweeps,
  * then its recovery).  iters, rel_res: host arrays of n, or NULL.  Returns the first
  * non-OK member status in handle order (NOT_CONVERGED / DIVERGED), else OK. */

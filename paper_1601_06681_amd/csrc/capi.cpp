@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -781,6 +782,11 @@ struct ehdg_batch_s {
     const KernelSet* ks;
     int sweep_first, sweep_n, step_first, step_n;
   };
+  // tables in the device's static scratch array (ehdg_batch_create_static): valid while
+  // no later static batch was created on the same device (generation check)
+  bool is_static = false;
+  int dev = 0;
+  unsigned gen = 0;
   std::vector<ehdg_problem*> h;
   hipStream_t stream = nullptr;
   std::vector<Group> groups;
@@ -792,7 +798,30 @@ struct ehdg_batch_s {
   std::string err;
 };
 
+// Device scratch of ehdg_batch_create_static: the batch's problem descriptors, workgroup
+// table and control-block copies (see batch_layout), at most kStaticBatchBytes (8 MiB)
+// per device, held until the process ends.
+constexpr size_t kStaticBatchBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticBatchBytes];
+
 namespace {
+
+// ---- batch tables in a static device array, for callers that cannot allocate
+// One array per GPU (each device holds its own copy of a __device__ variable), found
+// with hipGetSymbolAddress the first time a static batch is created on that device.
+// In host code the array's name is not a device address: only the pointer returned by
+// hipGetSymbolAddress is passed to kernels and copies.
+constexpr int kMaxDevices = 64;
+
+struct StaticScratch {
+  std::mutex mu;
+  void* ptr[kMaxDevices] = {};
+  unsigned gen[kMaxDevices] = {};
+};
+StaticScratch& static_scratch() {
+  static StaticScratch s;
+  return s;
+}
 
 int bfail(ehdg_batch_s* b, int code, const std::string& msg) {
   if (b) b->err = msg;
@@ -893,8 +922,15 @@ int batch_upload(ehdg_batch_s* b, const std::vector<int>& steps_target) {
   return EHDG_OK;
 }
 
-// waits for the members' own streams, so no earlier work on a member is still queued
+// waits for the members' own streams, so no earlier work on a member is still queued;
+// refuses a static batch whose tables a later static batch on its device has replaced
 int batch_quiesce(ehdg_batch_s* b) {
+  if (b->is_static) {
+    StaticScratch& ss = static_scratch();
+    std::lock_guard<std::mutex> lk(ss.mu);
+    if (ss.gen[b->dev] != b->gen)
+      return bfail(b, EHDG_ERR_INVALID_ARG, "static batch replaced by a later ehdg_batch_create_static on its device");
+  }
   for (auto* h : b->h) HIP_TRY_B(b, hipStreamSynchronize(h->stream));
   return EHDG_OK;
 }
@@ -929,14 +965,13 @@ int ehdg_batch_workspace_bytes(const ehdg_handle* handles, int32_t n, size_t* by
   return EHDG_OK;
 }
 
-int ehdg_batch_create(const ehdg_handle* handles, int32_t n, void* d_workspace, size_t workspace_bytes, void* stream,
-                      ehdg_batch* out) {
-  if (!out) return EHDG_ERR_INVALID_ARG;
-  *out = nullptr;
-  std::vector<ehdg_problem*> hs;
-  int rc = batch_check(handles, n, hs);
-  if (rc) return rc;
-  if (!d_workspace || ((uintptr_t)d_workspace & 255)) return EHDG_ERR_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+// ehdg_batch_create's work with the tables at d_workspace (256-byte aligned, bytes long)
+int batch_create_in(std::vector<ehdg_problem*>& hs, void* d_workspace, size_t workspace_bytes, void* stream,
+                    ehdg_batch_s** out) {
   ehdg_batch_s* b = new (std::nothrow) ehdg_batch_s();
   if (!b) return EHDG_ERR_INVALID_ARG;
   b->h = hs;
@@ -961,6 +996,57 @@ int ehdg_batch_create(const ehdg_handle* handles, int32_t n, void* d_workspace, 
     return EHDG_ERR_HIP;
   }
   *out = b;
+  return EHDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ehdg_batch_create(const ehdg_handle* handles, int32_t n, void* d_workspace, size_t workspace_bytes, void* stream,
+                      ehdg_batch* out) {
+  if (!out) return EHDG_ERR_INVALID_ARG;
+  *out = nullptr;
+  std::vector<ehdg_problem*> hs;
+  int rc = batch_check(handles, n, hs);
+  if (rc) return rc;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255)) return EHDG_ERR_INVALID_ARG;
+  return batch_create_in(hs, d_workspace, workspace_bytes, stream, out);
+}
+
+int ehdg_batch_create_static(const ehdg_handle* handles, int32_t n, void* stream, ehdg_batch* out) {
+  if (!out) return EHDG_ERR_INVALID_ARG;
+  *out = nullptr;
+  std::vector<ehdg_problem*> hs;
+  int rc = batch_check(handles, n, hs);
+  if (rc) return rc;
+  {
+    std::vector<ehdg_batch_s::Group> groups;
+    std::vector<BatchEntry> table;
+    batch_plan(hs, groups, table);
+    if (batch_layout(hs.size(), table.size()).total > kStaticBatchBytes) return EHDG_ERR_WORKSPACE_TOO_SMALL;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return EHDG_ERR_HIP;
+  StaticScratch& ss = static_scratch();
+  void* ptr = nullptr;
+  unsigned gen = 0;
+  {
+    std::lock_guard<std::mutex> lk(ss.mu);
+    if (!ss.ptr[dev]) {
+      // once per device, with that device current: the device address of its copy
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return EHDG_ERR_HIP;
+      ss.ptr[dev] = p;
+    }
+    ptr = ss.ptr[dev];
+    gen = ++ss.gen[dev];  // any earlier static batch on this device is now replaced
+  }
+  rc = batch_create_in(hs, ptr, kStaticBatchBytes, stream, out);
+  if (rc) return rc;
+  (*out)->is_static = true;
+  (*out)->dev = dev;
+  (*out)->gen = gen;
   return EHDG_OK;
 }
 

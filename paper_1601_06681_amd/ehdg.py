@@ -231,6 +231,13 @@ def ehdg_batch_create(handles, workspace, stream=None):
     return b
 
 
+def ehdg_batch_create_static(handles, stream=None):
+    b = ctypes.c_void_p()
+    _check(_lib.load().ehdg_batch_create_static(_handle_array(handles), len(handles), _stream_ptr(stream),
+                                                ctypes.byref(b)))
+    return b
+
+
 def ehdg_batch_solve(b, n, rel_tol, max_iters, allow=(EHDG_OK,)):
     its = np.zeros(n, dtype=np.int32)
     res = np.zeros(n)
@@ -272,10 +279,16 @@ def ehdg_batch_last_error(b):
 class Batch:
     """Several Problems advanced together (ehdg_batch_*).  The Problems must outlive it."""
 
-    def __init__(self, problems, stream=None):
-        torch = _torch()
+    def __init__(self, problems, stream=None, static=False):
+        """static: tables in the library's static device array (ehdg_batch_create_static),
+        no workspace allocated; one static batch per device at a time."""
         self.problems = list(problems)
         handles = [p.h for p in self.problems]
+        self.workspace = None
+        if static:
+            self.b = ehdg_batch_create_static(handles, stream)
+            return
+        torch = _torch()
         nbytes = ehdg_batch_workspace_bytes(handles)
         self.workspace = _aligned_bytes(torch, max(nbytes, 256), self.problems[0].device)
         self.b = ehdg_batch_create(handles, self.workspace, stream)
