@@ -227,18 +227,22 @@ int ehdg_destroy(ehdg_handle h);
 /* ---- Batches of independent problems ------------------------------------------
  * Algorithm 1 treats every element independently, so a set of unrelated problems is
  * one bigger set of independent local solves.  A batch advances many problems (any
- * PDE, degree, mesh and coefficients, FP64 precision) together: each sweep is one launch
- * per operator family in the batch, whose workgroups look up their problem in a table,
- * and each problem keeps its own control block, stopping test and residual history.  A
- * problem's iterates, iteration counts and solution are bit for bit those of the same
- * handle advanced alone.
+ * PDE, degree, mesh and coefficients, precision EHDG_FP64 or EHDG_FP32) together, and each
+ * problem keeps its own control block, stopping test and residual history.  A round of
+ * sweeps is one persistent launch per precision for every 2D transport and shallow-water
+ * member (a grid of resident workgroups striding over the (problem, tile range) table,
+ * each entry dispatched to its family's sweep), plus one launch per family for the other
+ * families; backward-Euler step completions are one launch per family.  The rounds are
+ * captured once into a HIP graph and replayed (ehdg_batch_set_graph).  A problem's iterates,
+ * iteration counts and solution are bit for bit those of the same handle advanced alone.
  *
- * handles: host array of n handles (from ehdg_setup, FP64 precision), all distinct; the
- * batch keeps pointers to them, so they must outlive it, and no call on a member
+ * handles: host array of n handles (from ehdg_setup, FP64 or FP32 precision), all distinct;
+ * the batch keeps pointers to them, so they must outlive it, and no call on a member
  * handle may overlap a batch call.  The workspace (device memory, 256-byte aligned,
  * at least ehdg_batch_workspace_bytes) holds the problem table; it stays the caller's.
  * Work is queued on `stream` (NULL = default).  Returns UNSUPPORTED for a handle in a
- * refinement precision, INVALID_ARG for a repeated or null handle. */
+ * refinement precision or with a variable velocity, INVALID_ARG for a repeated or null
+ * handle. */
 typedef struct ehdg_batch_s* ehdg_batch;
 int ehdg_batch_workspace_bytes(const ehdg_handle* handles, int32_t n, size_t* bytes);
 int ehdg_batch_create(const ehdg_handle* handles, int32_t n, void* d_workspace, size_t workspace_bytes,
@@ -279,6 +283,13 @@ int ehdg_batch_step(ehdg_batch b, int32_t n_steps, double rel_tol, int32_t max_i
  * steps), 2 non-finite increment.  ehdg_get_solution then gives a finished member's
  * result. */
 int ehdg_batch_advance(ehdg_batch b, int32_t rounds, double rel_tol, const int32_t* step_targets, int32_t* state);
+
+/* Rounds as a captured HIP graph (enabled != 0, the default for ehdg_batch_create) or as
+ * launches queued one by one (0).  The graph is captured on a private stream of the batch
+ * and replayed on the batch's stream; a caller's stream that is itself being captured gets
+ * plain launches.  Static batches (ehdg_batch_create_static) have no graphs (enabling
+ * returns UNSUPPORTED): instantiating a graph allocates. */
+int ehdg_batch_set_graph(ehdg_batch b, int32_t enabled);
 
 int ehdg_batch_destroy(ehdg_batch b);
 const char* ehdg_batch_last_error(ehdg_batch b);

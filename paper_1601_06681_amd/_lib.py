@@ -31,7 +31,7 @@ EXPORTED = [
     "ehdg_state_bytes", "ehdg_get_state", "ehdg_set_state", "ehdg_destroy", "ehdg_error_string",
     "ehdg_last_error", "ehdg_batch_workspace_bytes", "ehdg_batch_create", "ehdg_batch_solve", "ehdg_batch_step",
     "ehdg_batch_advance", "ehdg_batch_destroy", "ehdg_batch_last_error", "ehdg_variable_workspace_bytes",
-    "ehdg_setup_variable", "ehdg_batch_create_static",
+    "ehdg_setup_variable", "ehdg_batch_create_static", "ehdg_batch_set_graph",
 ]
 
 
@@ -89,6 +89,7 @@ def load():
         "ehdg_batch_workspace_bytes": (ctypes.c_int, [P, I32, ctypes.POINTER(SZ)]),
         "ehdg_batch_create": (ctypes.c_int, [P, I32, P, SZ, P, ctypes.POINTER(P)]),
         "ehdg_batch_create_static": (ctypes.c_int, [P, I32, P, ctypes.POINTER(P)]),
+        "ehdg_batch_set_graph": (ctypes.c_int, [P, I32]),
         "ehdg_batch_solve": (ctypes.c_int, [P, D, I32, P, P]),
         "ehdg_batch_step": (ctypes.c_int, [P, I32, D, I32, P]),
         "ehdg_batch_advance": (ctypes.c_int, [P, I32, D, P, P]),

@@ -233,13 +233,15 @@ bool mixed(const ehdg_problem* h) {
 // plain FP32 form: FP32 state, g and sweeps, FP64 stopping test and recovery
 bool plain32(const ehdg_problem* h) { return h->desc.precision == EHDG_FP32; }
 
-// element solution of the local solve that read state buffer `buf` into u_other
-void recover(ehdg_problem* h, int buf) {
+// element solution of the local solve that read state buffer `buf` into u_other (on the
+// handle's stream, or on `st`)
+void recover(ehdg_problem* h, int buf, hipStream_t st = nullptr) {
   DevProblem& dp = h->dp;
+  if (!st) st = h->stream;
   if (plain32(h))
-    h->ks->volume32(dp, (const float*)dp.s[buf & 1], u_cur(h), u_other(h), h->stream);
+    h->ks->volume32(dp, (const float*)dp.s[buf & 1], u_cur(h), u_other(h), st);
   else
-    h->ks->volume(dp, dp.s[buf & 1], u_cur(h), u_other(h), h->stream);
+    h->ks->volume(dp, dp.s[buf & 1], u_cur(h), u_other(h), st);
 }
 
 // queues one outer iteration: a plain sweep, or a refinement with its inner sweeps
@@ -778,10 +780,22 @@ int ehdg_destroy(ehdg_handle h) {
 }  // extern "C"
 
 struct ehdg_batch_s {
+  // members of one kernel family and precision: their own sweep entries (families the
+  // persistent sweep does not cover) and step-completion entries
   struct Group {
     const KernelSet* ks;
+    bool fp32;
     int sweep_first, sweep_n, step_first, step_n;
   };
+  // the persistent sweep's entries, per precision
+  int persist_first[2] = {0, 0}, persist_n[2] = {0, 0};
+  // rounds queued as a HIP graph (captured on a private stream, replayed on `stream`)
+  bool use_graph = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int graph_rounds = 0;
+  int graph_steps = 0;
+  double graph_tol = 0.0;
   // tables in the device's static scratch array (ehdg_batch_create_static): valid while
   // no later static batch was created on the same device (generation check)
   bool is_static = false;
@@ -834,28 +848,43 @@ int bfail(ehdg_batch_s* b, int code, const std::string& msg) {
     if (e_ != hipSuccess) return bfail((b), EHDG_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
   } while (0)
 
-// Groups by kernel family (in order of first appearance) and the workgroup table: for
-// each family, the sweep entries of its problems, then their step entries.
+// The workgroup table: first the persistent sweep's entries (FP64 members, then FP32
+// members, each member's entries contiguous), then per (family, precision) group in order
+// of first appearance its own sweep entries (families the persistent sweep does not cover)
+// and its step-completion entries.  A member's entries are those of its own launch shape,
+// so batched results are bitwise those of the member alone.
 void batch_plan(const std::vector<ehdg_problem*>& hs, std::vector<ehdg_batch_s::Group>& groups,
-                std::vector<BatchEntry>& table) {
-  std::vector<const KernelSet*> fams;
-  for (auto* h : hs)
-    if (std::find(fams.begin(), fams.end(), h->ks) == fams.end()) fams.push_back(h->ks);
-  for (const KernelSet* ks : fams) {
-    ehdg_batch_s::Group g{ks, (int)table.size(), 0, 0, 0};
-    for (size_t i = 0; i < hs.size(); ++i) {
-      if (hs[i]->ks != ks) continue;
-      int tpg = 0, ng = 0;
-      ks->sweep_groups(hs[i]->dp.mesh.nel, &tpg, &ng);
-      for (int b = 0; b < ng; ++b) table.push_back({(int)i, b, ng, tpg});
-    }
+                std::vector<BatchEntry>& table, int* persist_first, int* persist_n) {
+  auto fp32 = [&](size_t i) { return hs[i]->desc.precision == EHDG_FP32; };
+  auto sweep_entries = [&](size_t i) {
+    const KernelSet* ks = hs[i]->ks;
+    int tpg = 0, ng = 0;
+    (fp32(i) ? ks->sweep32_groups : ks->sweep_groups)(hs[i]->dp.mesh.nel, &tpg, &ng);
+    for (int b = 0; b < ng; ++b) table.push_back({(int)i, b, ng, tpg, ks->persist});
+  };
+  for (int prec = 0; prec < 2; ++prec) {
+    persist_first[prec] = (int)table.size();
+    for (size_t i = 0; i < hs.size(); ++i)
+      if (hs[i]->ks->persist >= 0 && fp32(i) == (prec == 1)) sweep_entries(i);
+    persist_n[prec] = (int)table.size() - persist_first[prec];
+  }
+  std::vector<std::pair<const KernelSet*, bool>> fams;
+  for (size_t i = 0; i < hs.size(); ++i) {
+    const auto key = std::make_pair(hs[i]->ks, fp32(i));
+    if (std::find(fams.begin(), fams.end(), key) == fams.end()) fams.push_back(key);
+  }
+  for (const auto& key : fams) {
+    const KernelSet* ks = key.first;
+    ehdg_batch_s::Group g{ks, key.second, (int)table.size(), 0, 0, 0};
+    for (size_t i = 0; i < hs.size(); ++i)
+      if (hs[i]->ks == ks && fp32(i) == key.second && ks->persist < 0) sweep_entries(i);
     g.sweep_n = (int)table.size() - g.sweep_first;
     g.step_first = (int)table.size();
     for (size_t i = 0; i < hs.size(); ++i) {
-      if (hs[i]->ks != ks || !hs[i]->dp.be) continue;
+      if (hs[i]->ks != ks || fp32(i) != key.second || !hs[i]->dp.be) continue;
       int tpg = 0, ng = 0;
       ks->step_groups(hs[i]->dp.mesh.nel, &tpg, &ng);
-      for (int b = 0; b < ng; ++b) table.push_back({(int)i, b, ng, tpg});
+      for (int b = 0; b < ng; ++b) table.push_back({(int)i, b, ng, tpg, -1});
     }
     g.step_n = (int)table.size() - g.step_first;
     groups.push_back(g);
@@ -886,7 +915,8 @@ int batch_check(const ehdg_handle* handles, int32_t n, std::vector<ehdg_problem*
   for (int i = 0; i < n; ++i) {
     if (!handles[i]) return EHDG_ERR_INVALID_ARG;
     if (std::find(hs.begin(), hs.end(), handles[i]) != hs.end()) return EHDG_ERR_INVALID_ARG;
-    if (handles[i]->desc.precision != EHDG_FP64 || handles[i]->var) return EHDG_ERR_UNSUPPORTED;
+    const int prec = handles[i]->desc.precision;
+    if ((prec != EHDG_FP64 && prec != EHDG_FP32) || handles[i]->var) return EHDG_ERR_UNSUPPORTED;
     hs.push_back(handles[i]);
   }
   return EHDG_OK;
@@ -904,6 +934,8 @@ int batch_upload(ehdg_batch_s* b, const std::vector<int>& steps_target) {
     P.step_cap = dp.step_cap;
     P.Tf64 = dp.Tf64;
     P.Mf64 = dp.Mf64;
+    P.Tf32 = dp.g32 ? dp.Tf32 : nullptr;
+    P.g32 = dp.g32;
     P.g = dp.g;
     P.s0 = dp.s[0];
     P.s1 = dp.s[1];
@@ -943,6 +975,62 @@ int batch_sync_ctrl(ehdg_batch_s* b) {
   return EHDG_OK;
 }
 
+// One round of the batch on stream st: a sweep of every member (the persistent sweep per
+// precision, then the families it does not cover), then, if steps, the step completions.
+void queue_round(ehdg_batch_s* b, double tol, bool steps, hipStream_t st) {
+  for (int prec = 0; prec < 2; ++prec)
+    launch_sweep_persist(b->d_table + b->persist_first[prec], b->persist_n[prec], b->d_probs, tol, prec, st);
+  for (const auto& g : b->groups)
+    if (g.sweep_n) (g.fp32 ? g.ks->sweep32_batch : g.ks->sweep64_batch)(b->d_table + g.sweep_first, g.sweep_n, b->d_probs, tol, st);
+  if (steps)
+    for (const auto& g : b->groups)
+      if (g.step_n) (g.fp32 ? g.ks->step32_batch : g.ks->step_batch)(b->d_table + g.step_first, g.step_n, b->d_probs, 1, st);
+}
+
+void drop_graph(ehdg_batch_s* b) {
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  b->graph_rounds = 0;
+}
+
+// `rounds` rounds on the batch's stream, with the step completions after every round
+// (steps = 1) or after the last one only (steps = 2), or none (0).  Graph mode: the rounds
+// are captured once into a HIP graph (kernels only: every counter the kernels use is reset
+// by the kernels themselves) and the graph is replayed `repeat` times, and again by later
+// calls while the round count, the step mode and the tolerance stay the same.  Otherwise
+// (static batches, a caller's stream that is being captured, or graphs switched off) the
+// launches are queued one by one.
+int run_rounds(ehdg_batch_s* b, int rounds, double tol, int steps, int repeat = 1) {
+  if (rounds <= 0 || repeat <= 0) return EHDG_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (b->stream) (void)hipStreamIsCapturing(b->stream, &cs);
+  if (!b->use_graph || cs != hipStreamCaptureStatusNone) {
+    for (int q = 0; q < repeat; ++q)
+      for (int r = 0; r < rounds; ++r) queue_round(b, tol, steps == 1 || (steps == 2 && r == rounds - 1), b->stream);
+    return EHDG_OK;
+  }
+  if (!(b->graph && b->graph_rounds == rounds && b->graph_steps == steps && b->graph_tol == tol)) {
+    drop_graph(b);
+    if (!b->cap_stream) HIP_TRY_B(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    HIP_TRY_B(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < rounds; ++r)
+      queue_round(b, tol, steps == 1 || (steps == 2 && r == rounds - 1), b->cap_stream);
+    hipGraph_t g = nullptr;
+    HIP_TRY_B(b, hipStreamEndCapture(b->cap_stream, &g));
+    const hipError_t e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      b->graph = nullptr;
+      return bfail(b, EHDG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    b->graph_rounds = rounds;
+    b->graph_steps = steps;
+    b->graph_tol = tol;
+  }
+  for (int q = 0; q < repeat; ++q) HIP_TRY_B(b, hipGraphLaunch(b->graph, b->stream));
+  return EHDG_OK;
+}
+
 int batch_check_launch(ehdg_batch_s* b) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return bfail(b, EHDG_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -960,7 +1048,8 @@ int ehdg_batch_workspace_bytes(const ehdg_handle* handles, int32_t n, size_t* by
   if (rc) return rc;
   std::vector<ehdg_batch_s::Group> groups;
   std::vector<BatchEntry> table;
-  batch_plan(hs, groups, table);
+  int pf[2], pn[2];
+  batch_plan(hs, groups, table, pf, pn);
   *bytes = batch_layout(hs.size(), table.size()).total;
   return EHDG_OK;
 }
@@ -977,7 +1066,7 @@ int batch_create_in(std::vector<ehdg_problem*>& hs, void* d_workspace, size_t wo
   b->h = hs;
   b->stream = (hipStream_t)stream;
   std::vector<BatchEntry> table;
-  batch_plan(hs, b->groups, table);
+  batch_plan(hs, b->groups, table, b->persist_first, b->persist_n);
   const BatchLayout L = batch_layout(hs.size(), table.size());
   if (workspace_bytes < L.total) {
     delete b;
@@ -1023,7 +1112,8 @@ int ehdg_batch_create_static(const ehdg_handle* handles, int32_t n, void* stream
   {
     std::vector<ehdg_batch_s::Group> groups;
     std::vector<BatchEntry> table;
-    batch_plan(hs, groups, table);
+    int pf[2], pn[2];
+    batch_plan(hs, groups, table, pf, pn);
     if (batch_layout(hs.size(), table.size()).total > kStaticBatchBytes) return EHDG_ERR_WORKSPACE_TOO_SMALL;
   }
   int dev = 0;
@@ -1045,6 +1135,7 @@ int ehdg_batch_create_static(const ehdg_handle* handles, int32_t n, void* stream
   rc = batch_create_in(hs, ptr, kStaticBatchBytes, stream, out);
   if (rc) return rc;
   (*out)->is_static = true;
+  (*out)->use_graph = false;  // graph instantiation allocates: static batches launch eagerly
   (*out)->dev = dev;
   (*out)->gen = gen;
   return EHDG_OK;
@@ -1062,9 +1153,7 @@ int ehdg_batch_solve(ehdg_batch b, double rel_tol, int32_t max_iters, int32_t* i
   int launched = 0, chunk = pred, next = 2;
   for (;;) {
     const int nq = std::min(chunk, max_iters - launched);
-    for (int j = 0; j < nq; ++j)
-      for (const auto& g : b->groups)
-        g.ks->sweep64_batch(b->d_table + g.sweep_first, g.sweep_n, b->d_probs, rel_tol, b->stream);
+    if ((rc = run_rounds(b, nq, rel_tol, 0))) return rc;
     launched += nq;
     if ((rc = batch_check_launch(b)) || (rc = batch_sync_ctrl(b))) return rc;
     bool all = true;
@@ -1085,7 +1174,7 @@ int ehdg_batch_solve(ehdg_batch b, double rel_tol, int32_t max_iters, int32_t* i
     if (st && !first_bad) first_bad = st;
     h->recovered = -1;
     if (c.iters > 0 && c.status != 2) {
-      h->ks->volume(h->dp, h->dp.s[(c.base + c.iters - 1) & 1], u_cur(h), u_other(h), b->stream);
+      recover(h, (c.base + c.iters - 1) & 1, b->stream);
       h->recovered = 1;
     }
   }
@@ -1129,12 +1218,7 @@ int ehdg_batch_step(ehdg_batch b, int32_t n_steps, double rel_tol, int32_t max_i
     std::vector<int> before(n);
     for (size_t i = 0; i < n; ++i) before[i] = b->ctrl[i].steps_done;
     const int per = std::min(pred + 1, max_outer);
-    for (int r = 0; r < remaining; ++r) {
-      for (int j = 0; j < per; ++j)
-        for (const auto& g : b->groups)
-          g.ks->sweep64_batch(b->d_table + g.sweep_first, g.sweep_n, b->d_probs, rel_tol, b->stream);
-      for (const auto& g : b->groups) g.ks->step_batch(b->d_table + g.step_first, g.step_n, b->d_probs, 1, b->stream);
-    }
+    if ((rc = run_rounds(b, per, rel_tol, 2, remaining))) return rc;
     if ((rc = batch_check_launch(b)) || (rc = batch_sync_ctrl(b))) return rc;
     for (size_t i = 0; i < n; ++i) {
       const int fresh = b->ctrl[i].steps_done - before[i];
@@ -1187,12 +1271,7 @@ int ehdg_batch_advance(ehdg_batch b, int32_t rounds, double rel_tol, const int32
     target[i] = step_targets ? step_targets[i] : b->h[i]->mirror.steps_done + 1;
   }
   if ((rc = batch_upload(b, target))) return rc;
-  for (int r = 0; r < rounds; ++r) {
-    for (const auto& g : b->groups)
-      g.ks->sweep64_batch(b->d_table + g.sweep_first, g.sweep_n, b->d_probs, rel_tol, b->stream);
-    if (any_be)
-      for (const auto& g : b->groups) g.ks->step_batch(b->d_table + g.step_first, g.step_n, b->d_probs, 1, b->stream);
-  }
+  if ((rc = run_rounds(b, rounds, rel_tol, any_be ? 1 : 0))) return rc;
   if ((rc = batch_check_launch(b)) || (rc = batch_sync_ctrl(b))) return rc;
   for (size_t i = 0; i < n; ++i) {
     ehdg_problem* h = b->h[i];
@@ -1209,8 +1288,18 @@ int ehdg_batch_advance(ehdg_batch b, int32_t rounds, double rel_tol, const int32
   return EHDG_OK;
 }
 
+int ehdg_batch_set_graph(ehdg_batch b, int32_t enabled) {
+  if (!b) return EHDG_ERR_INVALID_ARG;
+  if (enabled && b->is_static) return bfail(b, EHDG_ERR_UNSUPPORTED, "static batches launch without graphs");
+  b->use_graph = enabled != 0;
+  if (!b->use_graph) drop_graph(b);
+  return EHDG_OK;
+}
+
 int ehdg_batch_destroy(ehdg_batch b) {
   if (!b) return EHDG_ERR_INVALID_ARG;
+  drop_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   delete b;
   return EHDG_OK;
 }

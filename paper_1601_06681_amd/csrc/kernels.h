@@ -109,6 +109,8 @@ struct BatchProblem {
   int hist_cap, step_cap;
   const double* Tf64;      // fragment-major operators
   const double* Mf64;
+  const float* Tf32;       // plain FP32 members: FP32 fragments, g in FP32 (the state buffers
+  float* g32;              // s0, s1 then hold floats); null for FP64 members
   const double* g;
   double* s0;
   double* s1;
@@ -127,7 +129,15 @@ struct BatchProblem {
 // workgroups, their number, and the 16-element tiles each of them takes.
 struct BatchEntry {
   int problem, block, nblocks, tiles_per_group;
+  int family;  // persistent batched sweeps: the family's code (KernelSet::persist)
 };
+
+// The persistent batched sweep: one launch per precision covers every entry of every
+// family whose code is >= 0; a grid of resident workgroups strides over the n entries
+// (entry i on workgroup i mod grid), each entry doing the work of one workgroup of that
+// family's own batched sweep (so results are bitwise those of the per-family launch).
+void launch_sweep_persist(const BatchEntry* table, int n, const BatchProblem* probs, double tol, int fp32,
+                          hipStream_t st);
 
 // Kernels of one (pde, dim, active axes, face nodes) family.
 struct KernelSet {
@@ -171,6 +181,11 @@ struct KernelSet {
   void (*volume32)(const DevProblem&, const float* s_prev, const double* u_old, double* u_out, hipStream_t);
   void (*step32)(const DevProblem&, int lag, unsigned seq_next, double tol, int lagged, hipStream_t);
   void (*sweep32_groups)(int nel, int* tiles_per_group, int* groups);
+  // batches of plain FP32 members: the FP32 sweep (arrival-based test) and step completion
+  void (*sweep32_batch)(const BatchEntry* table, int n, const BatchProblem* probs, double tol, hipStream_t);
+  void (*step32_batch)(const BatchEntry* table, int n, const BatchProblem* probs, int lag, hipStream_t);
+  // code of the family in the persistent batched sweep, -1 if it is not covered there
+  int persist;
 };
 
 const KernelSet* find_kernels(int pde, int dim, int na, int nf);

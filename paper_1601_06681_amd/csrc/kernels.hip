@@ -1140,25 +1140,32 @@ __global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_inner32_mfma(
 // partial sums for the next launch (lagged test, canonical order), and the previous
 // sweep's test is taken at the start.  Buffers come from the control block and the
 // launch number, as in the FP64 sweep.
-template <class F>
-__global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_sweep32_mfma(
-    MeshDev m, const float* __restrict__ g, const float* __restrict__ Tf, ResidArgs ra, float* s0, float* s1,
-    int tiles_per_group, LagArgs lag) {
+// LAGGED: single-problem launches (the lagged test, as in the FP64 sweep); otherwise the
+// last workgroup of the problem to arrive takes this sweep's test (batched launches).
+template <class F, bool LAGGED>
+__device__ __forceinline__ void sweep32_body(const MeshDev& m, const float* __restrict__ g,
+                                             const float* __restrict__ Tf, const ResidArgs& ra, float* s0, float* s1,
+                                             int tiles_per_group, int bid, int nbk, const LagArgs& lag) {
   using TL = typename Inner32Tiling<F>::TL;
   constexpr int MTW = TL::MTW, KT = TL::KT;
   const CtrlHead ch = ctrl_head(ra.ctrl);
-  const unsigned seg = ra.ctrl->seg_seq;
+  const unsigned seg = LAGGED ? ra.ctrl->seg_seq : 0u;
   const int lane = threadIdx.x & 63, wave = wave_id();
   const int w = wave % TL::WPG, slot = wave / TL::WPG;
   const int j = lane & 15, kq = lane >> 4;
-  const int bid = (int)blockIdx.x, nbk = (int)gridDim.x;
   float a[MTW][KT];
 #pragma unroll
   for (int u = 0; u < MTW; ++u)
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) a[u][kt] = Tf[((w * MTW + u) * KT + kt) * 64 + lane];
-  const int k = lagged_begin<TL::NW>(ra, lag, nbk, bid, ch, seg);
-  if (k == 0) return;
+  int k;
+  if constexpr (LAGGED) {
+    k = lagged_begin<TL::NW>(ra, lag, nbk, bid, ch, seg);
+    if (k == 0) return;
+  } else {
+    if (ch.done) return;
+    k = ch.iters + 1;
+  }
   const int parity = (ch.base + k - 1) & 1;  // s^(k-1) of the segment
   const size_t nel = (size_t)m.nel;
   const Ld32 ld{parity ? s1 : s0, nel};
@@ -1208,7 +1215,17 @@ __global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_sweep32_mfma(
         }
       }
   }
-  lagged_end<TL::NW>(d2, n2, ra, lag, bid);
+  if constexpr (LAGGED)
+    lagged_end<TL::NW>(d2, n2, ra, lag, bid);
+  else
+    finish_residual<TL::NW>(d2, n2, ra, bid, nbk, ch.iters);
+}
+
+template <class F>
+__global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_sweep32_mfma(
+    MeshDev m, const float* __restrict__ g, const float* __restrict__ Tf, ResidArgs ra, float* s0, float* s1,
+    int tiles_per_group, LagArgs lag) {
+  sweep32_body<F, true>(m, g, Tf, ra, s0, s1, tiles_per_group, (int)blockIdx.x, (int)gridDim.x, lag);
 }
 
 // The same step completion on the matrix cores: [u_new; g_next] = [w_src; gbe] + M
@@ -1417,15 +1434,118 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_sweep_mfma_batch(
                                   be.tiles_per_group, be.block, be.nblocks, LagArgs{0u, 0});
 }
 
-template <class F>
+template <class F, typename ST = double>
 __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma_batch(
     const BatchEntry* __restrict__ table, const BatchProblem* __restrict__ probs, int lag) {
   const BatchEntry be = table[blockIdx.x];
   const BatchProblem& P = probs[be.problem];
   if (P.ctrl->steps_done >= P.steps_target) return;
-  step_mfma_body<F>(P.mesh, P.s0, P.s1, P.Mf64, P.u0, P.u1, P.w_src, P.gbe, const_cast<double*>(P.g), P.ctrl,
-                    P.counters + kCounterSet, P.step_iters, P.step_cap, lag, be.tiles_per_group, be.block,
-                    be.nblocks, StepLag{0, 0u, 0.0, nullptr, 0, 0, nullptr, 1});
+  ST* g_out;
+  if constexpr (std::is_same_v<ST, float>)
+    g_out = P.g32;
+  else
+    g_out = const_cast<double*>(P.g);
+  step_mfma_body<F, ST>(P.mesh, (ST*)P.s0, (ST*)P.s1, P.Mf64, P.u0, P.u1, P.w_src, P.gbe, g_out, P.ctrl,
+                        P.counters + kCounterSet, P.step_iters, P.step_cap, lag, be.tiles_per_group, be.block,
+                        be.nblocks, StepLag{0, 0u, 0.0, nullptr, 0, 0, nullptr, 1});
+}
+
+// One entry of a batched sweep (the work of one workgroup of the family's batched launch),
+// FP64 or plain FP32.
+template <class F, bool FP32>
+__device__ __forceinline__ void batch_sweep_item(const BatchEntry& be, const BatchProblem& P, double tol, int stop) {
+  ResidArgs ra;
+  ra.ctrl = P.ctrl;
+  ra.cnt = P.counters;
+  ra.partials = P.partials;
+  ra.hist = P.hist;
+  ra.hist_cap = P.hist_cap;
+  ra.tol = tol;
+  ra.stop = stop;
+  if constexpr (FP32)
+    sweep32_body<F, false>(P.mesh, P.g32, P.Tf32, ra, (float*)P.s0, (float*)P.s1, be.tiles_per_group, be.block,
+                           be.nblocks, LagArgs{0u, 0});
+  else
+    sweep_mfma_body<F, true, false>(P.mesh, Ld64{P.s0, (size_t)P.mesh.nel}, P.g, P.Tf64, nullptr, ra, P.s0, P.s1,
+                                    be.tiles_per_group, be.block, be.nblocks, LagArgs{0u, 0});
+}
+
+template <class F>
+__global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_sweep32_batch(
+    const BatchEntry* __restrict__ table, const BatchProblem* __restrict__ probs, double tol, int stop) {
+  const BatchEntry be = table[blockIdx.x];
+  const BatchProblem& P = probs[be.problem];
+  if (P.ctrl->steps_done >= P.steps_target) return;
+  batch_sweep_item<F, true>(be, P, tol, stop);
+}
+
+// ---------------------------------------------------------------------------
+// the persistent batched sweep
+// ---------------------------------------------------------------------------
+// The families it covers: 2D transport (one or two active axes; degree 1 with two axes is
+// refused at set-up) and shallow water, every degree the library builds.  Each is swept
+// by four wavefronts per workgroup in FP64 and in FP32, so one kernel of 256 threads can
+// run any of their entries.
+template <class... Fs>
+struct FamList {};
+using PersistFams =
+    FamList<TransportFam<2, 1, 2>, TransportFam<2, 1, 3>, TransportFam<2, 1, 4>, TransportFam<2, 1, 5>,
+            TransportFam<2, 1, 6>, TransportFam<2, 1, 7>, TransportFam<2, 2, 3>, TransportFam<2, 2, 4>,
+            TransportFam<2, 2, 5>, TransportFam<2, 2, 6>, TransportFam<2, 2, 7>, SweFam<2>, SweFam<3>, SweFam<4>,
+            SweFam<5>, SweFam<6>, SweFam<7>>;
+
+template <class F, class... Fs>
+struct IndexOf {
+  static constexpr int value = -1;
+};
+template <class F, class G, class... Fs>
+struct IndexOf<F, G, Fs...> {
+  static constexpr int rest = IndexOf<F, Fs...>::value;
+  static constexpr int value = std::is_same_v<F, G> ? 0 : (rest < 0 ? -1 : 1 + rest);
+};
+template <class F, class L>
+struct FamIndex;
+template <class F, class... Fs>
+struct FamIndex<F, FamList<Fs...>> {
+  static constexpr int value = IndexOf<F, Fs...>::value;
+};
+
+template <bool FP32, class L>
+struct PersistDispatch;
+template <bool FP32, class... Fs>
+struct PersistDispatch<FP32, FamList<Fs...>> {
+  __device__ __forceinline__ static void run(int code, const BatchEntry& be, const BatchProblem& P, double tol,
+                                             int stop) {
+    static_assert(((Tiling64<Fs::S, Fs::I>::NW == 4 && Inner32Tiling<Fs>::value == 4) && ...),
+                  "every family of the persistent sweep runs on four wavefronts");
+    int i = 0;
+    ((code == i++ ? (batch_sweep_item<Fs, FP32>(be, P, tol, stop), 0) : 0), ...);
+  }
+};
+
+template <bool FP32>
+__global__ __launch_bounds__(256) void k_sweep_persist(const BatchEntry* __restrict__ table, int n,
+                                                       const BatchProblem* __restrict__ probs, double tol, int stop) {
+  for (int it = (int)blockIdx.x; it < n; it += (int)gridDim.x) {
+    const BatchEntry be = table[it];
+    const BatchProblem& P = probs[be.problem];
+    if (P.ctrl->steps_done >= P.steps_target) continue;  // this problem has taken its steps
+    PersistDispatch<FP32, PersistFams>::run(be.family, be, P, tol, stop);
+  }
+}
+
+template <bool FP32>
+static int persist_resident();
+
+void launch_sweep_persist(const BatchEntry* table, int n, const BatchProblem* probs, double tol, int fp32,
+                          hipStream_t st) {
+  if (n <= 0) return;
+  const int groups = std::max(1, std::min(n, fp32 ? persist_resident<true>() : persist_resident<false>()));
+  if (fp32)
+    hipLaunchKernelGGL(k_sweep_persist<true>, dim3(groups), dim3(256), 0, st, table, n, probs, tol, tol >= 0.0 ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_sweep_persist<false>, dim3(groups), dim3(256), 0, st, table, n, probs, tol,
+                       tol >= 0.0 ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1443,6 +1563,12 @@ static int resident_groups(K kernel, int threads) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
   return per_cu * cus;
+}
+
+template <bool FP32>
+static int persist_resident() {
+  static const int r = resident_groups(k_sweep_persist<FP32>, 256);
+  return r;
 }
 
 // Matrix-core launches: one round of resident workgroups (resident = how many the
@@ -1550,6 +1676,16 @@ struct Family {
   static void sweep32_groups(int nel, int* tpg, int* groups) {
     using TL = typename Inner32Tiling<F>::TL;
     mfma_groups(nel, TL::TS, res_sweep32(), *tpg, *groups);
+  }
+  static void sweep32_batch(const BatchEntry* table, int n, const BatchProblem* probs, double tol, hipStream_t st) {
+    using TL = typename Inner32Tiling<F>::TL;
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_sweep32_batch<F>), dim3(n), dim3(64 * TL::NW), 0, st, table, probs, tol, tol >= 0.0 ? 1 : 0);
+  }
+  static void step32_batch(const BatchEntry* table, int n, const BatchProblem* probs, int lag, hipStream_t st) {
+    using TL = typename StepTiling<F>::TL;
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_step_mfma_batch<F, float>), dim3(n), dim3(64 * TL::NW), 0, st, table, probs, lag);
   }
   static void step32(const DevProblem& dp, int lag, unsigned seq_next, double tol, int lagged, hipStream_t st) {
     using TL = typename StepTiling<F>::TL;
@@ -1748,7 +1884,9 @@ static const KernelSet* set_of() {
                                &Family<F>::sweep_groups,  &Family<F>::step_groups,
                                &Family<F>::sweep64_batch, &Family<F>::step_batch,
                                &Family<F>::sweep32,       &Family<F>::volume32,
-                               &Family<F>::step32,        &Family<F>::sweep32_groups};
+                               &Family<F>::step32,        &Family<F>::sweep32_groups,
+                               &Family<F>::sweep32_batch, &Family<F>::step32_batch,
+                               FamIndex<F, PersistFams>::value};
   return &ks;
 }
 
@@ -1908,7 +2046,13 @@ struct VarFamily {
 
 template <class F>
 static const KernelSet* var_set_of() {
-  static const KernelSet ks = {&VarFamily<F>::sweep64, &VarFamily<F>::volume};
+  static const KernelSet ks = [] {
+    KernelSet k{};
+    k.sweep64 = &VarFamily<F>::sweep64;
+    k.volume = &VarFamily<F>::volume;
+    k.persist = -1;
+    return k;
+  }();
   return &ks;
 }
 

@@ -267,6 +267,10 @@ def ehdg_batch_advance(b, n, rounds, rel_tol, step_targets=None):
     return state.tolist()
 
 
+def ehdg_batch_set_graph(b, enabled):
+    _check_batch(_lib.load().ehdg_batch_set_graph(b, int(bool(enabled))), b)
+
+
 def ehdg_batch_destroy(b):
     _check(_lib.load().ehdg_batch_destroy(b))
 
@@ -298,6 +302,10 @@ class Batch:
 
     def step(self, n_steps, tol, max_iters=100000, allow=(EHDG_OK,)):
         return ehdg_batch_step(self.b, len(self.problems), n_steps, tol, max_iters, allow)
+
+    def set_graph(self, enabled):
+        """Rounds replayed from a captured HIP graph (True, the default) or launched one by one."""
+        ehdg_batch_set_graph(self.b, enabled)
 
     def advance(self, rounds, tol, step_targets=None):
         """Member states after `rounds` more rounds: 0 running, 1 finished, 2 failed."""

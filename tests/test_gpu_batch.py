@@ -1,10 +1,12 @@
 """Batches of independent problems (ehdg_batch_*), through the C ABI.
 
-A batch advances many problems together: each sweep is one launch per operator family,
-whose workgroups look up their problem in a table.  Each member gets exactly the work it
-gets alone, so the bar is bitwise: every member's iteration counts, residual history and
-solution equal those of the same problem advanced on its own.  One member of each batch
-is also checked against the FP64 oracle (same iteration count, 1e-10).
+A batch advances many problems together.  A round of sweeps is one persistent launch per
+precision for the 2D transport and shallow-water members (workgroups striding over the
+(problem, tile range) table) plus one launch per family for the others, replayed from a
+captured HIP graph.  Each member gets exactly the work it gets alone, so the bar is
+bitwise: every member's iteration counts, residual history and solution equal those of the
+same problem advanced on its own, with graphs or without.  One member of each batch is also
+checked against the FP64 oracle (same iteration count, 1e-10).
 """
 import numpy as np
 import pytest
@@ -126,3 +128,67 @@ def test_batch_iteration_cap_and_refinement_member():
     with pytest.raises(E.EhdgError) as ei:
         E.Batch([members[0], members[0]])
     assert ei.value.code == E.EHDG_ERR_INVALID_ARG
+
+
+def test_batch_mixed_precision_steps_equal_solo():
+    """FP64 and plain FP32 shallow-water members in one batch, stepped at one tolerance
+    (1e-6, within reach of both precisions): the FP32 members' sweeps run in the persistent
+    FP32 launch and their step completions in the FP32 step kernel; every member equals its
+    solo run at the same tolerance bitwise."""
+    from paper_1601_06681_amd.ehdg import EHDG_SWE, Batch, Problem
+
+    def mk(n, p, dt, prec, seed):
+        prob = Problem(EHDG_SWE, 2, n, L=(1.0, 1.0), periodic=(1, 1, 0), degree=p, Phi=1.0, dt=dt, precision=prec)
+        prob.set_initial(swe_random_fns(seed))
+        return prob
+    specs = [((16, 16), 3, 1e-3, 3, 1), ((12, 10), 2, 2e-3, 0, 2), ((9, 13), 4, 5e-4, 3, 3), ((11, 7), 1, 1e-3, 0, 4)]
+    tol = 1e-6
+    solo = []
+    for sp in specs:
+        prob = mk(*sp)
+        rc, its = prob.step(3, tol, 1000)
+        solo.append((its, prob.solution().clone()))
+        prob.close()
+    members = [mk(*sp) for sp in specs]
+    batch = Batch(members)
+    rc, its = batch.step(3, tol, 1000)
+    assert rc == 0
+    for i, prob in enumerate(members):
+        assert its[i] == solo[i][0], (i, its[i], solo[i][0])
+        assert bool((prob.solution() == solo[i][1]).all()), i
+    batch.close()
+    for prob in members:
+        prob.close()
+
+
+def test_batch_graph_replays_equal_eager_launches():
+    """The rounds replayed from the captured graph give bitwise the eager launches' results,
+    over several calls with unrelated eager GPU work and synchronizations between them:
+    advance (sweeps and step completions in every round), then solve."""
+    import torch
+    from paper_1601_06681_amd.ehdg import Batch
+    def members():
+        out = [_transport(c) for c in STEADY[:3]] + [mk() for mk in _be_members()[:2]]
+        return out
+    runs = []
+    for graph in (True, False):
+        ms = members()
+        batch = Batch(ms)
+        batch.set_graph(graph)
+        states, sols = [], []
+        for k in range(4):
+            x = torch.randn(1 << 20, device=ms[0].device)
+            y = (x * 2.0).sum()                       # eager work between replays
+            torch.cuda.synchronize()
+            states.append(batch.advance(7, 1e-10, step_targets=[10 ** 6] * len(ms)))
+            sols.append([p.solution().clone() for p in ms])
+            del x, y
+        runs.append((states, sols))
+        batch.close()
+        for p in ms:
+            p.close()
+    (s1, u1), (s2, u2) = runs
+    assert s1 == s2
+    for a, b in zip(u1, u2):
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)

@@ -164,10 +164,25 @@ def test_fp32_tight_tolerance_keeps_fp32_accuracy():
     prob.close()
 
 
-def test_fp32_batches_refused():
+def test_fp32_members_in_a_batch_equal_solo():
+    """Plain FP32 members in a batch (the persistent FP32 sweep) give bitwise their solo
+    results: iteration counts, residual histories, solutions."""
     from paper_1601_06681_amd import ehdg as E
-    prob = gpu_transport((8, 8), (1.0, 1.0), 2, (1.0, 0.5), 1.0, precision=FP32)
-    with pytest.raises(E.EhdgError) as ei:
-        E.Batch([prob])
-    assert ei.value.code == E.EHDG_ERR_UNSUPPORTED
-    prob.close()
+    cases = [((13, 7), 2, (1.0, 0.5)), ((20, 11), 4, (-0.6, 0.9)), ((9, 9), 3, (0.0, -0.7))]
+    solo = []
+    for n, p, beta in cases:
+        prob = gpu_transport(n, (1.0, 1.0), p, beta, 1.0, precision=FP32)
+        rc, it, res = prob.solve(1e-6, 5000)
+        solo.append((it, prob.solution().clone(), prob.residuals(0, it)))
+        prob.close()
+    members = [gpu_transport(n, (1.0, 1.0), p, beta, 1.0, precision=FP32) for n, p, beta in cases]
+    batch = E.Batch(members)
+    rc, its, _ = batch.solve(1e-6, 5000)
+    assert rc == 0
+    for i, prob in enumerate(members):
+        assert its[i] == solo[i][0]
+        assert bool((prob.solution() == solo[i][1]).all()), i
+        np.testing.assert_array_equal(prob.residuals(0, its[i]), solo[i][2])
+    batch.close()
+    for prob in members:
+        prob.close()
