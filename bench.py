@@ -377,28 +377,49 @@ def run_variable(torch, args):
 
 
 def run_batch(torch, args):
-    """Batched uneven solves: the batch_mix problems (seed 0) advanced as two batches (the
-    steady transport members solved to 1e-10, the shallow-water members 5 backward-Euler
-    steps to 1e-10 each), against the same problems solved one after another."""
-    import numpy as np
+    """Batched uneven solves: the batch_mix problems (seed 0) in plain FP32, with launch
+    shapes from the autotuner and rounds replayed from a captured HIP graph (one persistent
+    sweep launch per round over every member).  The steady transport members are solved to
+    an increment of 1e-6, the shallow-water members take 5 backward-Euler steps at 1e-6.
+    Compared with the same batch launched without the graph and with the first problems of
+    each kind solved one by one.  Members the library refuses (degree-1 transport with both
+    velocity components non-zero) are counted and left out."""
+    import tempfile
+    from paper_1601_06681_amd import autotune as A
     from paper_1601_06681_amd import workloads as W
-    from paper_1601_06681_amd.ehdg import EHDG_SWE, EHDG_TRANSPORT, Batch, Problem
-    specs = W.batch_mix(args.batch_size, 0)
+    from paper_1601_06681_amd.ehdg import EHDG_FP32, EHDG_SWE, EHDG_TRANSPORT, Batch, Problem
+    drawn = W.batch_mix(args.batch_size, 0)
+    specs = [sp for sp in drawn if not (sp["kind"] == "transport" and sp["degree"] == 1
+                                        and sp["beta"][0] != 0.0 and sp["beta"][1] != 0.0)]
     hump = W.gaussian_hump(W.hump_centre(0))
+    tol = 1e-6
 
     def make(sp):
         if sp["kind"] == "transport":
             prob = Problem(EHDG_TRANSPORT, 2, (sp["n"], sp["n"]), L=(1.0, 1.0), degree=sp["degree"], beta=sp["beta"],
-                           sigma=sp["sigma"])
+                           sigma=sp["sigma"], precision=EHDG_FP32)
             ue, f = W.transport_manufactured_2d(sp["beta"], sp["sigma"])
             prob.set_forcing([f], ue)
             prob.set_initial(None)
         else:
             prob = Problem(EHDG_SWE, 2, (sp["n"], sp["n"]), L=(1.0, 1.0), periodic=(1, 1, 0), degree=sp["degree"],
-                           Phi=1.0, dt=sp["dt"])
+                           Phi=1.0, dt=sp["dt"], precision=EHDG_FP32)
             prob.set_initial(hump)
         return prob
 
+    # launch shapes: the autotuner in batch mode (a round of 8 problems of 128 x 128 of the
+    # family through the persistent batched sweep) for each family in the batch
+    t0 = time.perf_counter()
+    cache = os.path.join(tempfile.mkdtemp(prefix="ehdg_tune_"), "tune.json")
+    tuned = {}
+    for kind, p in sorted({(sp["kind"], sp["degree"]) for sp in specs}):
+        rep = dict(kind=kind, n=128, degree=p, beta=(0.96, 0.28), sigma=1.0,
+                   dt=0.25 / 128 / ((p + 1) * (p + 2)), steps=5)
+        pde = EHDG_TRANSPORT if kind == "transport" else EHDG_SWE
+        out = A.tune(lambda rep=rep: make(rep), pde, 2, p, EHDG_FP32, sweeps=30, path=cache, batch=8)
+        tuned[f"{kind}_p{p}"] = {k: out["best"][k] for k in ("tiles_per_group", "reverse_order", "sweep_us")}
+    t_tune = time.perf_counter() - t0
+    log(f"[bench] batch: autotuned {len(tuned)} families in {t_tune:.1f} s")
     t0 = time.perf_counter()
     probs = [make(sp) for sp in specs]
     torch.cuda.synchronize()
@@ -406,8 +427,10 @@ def run_batch(torch, args):
     tr = [i for i, sp in enumerate(specs) if sp["kind"] == "transport"]
     sw = [i for i, sp in enumerate(specs) if sp["kind"] == "swe"]
     dofs = [p.nel * p.m * p.Np for p in probs]
-    out = {"workload": f"batch_mix_{len(specs)}", "problems": len(specs), "transport": len(tr), "swe": len(sw),
-           "elements": int(sum(p.nel for p in probs)), "dofs": int(sum(dofs))}
+    out = {"workload": f"batch_mix_{len(drawn)}", "problems": len(specs), "transport": len(tr), "swe": len(sw),
+           "left_out_degree1_two_axis_transport": len(drawn) - len(specs), "precision": "fp32", "rel_tol": tol,
+           "elements": int(sum(p.nel for p in probs)), "dofs": int(sum(dofs)), "autotune_s": t_tune,
+           "tuned_shapes": tuned}
 
     def timed(fn):
         torch.cuda.synchronize()
@@ -416,36 +439,40 @@ def run_batch(torch, args):
         torch.cuda.synchronize()
         return r, time.perf_counter() - t
 
+    def reset(idx):
+        for i in idx:
+            probs[i].set_initial(None if specs[i]["kind"] == "transport" else hump)
+
     bt = Batch([probs[i] for i in tr])
     bs = Batch([probs[i] for i in sw])
-    bt.solve(1e-10, 100000)                      # warm-up: kernel loading, predictions
-    bs.step(1, 1e-10, 1000)
-    for i in tr:
-        probs[i].set_initial(None)
-    for i in sw:
-        probs[i].set_initial(hump)
-    (rc_t, its_t, _), wall_t = timed(lambda: bt.solve(1e-10, 100000))
-    (rc_s, its_s), wall_s = timed(lambda: bs.step(5, 1e-10, 1000))
-    upd_t = sum(dofs[i] * its_t[k] for k, i in enumerate(tr))
-    upd_s = sum(dofs[i] * sum(its_s[k]) for k, i in enumerate(sw))
-    out["batched"] = {"transport_solve_ms": wall_t * 1e3, "transport_sweeps_total": int(sum(its_t)),
-                      "swe_5_steps_ms": wall_s * 1e3, "swe_sweeps_total": int(sum(sum(v) for v in its_s)),
-                      "dof_updates_per_s": (upd_t + upd_s) / (wall_t + wall_s)}
-    log(f"[bench] batch: transport {wall_t * 1e3:.1f} ms, swe {wall_s * 1e3:.1f} ms, "
-        f"{out['batched']['dof_updates_per_s']:.3e} DOF-updates/s")
+    for graph in (True, False):
+        bt.set_graph(graph)
+        bs.set_graph(graph)
+        bt.solve(tol, 100000)                  # warm-up: kernel loading, graph capture, predictions
+        bs.step(1, tol, 1000)
+        reset(tr)
+        reset(sw)
+        (rc_t, its_t, _), wall_t = timed(lambda: bt.solve(tol, 100000))
+        (rc_s, its_s), wall_s = timed(lambda: bs.step(5, tol, 1000))
+        upd_t = sum(dofs[i] * its_t[k] for k, i in enumerate(tr))
+        upd_s = sum(dofs[i] * sum(its_s[k]) for k, i in enumerate(sw))
+        row = {"transport_solve_ms": wall_t * 1e3, "transport_sweeps_total": int(sum(its_t)),
+               "swe_5_steps_ms": wall_s * 1e3, "swe_sweeps_total": int(sum(sum(v) for v in its_s)),
+               "dof_updates_per_s": (upd_t + upd_s) / (wall_t + wall_s)}
+        out["batched_graph" if graph else "batched_eager"] = row
+        log(f"[bench] batch ({'graph' if graph else 'eager'}): transport {wall_t * 1e3:.1f} ms, swe "
+            f"{wall_s * 1e3:.1f} ms, {row['dof_updates_per_s']:.3e} DOF-updates/s")
     # the same problems one after another (the first args.batch_solo of each kind)
     k = args.batch_solo
-    for i in tr[:k]:
-        probs[i].set_initial(None)
-    for i in sw[:k]:
-        probs[i].set_initial(hump)
+    reset(tr[:k])
+    reset(sw[:k])
     upd, wall = 0, 0.0
     for i in tr[:k]:
-        (rc, it, _), w = timed(lambda: probs[i].solve(1e-10, 100000))
+        (rc, it, _), w = timed(lambda: probs[i].solve(tol, 100000))
         upd += dofs[i] * it
         wall += w
     for i in sw[:k]:
-        (rc, its), w = timed(lambda: probs[i].step(5, 1e-10, 1000))
+        (rc, its), w = timed(lambda: probs[i].step(5, tol, 1000))
         upd += dofs[i] * sum(its)
         wall += w
     out["one_by_one_first"] = {"problems_per_kind": k, "dof_updates_per_s": upd / wall}
@@ -454,6 +481,8 @@ def run_batch(torch, args):
     bs.close()
     for p in probs:
         p.close()
+    from paper_1601_06681_amd.ehdg import ehdg_tune_clear
+    ehdg_tune_clear()
     return out
 
 

@@ -221,6 +221,24 @@ int ehdg_state_bytes(ehdg_handle h, size_t* bytes);
 int ehdg_get_state(ehdg_handle h, void* d_dst, size_t bytes);
 int ehdg_set_state(ehdg_handle h, const void* d_src, size_t bytes);
 
+/* Launch shapes of the plain sweeps (EHDG_FP64, EHDG_FP32), for a tuner.  The sweep applies
+ * the condensed operator to tiles of 16 elements; a launch gives each workgroup a range of
+ * tiles.  ehdg_tune_set registers, for the problems with this (pde, dim, degree, precision)
+ * set up afterwards in this process, the tiles per workgroup (0: as many as one round of
+ * resident workgroups needs, the default; > 0: that many, rounded up to the tiling's step,
+ * in as many rounds as it takes) and the order in which the workgroups take their ranges
+ * (reverse_order != 0: reversed).  tiles_per_group = 0 with reverse_order = 0 removes the
+ * entry; ehdg_tune_clear removes all.  The shape changes how the increment norms are summed
+ * (per workgroup, then in a fixed order), not the iterates: each element's local solve is
+ * the same arithmetic in any shape.  Batches use each member's shape.
+ * ehdg_tune_set returns INVALID_ARG for tiles_per_group < 0 and for the refinement
+ * precisions (their kernels keep their own shapes).  ehdg_launch_shape reports a handle's
+ * shape; UNSUPPORTED for variable velocity. */
+int ehdg_tune_set(int32_t pde, int32_t dim, int32_t degree, int32_t precision, int32_t tiles_per_group,
+                  int32_t reverse_order);
+int ehdg_tune_clear(void);
+int ehdg_launch_shape(ehdg_handle h, int32_t* tiles_per_group, int32_t* groups, int32_t* reverse_order);
+
 /* Releases the host-side handle (the workspace stays the caller's). */
 int ehdg_destroy(ehdg_handle h);
 

@@ -31,7 +31,8 @@ EXPORTED = [
     "ehdg_state_bytes", "ehdg_get_state", "ehdg_set_state", "ehdg_destroy", "ehdg_error_string",
     "ehdg_last_error", "ehdg_batch_workspace_bytes", "ehdg_batch_create", "ehdg_batch_solve", "ehdg_batch_step",
     "ehdg_batch_advance", "ehdg_batch_destroy", "ehdg_batch_last_error", "ehdg_variable_workspace_bytes",
-    "ehdg_setup_variable", "ehdg_batch_create_static", "ehdg_batch_set_graph",
+    "ehdg_setup_variable", "ehdg_batch_create_static", "ehdg_batch_set_graph", "ehdg_tune_set",
+    "ehdg_tune_clear", "ehdg_launch_shape",
 ]
 
 
@@ -90,6 +91,9 @@ def load():
         "ehdg_batch_create": (ctypes.c_int, [P, I32, P, SZ, P, ctypes.POINTER(P)]),
         "ehdg_batch_create_static": (ctypes.c_int, [P, I32, P, ctypes.POINTER(P)]),
         "ehdg_batch_set_graph": (ctypes.c_int, [P, I32]),
+        "ehdg_tune_set": (ctypes.c_int, [I32, I32, I32, I32, I32, I32]),
+        "ehdg_tune_clear": (ctypes.c_int, []),
+        "ehdg_launch_shape": (ctypes.c_int, [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "ehdg_batch_solve": (ctypes.c_int, [P, D, I32, P, P]),
         "ehdg_batch_step": (ctypes.c_int, [P, I32, D, I32, P]),
         "ehdg_batch_advance": (ctypes.c_int, [P, I32, D, P, P]),

@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <mutex>
 #include <new>
 #include <string>
@@ -147,6 +149,25 @@ Layout layout_for(const Operators& o, long long nel, bool lowp, bool plain32 = f
   L.off_Wv = take(var ? n * n * ne * 8 : 8);
   L.total = off;
   return L;
+}
+
+// Launch shapes of the plain sweeps chosen by a tuner, keyed by (pde, dim, degree,
+// precision): tiles per workgroup (0 = one round of resident workgroups) and workgroup
+// order.  Read when a handle is set up; the shape is fixed for the handle's life (the
+// lagged stopping test reads the previous launch's per-workgroup partial sums).
+struct TuneTable {
+  std::mutex mu;
+  std::map<std::tuple<int, int, int, int>, std::pair<int, int>> shape;
+};
+TuneTable& tune_table() {
+  static TuneTable t;
+  return t;
+}
+std::pair<int, int> tuned_shape(const ehdg_desc* d) {
+  TuneTable& t = tune_table();
+  std::lock_guard<std::mutex> lk(t.mu);
+  const auto it = t.shape.find(std::make_tuple(d->pde, d->dim, d->degree, d->precision));
+  return it == t.shape.end() ? std::make_pair(0, 0) : it->second;
 }
 
 long long nel_of(const ehdg_desc* d) {
@@ -393,8 +414,11 @@ static int setup_impl(const ehdg_desc* desc, const VarSamples* smp, void* d_work
   dp.partials = (double*)(ws + L.off_partials);
   dp.partial_stride = (int)((L.off_hist - L.off_partials) / sizeof(double) / 2);
   if (h->ks->sweep_groups) {
-    int tpg = 0, groups = 0;
+    const std::pair<int, int> shape = tuned_shape(desc);
+    dp.mesh.order = shape.second ? 1 : 0;
+    int tpg = shape.first, groups = 0;
     (desc->precision == EHDG_FP32 ? h->ks->sweep32_groups : h->ks->sweep_groups)((int)nel, &tpg, &groups);
+    dp.sweep_tpg = shape.first > 0 ? tpg : 0;
     dp.nb_sweep = groups;
   } else {
     dp.nb_sweep = (int)var_sweep_groups(nel, o.S);
@@ -770,6 +794,37 @@ int ehdg_set_state(ehdg_handle h, const void* d_src, size_t bytes) {
   return check_launch(h);
 }
 
+int ehdg_tune_set(int32_t pde, int32_t dim, int32_t degree, int32_t precision, int32_t tiles_per_group,
+                  int32_t reverse_order) {
+  if (tiles_per_group < 0 || (precision != EHDG_FP64 && precision != EHDG_FP32)) return EHDG_ERR_INVALID_ARG;
+  TuneTable& t = tune_table();
+  std::lock_guard<std::mutex> lk(t.mu);
+  const auto key = std::make_tuple((int)pde, (int)dim, (int)degree, (int)precision);
+  if (tiles_per_group == 0 && !reverse_order)
+    t.shape.erase(key);
+  else
+    t.shape[key] = std::make_pair((int)tiles_per_group, reverse_order ? 1 : 0);
+  return EHDG_OK;
+}
+
+int ehdg_tune_clear(void) {
+  TuneTable& t = tune_table();
+  std::lock_guard<std::mutex> lk(t.mu);
+  t.shape.clear();
+  return EHDG_OK;
+}
+
+int ehdg_launch_shape(ehdg_handle h, int32_t* tiles_per_group, int32_t* groups, int32_t* reverse_order) {
+  if (!h) return EHDG_ERR_INVALID_ARG;
+  if (h->var) return fail(h, EHDG_ERR_UNSUPPORTED, "variable-velocity sweeps have a fixed shape");
+  int tpg = h->dp.sweep_tpg, ng = 0;
+  (plain32(h) ? h->ks->sweep32_groups : h->ks->sweep_groups)(h->dp.mesh.nel, &tpg, &ng);
+  if (tiles_per_group) *tiles_per_group = tpg;
+  if (groups) *groups = ng;
+  if (reverse_order) *reverse_order = h->dp.mesh.order;
+  return EHDG_OK;
+}
+
 int ehdg_destroy(ehdg_handle h) {
   if (!h) return EHDG_ERR_INVALID_ARG;
   delete h;
@@ -858,7 +913,7 @@ void batch_plan(const std::vector<ehdg_problem*>& hs, std::vector<ehdg_batch_s::
   auto fp32 = [&](size_t i) { return hs[i]->desc.precision == EHDG_FP32; };
   auto sweep_entries = [&](size_t i) {
     const KernelSet* ks = hs[i]->ks;
-    int tpg = 0, ng = 0;
+    int tpg = hs[i]->dp.sweep_tpg, ng = 0;
     (fp32(i) ? ks->sweep32_groups : ks->sweep_groups)(hs[i]->dp.mesh.nel, &tpg, &ng);
     for (int b = 0; b < ng; ++b) table.push_back({(int)i, b, ng, tpg, ks->persist});
   };

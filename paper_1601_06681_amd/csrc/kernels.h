@@ -57,6 +57,7 @@ struct MeshDev {
   int periodic[3];
   int ax[3];   // transport: active axes
   int dir[3];  // transport: +1 if beta_ax > 0 (upwind neighbour at i-1), -1 otherwise
+  int order;   // plain sweeps: 1 = workgroups take their tile ranges in reverse order (tuning)
 };
 
 // All device pointers of a problem (SoA: component k of element e at [k * nel + e]).
@@ -88,7 +89,9 @@ struct DevProblem {
   void* rlo[2];            // low-precision residual, double buffered (S)
   double* partials;        // per workgroup (d2, n2); FP64 sweeps: two sets, partial_stride apart
   int partial_stride;      // doubles between the two sets
-  int nb_sweep;            // workgroups of one FP64 sweep launch
+  int nb_sweep;            // workgroups of one plain sweep launch
+  int sweep_tpg;           // tiles per workgroup of the plain sweeps (0: one round of resident
+                           // workgroups; > 0: the tuned value, rounded to the tiling's step)
   Ctrl* ctrl;
   unsigned* counters;      // kCounterBytes: arrival counters (zero between launches)
   double* hist;            // residual ring
@@ -165,7 +168,8 @@ struct KernelSet {
   void (*refine16)(const DevProblem&, const void* lo_in, void* r_out, double tol, hipStream_t);
   void (*inner16)(const DevProblem&, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t);
   // workgroups of the FP64 sweep / step completion for n_el elements (the same shape a
-  // single problem launches with, so batched and single results agree bit for bit)
+  // single problem launches with, so batched and single results agree bit for bit);
+  // sweep_groups takes a tuned tiles-per-workgroup in *tiles_per_group (0: default)
   void (*sweep_groups)(int nel, int* tiles_per_group, int* groups);
   void (*step_groups)(int nel, int* tiles_per_group, int* groups);
   // one FP64 sweep / one step completion of every problem of a batch that uses this

@@ -731,7 +731,7 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
   }
   const size_t nel = (size_t)m.nel;
   const int ntiles = (m.nel + 15) >> 4;
-  const int t0 = remap_block(bid, nbk) * tiles_per_group;
+  const int t0 = remap_block(m.order ? nbk - 1 - bid : bid, nbk) * tiles_per_group;
   const int t1 = min(t0 + tiles_per_group, ntiles);
   double d2 = 0.0, n2 = 0.0;
   if constexpr (TL::WPG > 1) {
@@ -1171,7 +1171,7 @@ __device__ __forceinline__ void sweep32_body(const MeshDev& m, const float* __re
   const Ld32 ld{parity ? s1 : s0, nel};
   float* __restrict__ out = parity ? s0 : s1;
   const int ntiles = (m.nel + 15) >> 4;
-  const int t0 = remap_block(bid, nbk) * tiles_per_group;
+  const int t0 = remap_block(m.order ? nbk - 1 - bid : bid, nbk) * tiles_per_group;
   const int t1 = min(t0 + tiles_per_group, ntiles);
   double d2 = 0.0, n2 = 0.0;
   for (int t = t0 + slot; t < t1; t += TL::TS) {
@@ -1510,6 +1510,13 @@ struct FamIndex<F, FamList<Fs...>> {
   static constexpr int value = IndexOf<F, Fs...>::value;
 };
 
+// Each family's entry body is a function of its own (not inlined), so the persistent kernel
+// needs the registers of its largest body, not of all bodies inlined into one function.
+template <class F, bool FP32>
+__device__ __noinline__ void persist_item(const BatchEntry& be, const BatchProblem& P, double tol, int stop) {
+  batch_sweep_item<F, FP32>(be, P, tol, stop);
+}
+
 template <bool FP32, class L>
 struct PersistDispatch;
 template <bool FP32, class... Fs>
@@ -1519,18 +1526,48 @@ struct PersistDispatch<FP32, FamList<Fs...>> {
     static_assert(((Tiling64<Fs::S, Fs::I>::NW == 4 && Inner32Tiling<Fs>::value == 4) && ...),
                   "every family of the persistent sweep runs on four wavefronts");
     int i = 0;
-    ((code == i++ ? (batch_sweep_item<Fs, FP32>(be, P, tol, stop), 0) : 0), ...);
+    ((code == i++ ? (persist_item<Fs, FP32>(be, P, tol, stop), 0) : 0), ...);
   }
 };
 
+// Workgroup g takes entries g, g + G, g + 2 G, ... (G = grid).  Most entries of a late
+// round belong to problems that have already converged, and finding that out is a chain of
+// three dependent loads (entry, problem, control block), so the workgroup first checks 256
+// of its entries at once (one per thread), keeps the live ones in LDS in entry order, and
+// then runs only those.  A problem's done flag changes only when the last entry of its
+// sweep has arrived, so an entry found live is still live when it runs.
 template <bool FP32>
-__global__ __launch_bounds__(256) void k_sweep_persist(const BatchEntry* __restrict__ table, int n,
+__global__ __launch_bounds__(256, 3) void k_sweep_persist(const BatchEntry* __restrict__ table, int n,
                                                        const BatchProblem* __restrict__ probs, double tol, int stop) {
-  for (int it = (int)blockIdx.x; it < n; it += (int)gridDim.x) {
-    const BatchEntry be = table[it];
-    const BatchProblem& P = probs[be.problem];
-    if (P.ctrl->steps_done >= P.steps_target) continue;  // this problem has taken its steps
-    PersistDispatch<FP32, PersistFams>::run(be.family, be, P, tol, stop);
+  __shared__ int live_at[256];
+  __shared__ int wave_count[4];
+  const int G = (int)gridDim.x, lane = threadIdx.x & 63, w = wave_id();
+  for (int base = (int)blockIdx.x; base < n; base += 256 * G) {
+    const int it = base + (int)threadIdx.x * G;
+    bool live = false;
+    if (it < n) {
+      const BatchEntry be = table[it];
+      const BatchProblem& P = probs[be.problem];
+      const CtrlHead ch = ctrl_head(P.ctrl);
+      live = !ch.done && P.ctrl->steps_done < P.steps_target;
+    }
+    // compaction in entry order: per-wavefront ballot, then the wavefronts' counts in order
+    const unsigned long long ball = __ballot(live);
+    if (lane == 0) wave_count[w] = __popcll(ball);
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int q = 0; q < 4; ++q) {
+      before += q < w ? wave_count[q] : 0;
+      total += wave_count[q];
+    }
+    if (live) live_at[before + __popcll(ball & ((1ull << lane) - 1ull))] = it;
+    __syncthreads();
+    for (int k = 0; k < total; ++k) {
+      const BatchEntry be = table[live_at[k]];
+      const BatchProblem& P = probs[be.problem];
+      PersistDispatch<FP32, PersistFams>::run(be.family, be, P, tol, stop);
+    }
+    __syncthreads();  // live_at and wave_count are rewritten for the next chunk
   }
 }
 
@@ -1581,6 +1618,17 @@ static inline void mfma_groups(int nel, int ts, int resident, int& tiles_per_gro
   tiles_per_group = std::max(ts, (ntiles + resident - 1) / resident);
   tiles_per_group = (tiles_per_group + ts - 1) / ts * ts;
   groups = (ntiles + tiles_per_group - 1) / tiles_per_group;
+}
+// The same with a tuned tiles-per-workgroup (tuned > 0, rounded up to a multiple of ts):
+// as many workgroups as that takes, in as many rounds as needed.
+static inline void tuned_groups(int nel, int ts, int resident, int tuned, int& tiles_per_group, int& groups) {
+  if (tuned <= 0) {
+    mfma_groups(nel, ts, resident, tiles_per_group, groups);
+    return;
+  }
+  const int ntiles = (nel + kMfmaTileElems - 1) / kMfmaTileElems;
+  tiles_per_group = (std::max(tuned, ts) + ts - 1) / ts * ts;
+  groups = std::max(1, (ntiles + tiles_per_group - 1) / tiles_per_group);
 }
 
 static inline ResidArgs resid_args(const DevProblem& dp, double tol, int stop) {
@@ -1635,7 +1683,7 @@ struct Family {
     using TL = Tiling64<F::S, F::I>;
     const ResidArgs ra = resid_args(dp, tol, tol >= 0.0 ? 1 : 0);
     int tpg, groups;
-    mfma_groups(dp.mesh.nel, TL::TS, res_sweep(), tpg, groups);
+    tuned_groups(dp.mesh.nel, TL::TS, res_sweep(), dp.sweep_tpg, tpg, groups);
     hipLaunchKernelGGL((k_sweep_mfma<F, true>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh,
                        Ld64{dp.s[0], (size_t)dp.mesh.nel}, (const double*)dp.g, dp.Tf64, (double*)nullptr, ra,
                        dp.s[0], dp.s[1], tpg, LagArgs{seq, dp.partial_stride});
@@ -1669,13 +1717,13 @@ struct Family {
     using TL = typename Inner32Tiling<F>::TL;
     const ResidArgs ra = resid_args(dp, tol, tol >= 0.0 ? 1 : 0);
     int tpg, groups;
-    mfma_groups(dp.mesh.nel, TL::TS, res_sweep32(), tpg, groups);
+    tuned_groups(dp.mesh.nel, TL::TS, res_sweep32(), dp.sweep_tpg, tpg, groups);
     hipLaunchKernelGGL((k_sweep32_mfma<F>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, (const float*)dp.g32,
                        dp.Tf32, ra, (float*)dp.s[0], (float*)dp.s[1], tpg, LagArgs{seq, dp.partial_stride});
   }
   static void sweep32_groups(int nel, int* tpg, int* groups) {
     using TL = typename Inner32Tiling<F>::TL;
-    mfma_groups(nel, TL::TS, res_sweep32(), *tpg, *groups);
+    tuned_groups(nel, TL::TS, res_sweep32(), *tpg, *tpg, *groups);
   }
   static void sweep32_batch(const BatchEntry* table, int n, const BatchProblem* probs, double tol, hipStream_t st) {
     using TL = typename Inner32Tiling<F>::TL;
@@ -1699,7 +1747,7 @@ struct Family {
   }
   static void sweep_groups(int nel, int* tpg, int* groups) {
     using TL = Tiling64<F::S, F::I>;
-    mfma_groups(nel, TL::TS, res_sweep(), *tpg, *groups);
+    tuned_groups(nel, TL::TS, res_sweep(), *tpg, *tpg, *groups);
   }
   static void step_groups(int nel, int* tpg, int* groups) {
     using TL = typename StepTiling<F>::TL;

@@ -267,6 +267,22 @@ def ehdg_batch_advance(b, n, rounds, rel_tol, step_targets=None):
     return state.tolist()
 
 
+def ehdg_tune_set(pde, dim, degree, precision, tiles_per_group, reverse_order=0):
+    _check(_lib.load().ehdg_tune_set(int(pde), int(dim), int(degree), int(precision), int(tiles_per_group),
+                                     int(reverse_order)))
+
+
+def ehdg_tune_clear():
+    _check(_lib.load().ehdg_tune_clear())
+
+
+def ehdg_launch_shape(h):
+    """(tiles per workgroup, workgroups, reversed order) of the handle's plain sweeps."""
+    tpg, ng, rev = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(_lib.load().ehdg_launch_shape(h, ctypes.byref(tpg), ctypes.byref(ng), ctypes.byref(rev)), h)
+    return tpg.value, ng.value, rev.value
+
+
 def ehdg_batch_set_graph(b, enabled):
     _check_batch(_lib.load().ehdg_batch_set_graph(b, int(bool(enabled))), b)
 

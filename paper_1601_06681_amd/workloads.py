@@ -106,9 +106,7 @@ def batch_mix(count=512, seed=0):
       transport: steady, b = (cos t, sin t), t ~ U[0, 2 pi), sigma ~ U[0.5, 2], the
                  manufactured solution of transport_manufactured_2d, inflow data u_e;
       swe:       periodic shallow water, Phi = 1, the Gaussian hump of seed 0, 5
-                 backward-Euler steps with dt (p+1)(p+2) / h = 0.25.
-    Transport problems of degree 1 are drawn at degree 2 instead (the degree-1 kernels
-    with two active axes are held back)."""
+                 backward-Euler steps with dt (p+1)(p+2) / h = 0.25."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
@@ -117,7 +115,7 @@ def batch_mix(count=512, seed=0):
         if rng.random() < 0.5:
             t = float(rng.uniform(0.0, 2.0 * PI))
             sigma = float(rng.uniform(0.5, 2.0))
-            out.append(dict(kind="transport", n=n, degree=max(p, 2), beta=(math.cos(t), math.sin(t)), sigma=sigma))
+            out.append(dict(kind="transport", n=n, degree=p, beta=(math.cos(t), math.sin(t)), sigma=sigma))
         else:
             h = 1.0 / n
             out.append(dict(kind="swe", n=n, degree=p, dt=0.25 * h / ((p + 1) * (p + 2)), steps=5))

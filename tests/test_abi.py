@@ -133,3 +133,18 @@ def test_degree1_two_axis_2d_transport_is_refused():
     assert E.ehdg_workspace_bytes(E.make_desc(E.EHDG_TRANSPORT, 2, (8, 8), degree=2, beta=(1.0, 0.5))) > 0
     assert E.ehdg_workspace_bytes(E.make_desc(E.EHDG_TRANSPORT, 3, (4, 4, 4), degree=1, beta=(1, 0.5, 0.2))) > 0
     assert E.ehdg_variable_workspace_bytes(E.make_desc(E.EHDG_TRANSPORT, 3, (4, 4, 4), degree=1)) > 0
+
+
+def test_tuning_registry_validation():
+    """ehdg_tune_set checks its arguments on the host (no GPU): negative tile counts and
+    refinement precisions are refused; clearing always succeeds."""
+    from paper_1601_06681_amd import ehdg as E
+    E.ehdg_tune_set(0, 2, 3, 0, 8, 1)
+    E.ehdg_tune_set(0, 2, 3, 0, 0, 0)          # removes the entry
+    with pytest.raises(E.EhdgError) as ei:
+        E.ehdg_tune_set(0, 2, 3, 0, -4, 0)
+    assert ei.value.code == 1
+    with pytest.raises(E.EhdgError) as ei:
+        E.ehdg_tune_set(0, 2, 3, 1, 8, 0)      # refinement forms have their own launches
+    assert ei.value.code == 1
+    E.ehdg_tune_clear()

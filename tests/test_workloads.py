@@ -45,10 +45,12 @@ def test_batch_mix_ranges_and_determinism():
     assert a != W.batch_mix(512, seed=1)
     kinds = [r["kind"] for r in a]
     assert 0.4 < kinds.count("swe") / len(a) < 0.6
+    # the draw is the whole specified mix: degree-1 transport members are present
+    assert any(r["kind"] == "transport" and r["degree"] == 1 for r in a)
     for r in a:
         assert 16 <= r["n"] <= 256
         if r["kind"] == "transport":
-            assert 2 <= r["degree"] <= 5
+            assert 1 <= r["degree"] <= 5
             assert math.isclose(math.hypot(*r["beta"]), 1.0, rel_tol=1e-12)
             assert 0.5 <= r["sigma"] <= 2.0
         else:
