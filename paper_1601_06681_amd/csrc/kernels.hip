@@ -2153,10 +2153,64 @@ __global__ void k_matvec(const double* __restrict__ M, int rows, int cols, const
   }
 }
 
+// y (+)= M x for EB elements per workgroup (M: rows x cols, row-major, shared by every
+// element; x, y: SoA).  The workgroup stages its elements' x columns in LDS once; thread t
+// takes element t % EB and every (256 / EB)-th block of four rows, so each x value read
+// from LDS feeds four FMAs and no x value is read from memory twice.  Every output is one
+// FMA chain over c in ascending order from the old value (or 0): the same arithmetic as
+// k_matvec, so the results are bitwise those of k_matvec.
+template <int EB>
+__global__ __launch_bounds__(256) void k_matvec_lds(const double* __restrict__ M, int rows, int cols,
+                                                    const double* __restrict__ x, double* __restrict__ y, int nel,
+                                                    int accumulate) {
+  extern __shared__ double xs[];  // [cols][EB]
+  constexpr int kStreams = 256 / EB, kR = 4;
+  const int t = threadIdx.x, el = t % EB, stream = t / EB;
+  const int e0 = blockIdx.x * EB;
+  const size_t n = (size_t)nel;
+  for (int i = t; i < cols * EB; i += 256) {
+    const int c = i / EB, l = i % EB;
+    xs[i] = e0 + l < nel ? x[(size_t)c * n + e0 + l] : 0.0;
+  }
+  __syncthreads();
+  const int e = e0 + el;
+  if (e >= nel) return;
+  for (int r0 = stream * kR; r0 < rows; r0 += kStreams * kR) {
+    // rows past the end compute on row rows-1 and are not stored
+    const double* Mr[kR];
+    double acc[kR];
+#pragma unroll
+    for (int k = 0; k < kR; ++k) {
+      const int r = min(r0 + k, rows - 1);
+      Mr[k] = M + (size_t)r * cols;
+      acc[k] = accumulate ? y[(size_t)r * n + e] : 0.0;
+    }
+#pragma unroll 2
+    for (int c = 0; c < cols; ++c) {
+      const double xv = xs[c * EB + el];
+#pragma unroll
+      for (int k = 0; k < kR; ++k) acc[k] = fma(Mr[k][c], xv, acc[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kR; ++k)
+      if (r0 + k < rows) y[(size_t)(r0 + k) * n + e] = acc[k];
+  }
+}
+
 void launch_matvec(const double* M, int rows, int cols, const double* x, double* y, int nel, bool accumulate,
                    hipStream_t st) {
-  hipLaunchKernelGGL(k_matvec, dim3(nblocks(nel)), dim3(kBlock), 0, st, M, rows, cols, x, y, nel,
-                     accumulate ? 1 : 0);
+  if (nel <= 0 || rows <= 0) return;
+  constexpr size_t kLds = 64 * 1024;
+  if ((size_t)cols * 64 * sizeof(double) <= kLds) {
+    hipLaunchKernelGGL(k_matvec_lds<64>, dim3((nel + 63) / 64), dim3(256), (size_t)cols * 64 * sizeof(double), st, M,
+                       rows, cols, x, y, nel, accumulate ? 1 : 0);
+  } else if ((size_t)cols * 32 * sizeof(double) <= kLds) {
+    hipLaunchKernelGGL(k_matvec_lds<32>, dim3((nel + 31) / 32), dim3(256), (size_t)cols * 32 * sizeof(double), st, M,
+                       rows, cols, x, y, nel, accumulate ? 1 : 0);
+  } else {
+    hipLaunchKernelGGL(k_matvec, dim3(nblocks(nel)), dim3(kBlock), 0, st, M, rows, cols, x, y, nel,
+                       accumulate ? 1 : 0);
+  }
 }
 
 __global__ void k_matvec_pe(const double* __restrict__ M, int rows, int cols, const double* __restrict__ x,
@@ -2177,30 +2231,50 @@ void launch_matvec_pe(const double* M, int rows, int cols, const double* x, doub
                      cols, x, y, nel, accumulate ? 1 : 0);
 }
 
-__global__ void k_transpose(const double* __restrict__ src, double* __restrict__ dst, int K, int nel, int to_soa) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t total = (size_t)K * nel;
-  if (i >= total) return;
-  // i indexes the destination
+// ext [nel][K] <-> SoA [K][nel] through a 64-element x 32-value LDS tile, so that both the
+// reads and the writes are runs of consecutive addresses.
+constexpr int kTrE = 64, kTrK = 32;
+__global__ __launch_bounds__(256) void k_transpose_tiled(const double* __restrict__ src, double* __restrict__ dst,
+                                                         int K, int nel, int to_soa) {
+  __shared__ double tile[kTrE][kTrK + 1];
+  const int e0 = blockIdx.x * kTrE, k0 = blockIdx.y * kTrK;
+  const int ne = min(kTrE, nel - e0), nk = min(kTrK, K - k0);
+  const size_t n = (size_t)nel;
   if (to_soa) {
-    const size_t k = i / nel, e = i % nel;
-    dst[i] = src[e * K + k];
+    for (int i = threadIdx.x; i < kTrE * kTrK; i += 256) {
+      const int el = i / kTrK, kl = i % kTrK;
+      if (el < ne && kl < nk) tile[el][kl] = src[(size_t)(e0 + el) * K + k0 + kl];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTrE * kTrK; i += 256) {
+      const int kl = i / kTrE, el = i % kTrE;
+      if (el < ne && kl < nk) dst[(size_t)(k0 + kl) * n + e0 + el] = tile[el][kl];
+    }
   } else {
-    const size_t e = i / K, k = i % K;
-    dst[i] = src[k * nel + e];
+    for (int i = threadIdx.x; i < kTrE * kTrK; i += 256) {
+      const int kl = i / kTrE, el = i % kTrE;
+      if (el < ne && kl < nk) tile[el][kl] = src[(size_t)(k0 + kl) * n + e0 + el];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTrE * kTrK; i += 256) {
+      const int el = i / kTrK, kl = i % kTrK;
+      if (el < ne && kl < nk) dst[(size_t)(e0 + el) * K + k0 + kl] = tile[el][kl];
+    }
   }
 }
 
+static void launch_transpose(const double* src, double* dst, int K, int nel, int to_soa, hipStream_t st) {
+  if (K <= 0 || nel <= 0) return;
+  const dim3 grid((unsigned)((nel + kTrE - 1) / kTrE), (unsigned)((K + kTrK - 1) / kTrK));
+  hipLaunchKernelGGL(k_transpose_tiled, grid, dim3(256), 0, st, src, dst, K, nel, to_soa);
+}
+
 void launch_ext_to_soa(const double* ext, double* soa, int K, int nel, hipStream_t st) {
-  const size_t total = (size_t)K * nel;
-  hipLaunchKernelGGL(k_transpose, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, ext, soa,
-                     K, nel, 1);
+  launch_transpose(ext, soa, K, nel, 1, st);
 }
 
 void launch_soa_to_ext(const double* soa, double* ext, int K, int nel, hipStream_t st) {
-  const size_t total = (size_t)K * nel;
-  hipLaunchKernelGGL(k_transpose, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, soa, ext,
-                     K, nel, 0);
+  launch_transpose(soa, ext, K, nel, 0, st);
 }
 
 __global__ void k_fill(double* p, double v, size_t count) {
