@@ -505,11 +505,17 @@ def run_serving(torch, args):
     rate = 0.8 / service.mean()
     arrivals = np.cumsum([r["gap"] for r in reqs]) / rate
     fifo_lat, fifo_end = S.fifo_latencies(arrivals, service)
-    server = S.Server(args.serve_hbm_gb * 2 ** 30, rounds=args.serve_rounds)
+    server = S.Server(args.serve_hbm_gb * 2 ** 30, rounds=args.serve_rounds, depth=args.serve_depth,
+                      max_active=args.serve_max_active or None, lookahead=args.serve_lookahead)
     out = server.run(reqs, arrivals)
     lat = out["latency"]
+    log(f"[bench] serving: batched run done ({out['makespan']:.1f} s)")
     # capacity: everything queued at once (the FIFO capacity is 1 / mean service time)
     sat = server.run(reqs, np.zeros(len(reqs)))
+    log(f"[bench] serving: saturated run done ({sat['makespan']:.1f} s)")
+    # one member at a time: first in, first out, with the next requests' set-up overlapped
+    one = S.Server(args.serve_hbm_gb * 2 ** 30, rounds=args.serve_rounds, depth=2, max_active=1,
+                   lookahead=args.serve_lookahead).run(reqs, arrivals)
 
     def pct(x):
         return {"p50_ms": float(np.percentile(x, 50) * 1e3), "p99_ms": float(np.percentile(x, 99) * 1e3)}
@@ -518,14 +524,22 @@ def run_serving(torch, args):
            "fifo_fp64": {**pct(fifo_lat), "throughput_per_s": len(reqs) / fifo_end,
                          "mean_service_ms": float(service.mean() * 1e3)},
            "continuous_batching": {**pct(lat), "throughput_per_s": len(reqs) / out["makespan"],
-                                   "ticks": out["ticks"], "batches": out["batches"],
+                                   "launches": out["launches"], "batches": out["batches"],
                                    "peak_workspace_gb": out["peak_bytes"] / 2 ** 30,
-                                   "hbm_budget_gb": args.serve_hbm_gb, "rounds_per_tick": args.serve_rounds},
+                                   "hbm_budget_gb": args.serve_hbm_gb, "rounds_per_launch": args.serve_rounds,
+                                   "launches_queued_ahead": args.serve_depth,
+                                   "max_active": args.serve_max_active or None,
+                                   "lookahead": args.serve_lookahead},
+           "one_member_overlapped_setup": {**pct(one["latency"]), "throughput_per_s": len(reqs) / one["makespan"],
+                                           "launches": one["launches"], "rounds_per_launch": args.serve_rounds,
+                                           "launches_queued_ahead": 2},
            "capacity_per_s": {"fifo_fp64": float(1.0 / service.mean()),
                               "continuous_batching": len(reqs) / sat["makespan"]}}
     log(f"[bench] serving: FIFO p50 {res['fifo_fp64']['p50_ms']:.1f} ms p99 {res['fifo_fp64']['p99_ms']:.1f} ms; "
         f"batched p50 {res['continuous_batching']['p50_ms']:.1f} ms p99 {res['continuous_batching']['p99_ms']:.1f} ms; "
-        f"capacity {res['capacity_per_s']['fifo_fp64']:.1f} vs {res['capacity_per_s']['continuous_batching']:.1f} /s")
+        f"capacity {res['capacity_per_s']['fifo_fp64']:.1f} vs {res['capacity_per_s']['continuous_batching']:.1f} /s; "
+        f"one member p50 {res['one_member_overlapped_setup']['p50_ms']:.1f} ms "
+        f"p99 {res['one_member_overlapped_setup']['p99_ms']:.1f} ms")
     return res
 
 
@@ -640,7 +654,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--serve-hbm-gb", type=float, default=64.0)
-    ap.add_argument("--serve-rounds", type=int, default=96)
+    ap.add_argument("--serve-rounds", type=int, default=16, help="rounds per launch")
+    ap.add_argument("--serve-depth", type=int, default=3, help="launches queued ahead")
+    ap.add_argument("--serve-max-active", type=int, default=2, help="batch members at most (0: no limit)")
+    ap.add_argument("--serve-lookahead", type=int, default=2, help="requests set up ahead of the batch")
     ap.add_argument("--counter-sample", action="store_true",
                     help="only the copy-calibration kernel and a few sweeps, for rocprofv3 --pmc")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),

@@ -302,6 +302,37 @@ int ehdg_batch_step(ehdg_batch b, int32_t n_steps, double rel_tol, int32_t max_i
  * result. */
 int ehdg_batch_advance(ehdg_batch b, int32_t rounds, double rel_tol, const int32_t* step_targets, int32_t* state);
 
+/* Asynchronous rounds with a report per launch, for serving loops that keep the GPU busy
+ * while they admit and retire problems.
+ *
+ * ehdg_batch_launch queues `rounds` rounds (as ehdg_batch_advance; step_targets is
+ * required when the batch has backward-Euler members), then a copy of every member's
+ * control block into h_report, and returns without waiting.  h_report: host memory of at
+ * least ehdg_batch_report_bytes, pinned (hipHostMalloc; pageable memory makes the copy,
+ * and so the call, wait for the rounds), owned by the caller, left untouched until the
+ * launch's report is read, and not shared with another pending launch.  At most four
+ * launches may be pending; INVALID_ARG beyond that.
+ *
+ * ehdg_batch_poll reads the oldest pending launch's report if its work has completed:
+ * *ready = 1, state[] (host array of n, or NULL) as ehdg_batch_advance gives it, and
+ * the members' host-side control-block copies refreshed; else *ready = 0 without waiting.
+ * INVALID_ARG when no launch is pending.
+ *
+ * ehdg_batch_get_solution queues on the batch's stream the solution of a member that the
+ * last report read showed finished (state 1; INVALID_ARG otherwise) into d_u (device,
+ * layout as ehdg_get_solution); later rounds leave a finished member unchanged, so this
+ * may follow pending launches.  Asynchronous.
+ *
+ * Ordering: every batch call queues its work after what the members' own streams hold at
+ * the call (the batch stream waits on an event recorded there; static batches wait on the
+ * host).  ehdg_batch_solve, _step and _advance return INVALID_ARG while launches are
+ * pending.  ehdg_batch_destroy waits for the batch's own queued work. */
+int ehdg_batch_report_bytes(ehdg_batch b, size_t* bytes);
+int ehdg_batch_launch(ehdg_batch b, int32_t rounds, double rel_tol, const int32_t* step_targets, void* h_report,
+                      size_t report_bytes);
+int ehdg_batch_poll(ehdg_batch b, int32_t* state, int32_t* ready);
+int ehdg_batch_get_solution(ehdg_batch b, int32_t member, double* d_u);
+
 /* Rounds as a captured HIP graph (enabled != 0, the default for ehdg_batch_create) or as
  * launches queued one by one (0).  The graph is captured on a private stream of the batch
  * and replayed on the batch's stream; a caller's stream that is itself being captured gets

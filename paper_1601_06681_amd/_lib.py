@@ -32,7 +32,8 @@ EXPORTED = [
     "ehdg_last_error", "ehdg_batch_workspace_bytes", "ehdg_batch_create", "ehdg_batch_solve", "ehdg_batch_step",
     "ehdg_batch_advance", "ehdg_batch_destroy", "ehdg_batch_last_error", "ehdg_variable_workspace_bytes",
     "ehdg_setup_variable", "ehdg_batch_create_static", "ehdg_batch_set_graph", "ehdg_tune_set",
-    "ehdg_tune_clear", "ehdg_launch_shape",
+    "ehdg_tune_clear", "ehdg_launch_shape", "ehdg_batch_report_bytes", "ehdg_batch_launch", "ehdg_batch_poll",
+    "ehdg_batch_get_solution",
 ]
 
 
@@ -97,6 +98,10 @@ def load():
         "ehdg_batch_solve": (ctypes.c_int, [P, D, I32, P, P]),
         "ehdg_batch_step": (ctypes.c_int, [P, I32, D, I32, P]),
         "ehdg_batch_advance": (ctypes.c_int, [P, I32, D, P, P]),
+        "ehdg_batch_report_bytes": (ctypes.c_int, [P, ctypes.POINTER(SZ)]),
+        "ehdg_batch_launch": (ctypes.c_int, [P, I32, D, P, P, SZ]),
+        "ehdg_batch_poll": (ctypes.c_int, [P, P, ctypes.POINTER(I32)]),
+        "ehdg_batch_get_solution": (ctypes.c_int, [P, I32, P]),
         "ehdg_batch_destroy": (ctypes.c_int, [P]),
         "ehdg_batch_last_error": (ctypes.c_char_p, [P]),
         "ehdg_variable_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(ehdg_desc), ctypes.POINTER(SZ)]),

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <tuple>
 #include <mutex>
@@ -702,21 +703,34 @@ int ehdg_step(ehdg_handle h, int32_t n_steps, double rel_tol, int32_t max_iters_
   return EHDG_OK;
 }
 
-int ehdg_get_solution(ehdg_handle h, double* d_u) {
-  if (!h || !d_u) return EHDG_ERR_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+// Queues on st the element solution of the state the host mirror describes into d_u
+// (external layout): the recovery from the latest sweep's traces, unless it is there
+// already or no sweep ran since the current time level was set.
+void queue_solution(ehdg_problem* h, double* d_u, hipStream_t st) {
   DevProblem& dp = h->dp;
-  int rc = sync_ctrl(h);
-  if (rc) return rc;
   const Ctrl& c = h->mirror;
   const double* src = u_cur(h);
   if (h->recovered == 1) {
     src = u_other(h);
   } else if (c.iters > 0 && !mixed(h)) {
-    recover(h, (c.base + c.iters - 1) & 1);
+    recover(h, (c.base + c.iters - 1) & 1, st);
     h->recovered = 1;
     src = u_other(h);
   }
-  launch_soa_to_ext(src, d_u, dp.n, dp.mesh.nel, h->stream);
+  launch_soa_to_ext(src, d_u, dp.n, dp.mesh.nel, st);
+}
+}  // namespace
+
+extern "C" {
+
+int ehdg_get_solution(ehdg_handle h, double* d_u) {
+  if (!h || !d_u) return EHDG_ERR_INVALID_ARG;
+  int rc = sync_ctrl(h);
+  if (rc) return rc;
+  queue_solution(h, d_u, h->stream);
   return check_launch(h);
 }
 
@@ -865,6 +879,26 @@ struct ehdg_batch_s {
   std::vector<BatchProblem> probs;
   std::vector<Ctrl> ctrl;
   std::string err;
+  // the workgroup table as uploaded (the upload is asynchronous: kept until destroy) and
+  // whether d_probs holds `probs` already
+  std::vector<BatchEntry> table_host;
+  bool probs_valid = false;
+  // asynchronous rounds (ehdg_batch_launch / ehdg_batch_poll): launches whose report has
+  // not been read, oldest first, each with the event recorded after its report copy
+  static constexpr int kMaxPending = 4;
+  struct Pending {
+    int slot;
+    const Ctrl* report;
+    std::vector<int> target;
+  };
+  hipEvent_t ev[kMaxPending] = {};
+  std::deque<Pending> pending;
+  unsigned launches = 0;
+  std::vector<int> polled;        // per member: state in the last report read (-1: none)
+  hipEvent_t join_ev = nullptr;   // orders the batch stream after the members' own streams
+  hipEvent_t last_ev = nullptr;   // after the batch's latest asynchronous work
+  bool last_ev_set = false;
+  hipEvent_t probs_ev = nullptr;  // after the latest upload of `probs`
 };
 
 // Device scratch of ehdg_batch_create_static: the batch's problem descriptors, workgroup
@@ -980,9 +1014,10 @@ int batch_check(const ehdg_handle* handles, int32_t n, std::vector<ehdg_problem*
 // Device copies of the members' current state pointers (forcing may have changed since
 // the batch was made) with each member's step limit, and uploads them.
 int batch_upload(ehdg_batch_s* b, const std::vector<int>& steps_target) {
+  std::vector<BatchProblem> np(b->h.size(), BatchProblem{});
   for (size_t i = 0; i < b->h.size(); ++i) {
     const DevProblem& dp = b->h[i]->dp;
-    BatchProblem& P = b->probs[i];
+    BatchProblem& P = np[i];
     P.mesh = dp.mesh;
     P.steps_target = steps_target[i];
     P.hist_cap = dp.hist_cap;
@@ -1004,8 +1039,25 @@ int batch_upload(ehdg_batch_s* b, const std::vector<int>& steps_target) {
     P.hist = dp.hist;
     P.step_iters = dp.step_iters;
   }
+  // the kernels only read the descriptors: skip an upload of what d_probs holds already
+  if (b->probs_valid && std::memcmp(np.data(), b->probs.data(), np.size() * sizeof(BatchProblem)) == 0)
+    return EHDG_OK;
+  // the host copy is the source of an asynchronous upload: an earlier upload from it must
+  // have completed before it is rewritten
+  if (b->probs_valid) {
+    if (b->probs_ev)
+      HIP_TRY_B(b, hipEventSynchronize(b->probs_ev));
+    else
+      HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+  }
+  b->probs.swap(np);
   HIP_TRY_B(b, hipMemcpyAsync(b->d_probs, b->probs.data(), b->probs.size() * sizeof(BatchProblem),
                               hipMemcpyHostToDevice, b->stream));
+  if (!b->is_static) {  // static batches create no events
+    if (!b->probs_ev) HIP_TRY_B(b, hipEventCreateWithFlags(&b->probs_ev, hipEventDisableTiming));
+    HIP_TRY_B(b, hipEventRecord(b->probs_ev, b->stream));
+  }
+  b->probs_valid = true;
   return EHDG_OK;
 }
 
@@ -1013,12 +1065,38 @@ int batch_upload(ehdg_batch_s* b, const std::vector<int>& steps_target) {
 // refuses a static batch whose tables a later static batch on its device has replaced
 int batch_quiesce(ehdg_batch_s* b) {
   if (b->is_static) {
-    StaticScratch& ss = static_scratch();
-    std::lock_guard<std::mutex> lk(ss.mu);
-    if (ss.gen[b->dev] != b->gen)
-      return bfail(b, EHDG_ERR_INVALID_ARG, "static batch replaced by a later ehdg_batch_create_static on its device");
+    {
+      StaticScratch& ss = static_scratch();
+      std::lock_guard<std::mutex> lk(ss.mu);
+      if (ss.gen[b->dev] != b->gen)
+        return bfail(b, EHDG_ERR_INVALID_ARG, "static batch replaced by a later ehdg_batch_create_static on its device");
+    }
+    for (auto* h : b->h) HIP_TRY_B(b, hipStreamSynchronize(h->stream));
+    return EHDG_OK;
   }
-  for (auto* h : b->h) HIP_TRY_B(b, hipStreamSynchronize(h->stream));
+  // the batch stream waits for what is queued on each other member stream (no host wait)
+  std::vector<hipStream_t> seen;
+  for (auto* h : b->h) {
+    if (h->stream == b->stream || std::find(seen.begin(), seen.end(), h->stream) != seen.end()) continue;
+    seen.push_back(h->stream);
+    if (!b->join_ev) HIP_TRY_B(b, hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming));
+    HIP_TRY_B(b, hipEventRecord(b->join_ev, h->stream));
+    HIP_TRY_B(b, hipStreamWaitEvent(b->stream, b->join_ev, 0));
+  }
+  return EHDG_OK;
+}
+
+// records the batch's latest asynchronous work (the event destroy and uploads wait for)
+int mark_last(ehdg_batch_s* b) {
+  if (!b->last_ev) HIP_TRY_B(b, hipEventCreateWithFlags(&b->last_ev, hipEventDisableTiming));
+  HIP_TRY_B(b, hipEventRecord(b->last_ev, b->stream));
+  b->last_ev_set = true;
+  return EHDG_OK;
+}
+
+int no_pending(ehdg_batch_s* b) {
+  if (!b->pending.empty())
+    return bfail(b, EHDG_ERR_INVALID_ARG, "launches of ehdg_batch_launch are pending: read them with ehdg_batch_poll");
   return EHDG_OK;
 }
 
@@ -1115,7 +1193,7 @@ namespace {
 
 // ehdg_batch_create's work with the tables at d_workspace (256-byte aligned, bytes long)
 int batch_create_in(std::vector<ehdg_problem*>& hs, void* d_workspace, size_t workspace_bytes, void* stream,
-                    ehdg_batch_s** out) {
+                    ehdg_batch_s** out, bool in_static) {
   ehdg_batch_s* b = new (std::nothrow) ehdg_batch_s();
   if (!b) return EHDG_ERR_INVALID_ARG;
   b->h = hs;
@@ -1133,9 +1211,14 @@ int batch_create_in(std::vector<ehdg_problem*>& hs, void* d_workspace, size_t wo
   b->d_ctrl = (Ctrl*)(ws + L.off_ctrl);
   b->probs.assign(hs.size(), BatchProblem{});
   b->ctrl.assign(hs.size(), Ctrl{});
-  if (hipMemcpyAsync(b->d_table, table.data(), table.size() * sizeof(BatchEntry), hipMemcpyHostToDevice,
-                     b->stream) != hipSuccess ||
-      hipStreamSynchronize(b->stream) != hipSuccess) {
+  b->polled.assign(hs.size(), -1);
+  b->table_host.swap(table);
+  // asynchronous upload from table_host, which lives until destroy (destroy waits for it);
+  // static batches create no events: their upload completes here
+  if (hipMemcpyAsync(b->d_table, b->table_host.data(), b->table_host.size() * sizeof(BatchEntry),
+                     hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+      (in_static ? hipStreamSynchronize(b->stream) != hipSuccess : mark_last(b) != EHDG_OK)) {
+    if (b->last_ev) (void)hipEventDestroy(b->last_ev);
     delete b;
     return EHDG_ERR_HIP;
   }
@@ -1155,7 +1238,7 @@ int ehdg_batch_create(const ehdg_handle* handles, int32_t n, void* d_workspace, 
   int rc = batch_check(handles, n, hs);
   if (rc) return rc;
   if (!d_workspace || ((uintptr_t)d_workspace & 255)) return EHDG_ERR_INVALID_ARG;
-  return batch_create_in(hs, d_workspace, workspace_bytes, stream, out);
+  return batch_create_in(hs, d_workspace, workspace_bytes, stream, out, false);
 }
 
 int ehdg_batch_create_static(const ehdg_handle* handles, int32_t n, void* stream, ehdg_batch* out) {
@@ -1187,7 +1270,7 @@ int ehdg_batch_create_static(const ehdg_handle* handles, int32_t n, void* stream
     ptr = ss.ptr[dev];
     gen = ++ss.gen[dev];  // any earlier static batch on this device is now replaced
   }
-  rc = batch_create_in(hs, ptr, kStaticBatchBytes, stream, out);
+  rc = batch_create_in(hs, ptr, kStaticBatchBytes, stream, out, true);
   if (rc) return rc;
   (*out)->is_static = true;
   (*out)->use_graph = false;  // graph instantiation allocates: static batches launch eagerly
@@ -1199,7 +1282,8 @@ int ehdg_batch_create_static(const ehdg_handle* handles, int32_t n, void* stream
 int ehdg_batch_solve(ehdg_batch b, double rel_tol, int32_t max_iters, int32_t* iters, double* rel_res) {
   if (!b || max_iters < 1 || !(rel_tol >= 0.0)) return EHDG_ERR_INVALID_ARG;
   const size_t n = b->h.size();
-  int rc = batch_quiesce(b);
+  int rc = no_pending(b);
+  if (!rc) rc = batch_quiesce(b);
   if (!rc) rc = batch_upload(b, std::vector<int>(n, INT32_MAX));
   if (rc) return rc;
   launch_ctrl_reset_batch(b->d_probs, (int)n, 0, b->stream);
@@ -1246,7 +1330,8 @@ int ehdg_batch_step(ehdg_batch b, int32_t n_steps, double rel_tol, int32_t max_i
     if (!h->dp.be) return bfail(b, EHDG_ERR_INVALID_ARG, "ehdg_batch_step needs backward-Euler members");
   if (n_steps == 0) return EHDG_OK;
   const size_t n = b->h.size();
-  int rc = batch_quiesce(b);
+  int rc = no_pending(b);
+  if (!rc) rc = batch_quiesce(b);
   if (rc) return rc;
   // the first step of each member continues from its latest state
   if ((rc = batch_upload(b, std::vector<int>(n, INT32_MAX)))) return rc;
@@ -1316,7 +1401,8 @@ int ehdg_batch_step(ehdg_batch b, int32_t n_steps, double rel_tol, int32_t max_i
 int ehdg_batch_advance(ehdg_batch b, int32_t rounds, double rel_tol, const int32_t* step_targets, int32_t* state) {
   if (!b || rounds < 0 || !(rel_tol >= 0.0) || !state) return EHDG_ERR_INVALID_ARG;
   const size_t n = b->h.size();
-  int rc = batch_quiesce(b);
+  int rc = no_pending(b);
+  if (!rc) rc = batch_quiesce(b);
   if (rc) return rc;
   std::vector<int> target(n, INT32_MAX);
   bool any_be = false;
@@ -1339,8 +1425,97 @@ int ehdg_batch_advance(ehdg_batch b, int32_t rounds, double rel_tol, const int32
       state[i] = c.steps_done >= target[i] ? 1 : 0;
     else
       state[i] = c.status == 1 ? 1 : 0;
+    b->polled[i] = state[i];
   }
   return EHDG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// state of member i in a control block: 2 non-finite increment, 1 finished (converged, or
+// took `target` steps for a backward-Euler member), 0 running
+int member_state(const ehdg_problem* h, const Ctrl& c, int target) {
+  if (c.status == 2) return 2;
+  if (h->dp.be) return c.steps_done >= target ? 1 : 0;
+  return c.status == 1 ? 1 : 0;
+}
+}  // namespace
+
+extern "C" {
+
+int ehdg_batch_report_bytes(ehdg_batch b, size_t* bytes) {
+  if (!b || !bytes) return EHDG_ERR_INVALID_ARG;
+  *bytes = b->h.size() * sizeof(Ctrl);
+  return EHDG_OK;
+}
+
+int ehdg_batch_launch(ehdg_batch b, int32_t rounds, double rel_tol, const int32_t* step_targets, void* h_report,
+                      size_t report_bytes) {
+  if (!b || rounds < 1 || !(rel_tol >= 0.0) || !h_report) return EHDG_ERR_INVALID_ARG;
+  const size_t n = b->h.size();
+  if (report_bytes < n * sizeof(Ctrl)) return bfail(b, EHDG_ERR_INVALID_ARG, "report buffer smaller than ehdg_batch_report_bytes");
+  if ((int)b->pending.size() >= ehdg_batch_s::kMaxPending)
+    return bfail(b, EHDG_ERR_INVALID_ARG, "four launches pending: read one with ehdg_batch_poll first");
+  for (const auto& p : b->pending)
+    if ((const void*)p.report == h_report)
+      return bfail(b, EHDG_ERR_INVALID_ARG, "report buffer in use by a pending launch");
+  std::vector<int> target(n, INT32_MAX);
+  bool any_be = false;
+  for (size_t i = 0; i < n; ++i) {
+    if (!b->h[i]->dp.be) continue;
+    if (!step_targets) return bfail(b, EHDG_ERR_INVALID_ARG, "backward-Euler members need step targets");
+    any_be = true;
+    target[i] = step_targets[i];
+  }
+  int rc = batch_quiesce(b);
+  if (!rc) rc = batch_upload(b, target);
+  if (!rc) rc = run_rounds(b, rounds, rel_tol, any_be ? 1 : 0);
+  if (rc) return rc;
+  const int slot = (int)(b->launches % ehdg_batch_s::kMaxPending);
+  if (!b->ev[slot]) HIP_TRY_B(b, hipEventCreateWithFlags(&b->ev[slot], hipEventDisableTiming));
+  launch_ctrl_gather(b->d_probs, (int)n, b->d_ctrl, b->stream);
+  HIP_TRY_B(b, hipMemcpyAsync(h_report, b->d_ctrl, n * sizeof(Ctrl), hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY_B(b, hipEventRecord(b->ev[slot], b->stream));
+  if ((rc = mark_last(b)) || (rc = batch_check_launch(b))) return rc;
+  b->pending.push_back({slot, (const Ctrl*)h_report, std::move(target)});
+  ++b->launches;
+  return EHDG_OK;
+}
+
+int ehdg_batch_poll(ehdg_batch b, int32_t* state, int32_t* ready) {
+  if (!b || !ready) return EHDG_ERR_INVALID_ARG;
+  *ready = 0;
+  if (b->pending.empty()) return bfail(b, EHDG_ERR_INVALID_ARG, "no launch pending");
+  const ehdg_batch_s::Pending& p = b->pending.front();
+  const hipError_t e = hipEventQuery(b->ev[p.slot]);
+  if (e == hipErrorNotReady) {
+    (void)hipGetLastError();  // not an error: leave no trace for later launch checks
+    return EHDG_OK;
+  }
+  if (e != hipSuccess) return bfail(b, EHDG_ERR_HIP, std::string("hipEventQuery: ") + hipGetErrorString(e));
+  for (size_t i = 0; i < b->h.size(); ++i) {
+    ehdg_problem* h = b->h[i];
+    const int st = member_state(h, p.report[i], p.target[i]);
+    // a finished member keeps its state (later rounds leave it), and with it its recovery
+    if (!(b->polled[i] == 1 && st == 1)) h->recovered = -1;
+    h->mirror = p.report[i];
+    b->polled[i] = st;
+    if (state) state[i] = st;
+  }
+  b->pending.pop_front();
+  *ready = 1;
+  return EHDG_OK;
+}
+
+int ehdg_batch_get_solution(ehdg_batch b, int32_t member, double* d_u) {
+  if (!b || !d_u || member < 0 || member >= (int32_t)b->h.size()) return EHDG_ERR_INVALID_ARG;
+  if (b->polled[member] != 1)
+    return bfail(b, EHDG_ERR_INVALID_ARG, "member not reported finished by the last report read");
+  queue_solution(b->h[member], d_u, b->stream);
+  int rc = batch_check_launch(b);
+  if (!rc && !b->is_static) rc = mark_last(b);
+  return rc;
 }
 
 int ehdg_batch_set_graph(ehdg_batch b, int32_t enabled) {
@@ -1353,8 +1528,15 @@ int ehdg_batch_set_graph(ehdg_batch b, int32_t enabled) {
 
 int ehdg_batch_destroy(ehdg_batch b) {
   if (!b) return EHDG_ERR_INVALID_ARG;
+  // the batch's own queued work (launches, uploads from its host copies) ends first
+  if (b->last_ev_set) (void)hipEventSynchronize(b->last_ev);
   drop_graph(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (auto& e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (b->join_ev) (void)hipEventDestroy(b->join_ev);
+  if (b->probs_ev) (void)hipEventDestroy(b->probs_ev);
+  if (b->last_ev) (void)hipEventDestroy(b->last_ev);
   delete b;
   return EHDG_OK;
 }

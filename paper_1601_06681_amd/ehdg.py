@@ -267,6 +267,36 @@ def ehdg_batch_advance(b, n, rounds, rel_tol, step_targets=None):
     return state.tolist()
 
 
+def ehdg_batch_report_bytes(b):
+    n = ctypes.c_size_t(0)
+    _check_batch(_lib.load().ehdg_batch_report_bytes(b, ctypes.byref(n)), b)
+    return n.value
+
+
+def ehdg_batch_launch(b, rounds, rel_tol, step_targets, report):
+    """Queues `rounds` rounds and a report into `report` (a pinned host tensor of at least
+    ehdg_batch_report_bytes bytes); returns at once."""
+    tg = None
+    if step_targets is not None:
+        tg = np.ascontiguousarray(step_targets, dtype=np.int32)
+    rc = _lib.load().ehdg_batch_launch(b, int(rounds), float(rel_tol),
+                                       tg.ctypes.data_as(ctypes.c_void_p) if tg is not None else None,
+                                       _ptr(report), report.numel() * report.element_size())
+    _check_batch(rc, b)
+
+
+def ehdg_batch_poll(b, n):
+    """The oldest pending launch's member states if its work has completed, else None."""
+    state = np.zeros(n, dtype=np.int32)
+    ready = ctypes.c_int32(0)
+    _check_batch(_lib.load().ehdg_batch_poll(b, state.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ready)), b)
+    return state.tolist() if ready.value else None
+
+
+def ehdg_batch_get_solution(b, member, out):
+    _check_batch(_lib.load().ehdg_batch_get_solution(b, int(member), _ptr(out)), b)
+
+
 def ehdg_tune_set(pde, dim, degree, precision, tiles_per_group, reverse_order=0):
     _check(_lib.load().ehdg_tune_set(int(pde), int(dim), int(degree), int(precision), int(tiles_per_group),
                                      int(reverse_order)))
@@ -326,6 +356,25 @@ class Batch:
     def advance(self, rounds, tol, step_targets=None):
         """Member states after `rounds` more rounds: 0 running, 1 finished, 2 failed."""
         return ehdg_batch_advance(self.b, len(self.problems), rounds, tol, step_targets)
+
+    def report_bytes(self):
+        return ehdg_batch_report_bytes(self.b)
+
+    def launch(self, rounds, tol, step_targets, report):
+        """Queues `rounds` rounds and their report (pinned host tensor); does not wait."""
+        ehdg_batch_launch(self.b, rounds, tol, step_targets, report)
+
+    def poll(self):
+        """Member states of the oldest pending launch once it has completed, else None."""
+        return ehdg_batch_poll(self.b, len(self.problems))
+
+    def solution(self, k, out=None):
+        """Queues member k's solution (finished in the last report read) into `out`."""
+        p = self.problems[k]
+        if out is None:
+            out = p.torch.empty(p.nel, p.m, p.Np, dtype=p.torch.float64, device=p.device)
+        ehdg_batch_get_solution(self.b, k, out)
+        return out
 
     def close(self):
         if self.b is not None:

@@ -192,3 +192,104 @@ def test_batch_graph_replays_equal_eager_launches():
     for a, b in zip(u1, u2):
         for x, y in zip(a, b):
             assert torch.equal(x, y)
+
+
+def _pinned_reports(batch, count):
+    import torch
+    return [torch.empty(batch.report_bytes(), dtype=torch.uint8, pin_memory=True) for _ in range(count)]
+
+
+def test_async_launches_equal_advance_and_retire_members_early():
+    """ehdg_batch_launch / _poll / _get_solution: three launches queued ahead, reports read
+    in order without waiting, each member retired from the first report that shows it
+    finished while later launches are still queued.  The retired solutions and the
+    members' iteration counts equal those of the same batch driven by ehdg_batch_advance
+    (and so those of each problem alone), bitwise."""
+    import torch
+    from paper_1601_06681_amd import ehdg as E
+
+    def members():
+        return [_transport(c) for c in STEADY[:4]] + [mk() for mk in _be_members()[:3]]
+    targets = [0, 0, 0, 0, 4, 3, 5]
+    ref = members()
+    rb = E.Batch(ref)
+    while True:
+        st = rb.advance(16, 1e-10, targets)
+        if all(s == 1 for s in st):
+            break
+    ref_u = [p.solution().clone() for p in ref]
+    ref_it = [p.iters() for p in ref]
+    rb.close()
+
+    ms = members()
+    b = E.Batch(ms)
+    b.set_graph(False)
+    reps = _pinned_reports(b, 3)
+    inflight = []
+    for r in reps:
+        b.launch(16, 1e-10, targets, r)
+        inflight.append(r)
+    with pytest.raises(E.EhdgError) as ei:       # a report buffer of a pending launch
+        b.launch(16, 1e-10, targets, reps[0])
+    assert ei.value.code == E.EHDG_ERR_INVALID_ARG
+    with pytest.raises(E.EhdgError) as ei:       # synchronous calls wait for the reports
+        b.advance(1, 1e-10, targets)
+    assert ei.value.code == E.EHDG_ERR_INVALID_ARG
+    got, polls, reports = {}, 0, 0
+    while len(got) < len(ms):
+        st = b.poll()
+        polls += 1
+        if st is None:
+            continue
+        reports += 1
+        r = inflight.pop(0)
+        for k, s in enumerate(st):
+            assert s in (0, 1)
+            if s == 1 and k not in got:
+                got[k] = b.solution(k)
+        if len(got) < len(ms):
+            b.launch(16, 1e-10, targets, r)
+            inflight.append(r)
+    while inflight:                              # drain the launches still queued
+        if b.poll() is not None:
+            inflight.pop(0)
+    with pytest.raises(E.EhdgError) as ei:       # nothing pending
+        b.poll()
+    assert ei.value.code == E.EHDG_ERR_INVALID_ARG
+    assert reports >= 2 and polls >= reports
+    torch.cuda.synchronize()
+    for k, p in enumerate(ms):
+        assert torch.equal(got[k], ref_u[k]), k
+        assert p.iters() == ref_it[k], k
+    b.close()
+    for p in ref + ms:
+        p.close()
+
+
+def test_async_solution_needs_a_finished_report():
+    import torch
+    from paper_1601_06681_amd import ehdg as E
+    ms = [_transport(c) for c in STEADY[:2]]
+    b = E.Batch(ms)
+    out = torch.empty(ms[0].nel, ms[0].m, ms[0].Np, dtype=torch.float64, device=ms[0].device)
+    with pytest.raises(E.EhdgError) as ei:       # no report read yet
+        b.solution(0, out)
+    assert ei.value.code == E.EHDG_ERR_INVALID_ARG
+    rep = _pinned_reports(b, 1)[0]
+    b.launch(2, 1e-10, None, rep)                # steady members: no step targets needed
+    st = None
+    while st is None:
+        st = b.poll()
+    assert st == [0, 0]                          # two rounds: nobody has converged
+    with pytest.raises(E.EhdgError) as ei:
+        b.solution(1, out)
+    assert ei.value.code == E.EHDG_ERR_INVALID_ARG
+    b.close()
+    be = [mk() for mk in _be_members()[:1]]
+    bb = E.Batch(be)
+    with pytest.raises(E.EhdgError) as ei:       # backward-Euler members need targets
+        bb.launch(2, 1e-10, None, _pinned_reports(bb, 1)[0])
+    assert ei.value.code == E.EHDG_ERR_INVALID_ARG
+    bb.close()
+    for p in ms + be:
+        p.close()

@@ -1,11 +1,18 @@
-"""Serving with continuous batching (paper_1601_06681_amd.serving): requests that join
-and leave the batch while it runs get bit for bit the results they get alone; the
-admitted workspaces never exceed the HBM budget."""
+"""Serving with continuous batching (paper_1601_06681_amd.serving).
+
+Requests that join and leave the batch while it runs get bit for bit the results they get
+alone; the admitted workspaces never exceed the HBM budget; a served linearized-Euler
+result and a served 3D transport result agree with the FP64 oracle (same stopping
+tolerance: 1e-10 relative, the bar of the solo parity tests)."""
 import math
 
 import numpy as np
 import pytest
 
+from oracle import ehdg as O
+from oracle.euler import Euler
+from oracle.mesh import StructuredMesh
+from tests._cases import oracle_transport, rel_err
 
 
 def _requests():
@@ -21,8 +28,23 @@ def _requests():
     return [reqs[i] for i in order]
 
 
+def _oracle(req):
+    """The oracle's solution of one request (external layout, flattened per element)."""
+    from paper_1601_06681_amd import workloads as W
+    n = req["n"]
+    if req["kind"] == "euler":
+        op = Euler(StructuredMesh((n, n), periodic=(True, True)), req["degree"], W.EULER_U0, W.EULER_C0,
+                   req["dt"])
+        u0 = op.interpolate([lambda X, fn=fn: fn(X, np) for fn in W.euler_pulse()])
+        u, _ = O.be_steps(op, u0, req["steps"], tol=1e-10)
+        return u
+    op, F, _, _ = oracle_transport((n, n, n), (1.0, 1.0, 1.0), req["degree"], req["beta"], req["sigma"])
+    return O.solve(op, F, np.zeros((op.mesh.nel, op.ref.Np)), tol=1e-10, max_iter=5000)["u"]
+
+
 @pytest.mark.gpu
-def test_served_results_equal_alone_within_budget():
+@pytest.mark.parametrize("max_active,depth,rounds", [(None, 2, 3), (2, 3, 5)])
+def test_served_results_equal_alone_and_oracle(max_active, depth, rounds):
     import torch
     from paper_1601_06681_amd import serving as S
     reqs = _requests()
@@ -30,12 +52,16 @@ def test_served_results_equal_alone_within_budget():
     need = [S.footprint(r) for r in reqs]
     budget = sum(sorted(need)[-3:])          # at most about three members at a time
     arrivals = [0.0, 0.0, 0.002, 0.004, 0.004, 0.01, 0.02, 0.02]
-    out = S.Server(budget, rounds=3).run(reqs, arrivals, keep=True)
+    out = S.Server(budget, rounds=rounds, max_active=max_active, depth=depth).run(reqs, arrivals, keep=True)
     assert out["peak_bytes"] <= budget
     assert out["batches"] >= 3                # membership changed while running
     for i, (dt, iters, u) in enumerate(alone):
         assert torch.equal(out["solutions"][i], u), i
     assert np.all(out["latency"] > 0)
+    for kind in ("euler", "transport"):
+        i = next(k for k, r in enumerate(reqs) if r["kind"] == kind)
+        served = out["solutions"][i].cpu().numpy().reshape(out["solutions"][i].shape[0], -1)
+        assert rel_err(served, _oracle(reqs[i])) < 1e-10, kind
 
 
 def test_fifo_latency_recursion():
