@@ -1,22 +1,37 @@
 // HIP kernels of the eHDG iteration for gfx950 (MI355X).
 //
-// One eHDG sweep (Algorithm 1: independent local solves with the previous traces,
-// then new traces) is, in trace form, per element e
+// One eHDG sweep (Algorithm 1: independent local solves with the previous traces, then
+// new traces) is, in trace form, per element e
 //     s_out[e] = g[e] + T in_e(s_in),
-// where in_e gathers the element's own and its face neighbours' trace data and T is
-// the condensed local operator shared by every element of a uniform mesh.  The
-// sweep is HBM-bound, so the design is about bytes:
-//   * state arrays are component-major (SoA): component k of element e at
-//     [k * n_el + e], so a wavefront of 64 consecutive elements reads and writes
-//     512 contiguous bytes per component, and the face neighbours (e +- 1,
-//     e +- n0, e +- n0 n1) are contiguous runs too;
-//   * T is addressed uniformly across the wavefront, so it is fetched with scalar
-//     loads and used as an SGPR operand of the FMAs (no LDS traffic);
-//   * workgroups are remapped so each of the 8 XCDs sweeps a contiguous slab of
-//     elements and the neighbour re-reads hit its own L2;
-//   * the FP64 relative-increment norms are reduced per wavefront, per block, and
-//     then by the last block to finish, in a fixed order (deterministic), which
-//     also raises a device-side "done" flag that makes later sweeps exit at once.
+// where in_e gathers the element's own and its face neighbours' trace data and T is the
+// condensed local operator shared by every element of a uniform mesh (Sec. 3).
+//   * Layout.  State arrays are component-major (SoA): component k of element e at
+//     [k * n_el + e], so 16 consecutive elements read and write 128 contiguous bytes per
+//     component, and face neighbours (e +- 1, e +- n0, e +- n0 n1) are contiguous runs.
+//   * Matrix cores.  Elements are taken in tiles of 16: the tile's gathered inputs are
+//     the B operand and T the A operand of v_mfma_f64_16x16x4f64 (FP64) or
+//     v_mfma_f32_16x16x4f32 (FP32 forms).  Each wavefront keeps its row block of T in
+//     registers for the whole launch (fragment-major copy made at set-up), so T is read
+//     once per wavefront, not per element.  Large operators split the rows over the
+//     waves of a workgroup and share the gathered tile through LDS, double-buffered so
+//     the next tile's gather overlaps the current tile's products.
+//   * Launch shape.  One round of resident workgroups, each over a contiguous range of
+//     tiles (or a tuned tiles-per-workgroup count and order); workgroup ids are remapped
+//     so each of the 8 XCDs sweeps a contiguous slab and neighbour re-reads hit its own
+//     L2.
+//   * Stopping test.  Single-problem sweeps take a lagged test: each sweep leaves
+//     per-workgroup partial sums of its increment and takes the previous sweep's test
+//     from the other partial set, summed in a canonical order, so no workgroup waits for
+//     another; batched sweeps reduce with the last workgroup to arrive.  Either raises a
+//     device-side done flag that makes queued sweeps exit at once.
+//   * Batches.  Problems of one family share a launch through a (problem, tile range)
+//     table; a persistent kernel strides over the table of every 2D transport and
+//     shallow-water member, dispatching each entry to its family's sweep.
+//   * Also here: the step completion of backward Euler (stacked recovery and next
+//     right-hand side), the refinement forms (FP64 residual on s', FP32 / BF16
+//     corrections), the variable-velocity sweep (per-element operators streamed from
+//     HBM), and the set-up kernels (per-element products with a shared matrix staged
+//     through LDS, tiled layout transposes).
 #include "kernels.h"
 
 #include <algorithm>
