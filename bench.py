@@ -378,11 +378,12 @@ def run_variable(torch, args):
 
 def run_batch(torch, args):
     """Batched uneven solves: the batch_mix problems (seed 0) in plain FP32, with launch
-    shapes from the autotuner and rounds replayed from a captured HIP graph (one persistent
-    sweep launch per round over every member).  The steady transport members are solved to
+    shapes from the autotuner and rounds replayed from a captured HIP graph (one sweep
+    launch per family and round).  The steady transport members are solved to
     an increment of 1e-6, the shallow-water members take 5 backward-Euler steps at 1e-6.
-    Compared with the same batch launched without the graph and with the first problems of
-    each kind solved one by one.  Members the library refuses (degree-1 transport with both
+    Compared with the same batch launched without the graph, with the persistent sweep
+    launch (one per round for every member) instead of the per-family launches, and with
+    the first problems of each kind solved one by one.  Members the library refuses (degree-1 transport with both
     velocity components non-zero) are counted and left out."""
     import tempfile
     from paper_1601_06681_amd import autotune as A
@@ -408,7 +409,7 @@ def run_batch(torch, args):
         return prob
 
     # launch shapes: the autotuner in batch mode (a round of 8 problems of 128 x 128 of the
-    # family through the persistent batched sweep) for each family in the batch
+    # family through the batched sweep) for each family in the batch
     t0 = time.perf_counter()
     cache = os.path.join(tempfile.mkdtemp(prefix="ehdg_tune_"), "tune.json")
     tuned = {}
@@ -445,9 +446,11 @@ def run_batch(torch, args):
 
     bt = Batch([probs[i] for i in tr])
     bs = Batch([probs[i] for i in sw])
-    for graph in (True, False):
+    for graph, persist in ((True, False), (False, False), (True, True)):
         bt.set_graph(graph)
         bs.set_graph(graph)
+        bt.set_persistent(persist)
+        bs.set_persistent(persist)
         bt.solve(tol, 100000)                  # warm-up: kernel loading, graph capture, predictions
         bs.step(1, tol, 1000)
         reset(tr)
@@ -459,8 +462,9 @@ def run_batch(torch, args):
         row = {"transport_solve_ms": wall_t * 1e3, "transport_sweeps_total": int(sum(its_t)),
                "swe_5_steps_ms": wall_s * 1e3, "swe_sweeps_total": int(sum(sum(v) for v in its_s)),
                "dof_updates_per_s": (upd_t + upd_s) / (wall_t + wall_s)}
-        out["batched_graph" if graph else "batched_eager"] = row
-        log(f"[bench] batch ({'graph' if graph else 'eager'}): transport {wall_t * 1e3:.1f} ms, swe "
+        name = ("batched_graph" if graph else "batched_eager") if not persist else "persistent_graph"
+        out[name] = row
+        log(f"[bench] batch ({name}): transport {wall_t * 1e3:.1f} ms, swe "
             f"{wall_s * 1e3:.1f} ms, {row['dof_updates_per_s']:.3e} DOF-updates/s")
     # the same problems one after another (the first args.batch_solo of each kind)
     k = args.batch_solo

@@ -247,12 +247,13 @@ int ehdg_destroy(ehdg_handle h);
  * one bigger set of independent local solves.  A batch advances many problems (any
  * PDE, degree, mesh and coefficients, precision EHDG_FP64 or EHDG_FP32) together, and each
  * problem keeps its own control block, stopping test and residual history.  A round of
- * sweeps is one persistent launch per precision for every 2D transport and shallow-water
- * member (a grid of resident workgroups striding over the (problem, tile range) table,
- * each entry dispatched to its family's sweep), plus one launch per family for the other
- * families; backward-Euler step completions are one launch per family.  The rounds are
- * captured once into a HIP graph and replayed (ehdg_batch_set_graph).  A problem's iterates,
- * iteration counts and solution are bit for bit those of the same handle advanced alone.
+ * sweeps is one launch per operator family and precision over a (problem, tile range)
+ * table, or (ehdg_batch_set_persistent) one persistent launch per precision for every 2D
+ * transport and shallow-water member, a grid of resident workgroups striding over the
+ * table and dispatching each entry to its family's sweep; backward-Euler step completions
+ * are one launch per family.  The rounds are captured once into a HIP graph and replayed
+ * (ehdg_batch_set_graph).  A problem's iterates, iteration counts and solution are bit for
+ * bit those of the same handle advanced alone.
  *
  * handles: host array of n handles (from ehdg_setup, FP64 or FP32 precision), all distinct;
  * the batch keeps pointers to them, so they must outlive it, and no call on a member
@@ -339,6 +340,13 @@ int ehdg_batch_get_solution(ehdg_batch b, int32_t member, double* d_u);
  * plain launches.  Static batches (ehdg_batch_create_static) have no graphs (enabling
  * returns UNSUPPORTED): instantiating a graph allocates. */
 int ehdg_batch_set_graph(ehdg_batch b, int32_t enabled);
+
+/* Sweeps of the 2D transport and shallow-water members in the persistent launch (enabled
+ * != 0) or in one launch per family like the other families (0, the default, faster on
+ * mixed batches: each family's kernel keeps its own register budget and occupancy).
+ * Every member gets the same work either way, so the results are bitwise the same.
+ * INVALID_ARG while launches are pending. */
+int ehdg_batch_set_persistent(ehdg_batch b, int32_t enabled);
 
 int ehdg_batch_destroy(ehdg_batch b);
 const char* ehdg_batch_last_error(ehdg_batch b);

@@ -33,7 +33,7 @@ EXPORTED = [
     "ehdg_batch_advance", "ehdg_batch_destroy", "ehdg_batch_last_error", "ehdg_variable_workspace_bytes",
     "ehdg_setup_variable", "ehdg_batch_create_static", "ehdg_batch_set_graph", "ehdg_tune_set",
     "ehdg_tune_clear", "ehdg_launch_shape", "ehdg_batch_report_bytes", "ehdg_batch_launch", "ehdg_batch_poll",
-    "ehdg_batch_get_solution",
+    "ehdg_batch_get_solution", "ehdg_batch_set_persistent",
 ]
 
 
@@ -92,6 +92,7 @@ def load():
         "ehdg_batch_create": (ctypes.c_int, [P, I32, P, SZ, P, ctypes.POINTER(P)]),
         "ehdg_batch_create_static": (ctypes.c_int, [P, I32, P, ctypes.POINTER(P)]),
         "ehdg_batch_set_graph": (ctypes.c_int, [P, I32]),
+        "ehdg_batch_set_persistent": (ctypes.c_int, [P, I32]),
         "ehdg_tune_set": (ctypes.c_int, [I32, I32, I32, I32, I32, I32]),
         "ehdg_tune_clear": (ctypes.c_int, []),
         "ehdg_launch_shape": (ctypes.c_int, [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),

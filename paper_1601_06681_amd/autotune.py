@@ -98,8 +98,8 @@ def tune(make_problem, pde, dim, degree, precision, sweeps=100, candidates=None,
     order) and registers the fastest for the family.  make_problem must set up a new
     problem of that family (it is called after each candidate is registered).  batch = 1:
     the sweep of one problem alone; batch > 1: a round of a batch of that many problems
-    (the persistent batched sweep, where more tiles per workgroup amortize each table
-    entry's fixed cost).  Returns {"best": {...}, "timings": [...]}; saves it in the cache
+    (the batched sweep, where more tiles per workgroup amortize each table entry's fixed
+    cost).  Returns {"best": {...}, "timings": [...]}; saves it in the cache
     when save is true."""
     if candidates is None:
         candidates = BATCH_CANDIDATES if batch > 1 else DEFAULT_CANDIDATES

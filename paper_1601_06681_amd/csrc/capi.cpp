@@ -943,18 +943,19 @@ int bfail(ehdg_batch_s* b, int code, const std::string& msg) {
 // and its step-completion entries.  A member's entries are those of its own launch shape,
 // so batched results are bitwise those of the member alone.
 void batch_plan(const std::vector<ehdg_problem*>& hs, std::vector<ehdg_batch_s::Group>& groups,
-                std::vector<BatchEntry>& table, int* persist_first, int* persist_n) {
+                std::vector<BatchEntry>& table, int* persist_first, int* persist_n, bool use_persist = true) {
   auto fp32 = [&](size_t i) { return hs[i]->desc.precision == EHDG_FP32; };
+  auto persist = [&](size_t i) { return use_persist ? hs[i]->ks->persist : -1; };
   auto sweep_entries = [&](size_t i) {
     const KernelSet* ks = hs[i]->ks;
     int tpg = hs[i]->dp.sweep_tpg, ng = 0;
     (fp32(i) ? ks->sweep32_groups : ks->sweep_groups)(hs[i]->dp.mesh.nel, &tpg, &ng);
-    for (int b = 0; b < ng; ++b) table.push_back({(int)i, b, ng, tpg, ks->persist});
+    for (int b = 0; b < ng; ++b) table.push_back({(int)i, b, ng, tpg, persist(i)});
   };
   for (int prec = 0; prec < 2; ++prec) {
     persist_first[prec] = (int)table.size();
     for (size_t i = 0; i < hs.size(); ++i)
-      if (hs[i]->ks->persist >= 0 && fp32(i) == (prec == 1)) sweep_entries(i);
+      if (persist(i) >= 0 && fp32(i) == (prec == 1)) sweep_entries(i);
     persist_n[prec] = (int)table.size() - persist_first[prec];
   }
   std::vector<std::pair<const KernelSet*, bool>> fams;
@@ -966,7 +967,7 @@ void batch_plan(const std::vector<ehdg_problem*>& hs, std::vector<ehdg_batch_s::
     const KernelSet* ks = key.first;
     ehdg_batch_s::Group g{ks, key.second, (int)table.size(), 0, 0, 0};
     for (size_t i = 0; i < hs.size(); ++i)
-      if (hs[i]->ks == ks && fp32(i) == key.second && ks->persist < 0) sweep_entries(i);
+      if (hs[i]->ks == ks && fp32(i) == key.second && persist(i) < 0) sweep_entries(i);
     g.sweep_n = (int)table.size() - g.sweep_first;
     g.step_first = (int)table.size();
     for (size_t i = 0; i < hs.size(); ++i) {
@@ -1199,7 +1200,7 @@ int batch_create_in(std::vector<ehdg_problem*>& hs, void* d_workspace, size_t wo
   b->h = hs;
   b->stream = (hipStream_t)stream;
   std::vector<BatchEntry> table;
-  batch_plan(hs, b->groups, table, b->persist_first, b->persist_n);
+  batch_plan(hs, b->groups, table, b->persist_first, b->persist_n, false);  // per-family launches by default
   const BatchLayout L = batch_layout(hs.size(), table.size());
   if (workspace_bytes < L.total) {
     delete b;
@@ -1523,6 +1524,36 @@ int ehdg_batch_set_graph(ehdg_batch b, int32_t enabled) {
   if (enabled && b->is_static) return bfail(b, EHDG_ERR_UNSUPPORTED, "static batches launch without graphs");
   b->use_graph = enabled != 0;
   if (!b->use_graph) drop_graph(b);
+  return EHDG_OK;
+}
+
+int ehdg_batch_set_persistent(ehdg_batch b, int32_t enabled) {
+  if (!b) return EHDG_ERR_INVALID_ARG;
+  int rc = no_pending(b);
+  if (rc) return rc;
+  std::vector<ehdg_batch_s::Group> groups;
+  std::vector<BatchEntry> table;
+  int pf[2], pn[2];
+  batch_plan(b->h, groups, table, pf, pn, enabled != 0);
+  if (table.size() != b->table_host.size()) return bfail(b, EHDG_ERR_INVALID_ARG, "table size changed");
+  // the table's host copy may be the source of a pending upload
+  if (b->last_ev_set)
+    HIP_TRY_B(b, hipEventSynchronize(b->last_ev));
+  else
+    HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+  b->table_host.swap(table);
+  b->groups.swap(groups);
+  for (int q = 0; q < 2; ++q) {
+    b->persist_first[q] = pf[q];
+    b->persist_n[q] = pn[q];
+  }
+  HIP_TRY_B(b, hipMemcpyAsync(b->d_table, b->table_host.data(), b->table_host.size() * sizeof(BatchEntry),
+                              hipMemcpyHostToDevice, b->stream));
+  if (b->is_static)
+    HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+  else if ((rc = mark_last(b)))
+    return rc;
+  drop_graph(b);
   return EHDG_OK;
 }
 

@@ -267,6 +267,10 @@ def ehdg_batch_advance(b, n, rounds, rel_tol, step_targets=None):
     return state.tolist()
 
 
+def ehdg_batch_set_persistent(b, enabled):
+    _check_batch(_lib.load().ehdg_batch_set_persistent(b, 1 if enabled else 0), b)
+
+
 def ehdg_batch_report_bytes(b):
     n = ctypes.c_size_t(0)
     _check_batch(_lib.load().ehdg_batch_report_bytes(b, ctypes.byref(n)), b)
@@ -352,6 +356,11 @@ class Batch:
     def set_graph(self, enabled):
         """Rounds replayed from a captured HIP graph (True, the default) or launched one by one."""
         ehdg_batch_set_graph(self.b, enabled)
+
+    def set_persistent(self, enabled):
+        """2D transport and shallow-water sweeps in the persistent launch (True) or in one
+        launch per family (False, the default)."""
+        ehdg_batch_set_persistent(self.b, enabled)
 
     def advance(self, rounds, tol, step_targets=None):
         """Member states after `rounds` more rounds: 0 running, 1 finished, 2 failed."""

@@ -1,9 +1,8 @@
 """Batches of independent problems (ehdg_batch_*), through the C ABI.
 
-A batch advances many problems together.  A round of sweeps is one persistent launch per
-precision for the 2D transport and shallow-water members (workgroups striding over the
-(problem, tile range) table) plus one launch per family for the others, replayed from a
-captured HIP graph.  Each member gets exactly the work it gets alone, so the bar is
+A batch advances many problems together.  A round of sweeps is one launch per family over
+a (problem, tile range) table (or, switched on, one persistent launch per precision for the
+2D transport and shallow-water members), replayed from a captured HIP graph.  Each member gets exactly the work it gets alone, so the bar is
 bitwise: every member's iteration counts, residual history and solution equal those of the
 same problem advanced on its own, with graphs or without.  One member of each batch is also
 checked against the FP64 oracle (same iteration count, 1e-10).
@@ -132,9 +131,9 @@ def test_batch_iteration_cap_and_refinement_member():
 
 def test_batch_mixed_precision_steps_equal_solo():
     """FP64 and plain FP32 shallow-water members in one batch, stepped at one tolerance
-    (1e-6, within reach of both precisions): the FP32 members' sweeps run in the persistent
-    FP32 launch and their step completions in the FP32 step kernel; every member equals its
-    solo run at the same tolerance bitwise."""
+    (1e-6, within reach of both precisions): the FP32 members' sweeps run in the FP32
+    batched sweep and their step completions in the FP32 step kernel; every member equals
+    its solo run at the same tolerance bitwise."""
     from paper_1601_06681_amd.ehdg import EHDG_SWE, Batch, Problem
 
     def mk(n, p, dt, prec, seed):
@@ -293,3 +292,37 @@ def test_async_solution_needs_a_finished_report():
     bb.close()
     for p in ms + be:
         p.close()
+
+
+def test_persistent_and_per_family_launches_agree():
+    """2D transport and shallow-water members (FP64 and plain FP32) swept by the persistent
+    launch and by one launch per family: bitwise the same iterates, counts and histories."""
+    import torch
+    from paper_1601_06681_amd.ehdg import EHDG_SWE, Batch, Problem
+
+    def members():
+        out = [_transport(c, precision=prec) for c in STEADY[:3] if len(c["n"]) == 2 for prec in (0, 3)]
+        for n, p, prec, seed in (((12, 10), 2, 0, 1), ((9, 13), 3, 3, 2)):
+            prob = Problem(EHDG_SWE, 2, n, L=(1.0, 1.0), periodic=(1, 1, 0), degree=p, Phi=1.0, dt=1e-3,
+                           precision=prec)
+            prob.set_initial(swe_random_fns(seed))
+            out.append(prob)
+        return out
+    runs = []
+    for persist in (True, False):
+        ms = members()
+        b = Batch(ms)
+        b.set_persistent(persist)
+        st = b.advance(40, 1e-6, [0] * 6 + [3, 3])
+        runs.append((st, [p.iters() for p in ms], [p.solution().clone() for p in ms],
+                     [p.residuals(0, min(p.iters(), 8)) if p.pde == 0 else None for p in ms]))
+        b.close()
+        for p in ms:
+            p.close()
+    (s1, i1, u1, h1), (s2, i2, u2, h2) = runs
+    assert s1 == s2 and i1 == i2
+    for a, c in zip(u1, u2):
+        assert torch.equal(a, c)
+    for a, c in zip(h1, h2):
+        if a is not None:
+            np.testing.assert_array_equal(a, c)
