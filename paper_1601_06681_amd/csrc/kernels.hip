@@ -203,6 +203,21 @@ struct TransportFam {
     const V v = ld(up ? c : c - NA * NF, (up && n >= 0) ? n : e);
     return inflow_bc ? V(0) : v;
   }
+  // row() in two parts: the loads, and the combination (which needs only indices), so
+  // that a caller can keep the loads in flight across other work
+  template <class LD>
+  __device__ __forceinline__ static void row_load(const MeshDev&, int e, const Nb& nb, const LD& ld, int c,
+                                                  decltype(ld(0, 0))& x, decltype(ld(0, 0))& y) {
+    const bool up = c < NA * NF;
+    const int n = nb.get(c / NF);
+    x = ld(up ? c : c - NA * NF, (up && n >= 0) ? n : e);
+    y = x;
+  }
+  template <class V>
+  __device__ __forceinline__ static V row_combine(const Nb& nb, int c, V x, V) {
+    const bool inflow_bc = c < NA * NF && nb.get(c / NF) < 0;
+    return inflow_bc ? V(0) : x;
+  }
   __device__ __forceinline__ static int own_row(int r) { return NA * NF + r; }
   static constexpr bool kSelfSum = false;
 };
@@ -237,6 +252,18 @@ struct SweFam {
     own = ld(c, e);
     const auto other = ld((f ^ 1) * NF + k, n >= 0 ? n : e);  // unconditional, in bounds
     return own + (n >= 0 ? other : own);
+  }
+  template <class LD>
+  __device__ __forceinline__ static void row_load(const MeshDev&, int e, const Nb& nb, const LD& ld, int c,
+                                                  decltype(ld(0, 0))& x, decltype(ld(0, 0))& y) {
+    const int f = c / NF, k = c - f * NF;
+    const int n = nb.get(f);
+    x = ld(c, e);
+    y = ld((f ^ 1) * NF + k, n >= 0 ? n : e);
+  }
+  template <class V>
+  __device__ __forceinline__ static V row_combine(const Nb& nb, int c, V own, V other) {
+    return own + (nb.get(c / NF) >= 0 ? other : own);
   }
   __device__ __forceinline__ static int own_row(int) { return -1; }
   static constexpr bool kSelfSum = true;
@@ -273,6 +300,18 @@ struct EulerFam {
     own = ld(c, e);
     const V other = ld((f ^ 1) * 4 * NF + rem, n >= 0 ? n : e);  // unconditional, in bounds
     return own + (n >= 0 ? other : V(0));
+  }
+  template <class LD>
+  __device__ __forceinline__ static void row_load(const MeshDev&, int e, const Nb& nb, const LD& ld, int c,
+                                                  decltype(ld(0, 0))& x, decltype(ld(0, 0))& y) {
+    const int f = c / (4 * NF), rem = c - f * 4 * NF;
+    const int n = nb.get(f);
+    x = ld(c, e);
+    y = ld((f ^ 1) * 4 * NF + rem, n >= 0 ? n : e);
+  }
+  template <class V>
+  __device__ __forceinline__ static V row_combine(const Nb& nb, int c, V own, V other) {
+    return own + (nb.get(c / (4 * NF)) >= 0 ? other : V(0));
   }
   __device__ __forceinline__ static int own_row(int) { return -1; }
   static constexpr bool kSelfSum = true;
@@ -679,14 +718,19 @@ struct PartialPrefetch {
 // launch queued past convergence leaves here, without waiting for the partials), the
 // partials are summed in the canonical order, and the stopping test of sweep k - 1 is
 // taken.  Returns k (> 0), or 0 if the segment has stopped (then the caller writes nothing).
+// The previous sweep's partial set.
+__device__ __forceinline__ const double* lagged_parts(const ResidArgs& ra, const LagArgs& lag) {
+  return ra.partials + (size_t)((lag.seq - 1u) & 1u) * lag.stride;
+}
+
+// The rest of lagged_begin once the partials' loads are issued (pf): callers may issue
+// other loads in between, whose latency then overlaps the sum.
 template <int NW>
-__device__ __forceinline__ int lagged_begin(const ResidArgs& ra, const LagArgs& lag, int nb, int bid,
-                                            const CtrlHead& ch, unsigned seg) {
+__device__ __forceinline__ int lagged_finish(const ResidArgs& ra, const LagArgs& lag, int nb, int bid,
+                                             const CtrlHead& ch, unsigned seg, const PartialPrefetch<NW>& pf,
+                                             const double* parts) {
   __shared__ double sq[kVirtLanes / 64][2];
   __shared__ int s_done;
-  const double* parts = ra.partials + (size_t)((lag.seq - 1u) & 1u) * lag.stride;
-  PartialPrefetch<NW> pf;
-  pf.issue(parts, nb);
   if (threadIdx.x == 0) s_done = ch.done;
   __syncthreads();
   if (s_done) return 0;
@@ -700,6 +744,15 @@ __device__ __forceinline__ int lagged_begin(const ResidArgs& ra, const LagArgs& 
     if (stop_test(res, ra.tol, ra.stop)) return 0;
   }
   return k;
+}
+
+template <int NW>
+__device__ __forceinline__ int lagged_begin(const ResidArgs& ra, const LagArgs& lag, int nb, int bid,
+                                            const CtrlHead& ch, unsigned seg) {
+  const double* parts = lagged_parts(ra, lag);
+  PartialPrefetch<NW> pf;
+  pf.issue(parts, nb);
+  return lagged_finish<NW>(ra, lag, nb, bid, ch, seg, pf, parts);
 }
 
 // End of a lagged sweep, all threads: the workgroup's partial sums into set seq & 1.
@@ -731,16 +784,11 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
   for (int u = 0; u < MTW; ++u)
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) a[u][kt] = Tf[((w * MTW + u) * KT + kt) * 64 + lane];
-  int k;
-  if constexpr (LAGGED) {
-    k = lagged_begin<TL::NW>(ra, lag, nbk, bid, ch, seg);
-    if (k == 0) return;
-  } else {
-    if (ch.done) return;
-    k = ch.iters + 1;
-  }
+  // the sweep number of the segment, and with it the input buffer, follow from the
+  // control block head alone (the lagged test below only decides whether to go on)
+  const int kpre = LAGGED ? (int)(lag.seq - seg) : ch.iters + 1;
   if constexpr (DEVPAR) {
-    const int parity = (ch.base + k - 1) & 1;  // s^(k-1) of the segment
+    const int parity = (ch.base + kpre - 1) & 1;  // s^(k-1) of the segment
     ld.p = parity ? s1 : s0;
     out = parity ? s0 : s1;
   }
@@ -750,6 +798,11 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
   const int t1 = min(t0 + tiles_per_group, ntiles);
   double d2 = 0.0, n2 = 0.0;
   if constexpr (TL::WPG > 1) {
+    if constexpr (LAGGED) {
+      if (lagged_begin<TL::NW>(ra, lag, nbk, bid, ch, seg) == 0) return;
+    } else {
+      if (ch.done) return;
+    }
     __shared__ double bt[2 * KT * 4 * 16];
     mfma64_shared_b<F, F::S, F::I, MTW, TL::WPG>(
         m, a, t0, t1, bt, [&](int c, int es, const Nb& nb) { return F::row(m, es, nb, ld, c); },
@@ -769,19 +822,67 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
       finish_residual<TL::NW>(d2, n2, ra, bid, nbk, ch.iters);
     return;
   }
+  // WPG == 1: each wavefront gathers and applies its own tiles.  The first tile's inputs
+  // (gathered traces, g, the element's own state) are loaded before the previous sweep's
+  // stopping test is summed, so their latency overlaps it; a launch that stops discards
+  // them (they are only read).
+  // (only loads here: every use of a loaded value, even a select, waits for it)
+  struct TileIn {
+    double x[KT], y[KT];
+    double g0[MTW][4];
+    double old[MTW][4];
+    Nb nb;
+  };
+  auto load_tile = [&](int t, bool active, TileIn& in) {
+    const int e = t * 16 + j;
+    const int es = (active && e < m.nel) ? e : 0;
+    F::neighbours(m, es, in.nb);
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      const int c = 4 * kt + kq;
+      F::row_load(m, es, in.nb, ld, c < F::I ? c : F::I - 1, in.x[kt], in.y[kt]);
+    }
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (w * MTW + u) + kq + 4 * r;
+        const int rc = row < F::S ? row : F::S - 1;
+        in.g0[u][r] = g[(size_t)rc * nel + es];
+        in.old[u][r] = ld(rc, es);
+      }
+  };
+  // issue order: the partials (addresses from the launch's arguments), then the tile
+  // (addresses from the control block head); loads complete in order, so the partials can
+  // be waited for and summed while the tile's loads are still in flight
+  const double* parts = nullptr;
+  PartialPrefetch<TL::NW> pf;
+  if constexpr (LAGGED) {
+    parts = lagged_parts(ra, lag);
+    pf.issue(parts, nbk);
+    __builtin_amdgcn_sched_barrier(0);  // keep the partials' loads ahead of the tile's
+  }
+  // unconditional (a branch around the loads would make the compiler wait for them before
+  // the sum): a wavefront without a tile, or a launch past convergence, reads element 0
+  TileIn cur;
+  const int tf = t0 + slot;
+  load_tile(tf, !ch.done && tf < t1, cur);
+  if constexpr (LAGGED) {
+    if (lagged_finish<TL::NW>(ra, lag, nbk, bid, ch, seg, pf, parts) == 0) return;
+  } else {
+    if (ch.done) return;
+  }
   doublex4_t pend[MTW];
   int pend_e = -1;
-  for (int t = t0 + slot; t < t1; t += TL::TS) {
+  for (int t = tf; t < t1; t += TL::TS) {
+    if (t != tf) load_tile(t, true, cur);
     const int e = t * 16 + j;
     const bool valid = e < m.nel;
-    const int es = valid ? e : 0;
-    Nb nb;
-    F::neighbours(m, es, nb);
     double b[KT];
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
       const int c = 4 * kt + kq;
-      const double v = F::row(m, es, nb, ld, c < F::I ? c : F::I - 1);
+      const double v = F::row_combine(cur.nb, c < F::I ? c : F::I - 1, cur.x[kt], cur.y[kt]);
       b[kt] = (valid && c < F::I) ? v : 0.0;
     }
     doublex4_t acc[MTW];
@@ -790,23 +891,21 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * (w * MTW + u) + kq + 4 * r;
-        const double gv = g[(size_t)(row < F::S ? row : F::S - 1) * nel + es];
-        acc[u][r] = (valid && row < F::S) ? gv : 0.0;
+        acc[u][r] = (valid && row < F::S) ? cur.g0[u][r] : 0.0;
       }
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
       for (int u = 0; u < MTW; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][kt], b[kt], acc[u], 0, 0, 0);
-    // the previous value of each output row (the element's own state) for the increment
+    // the increment against the element's own previous state
 #pragma unroll
     for (int u = 0; u < MTW; ++u)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * (w * MTW + u) + kq + 4 * r;
-        const double old = ld(row < F::S ? row : F::S - 1, es);
         if (valid && row < F::S) {
           const double v = acc[u][r];
-          const double dd = v - old;
+          const double dd = v - cur.old[u][r];
           d2 += dd * dd;
           n2 += v * v;
         }
