@@ -218,6 +218,15 @@ struct TransportFam {
     const bool inflow_bc = c < NA * NF && nb.get(c / NF) < 0;
     return inflow_bc ? V(0) : x;
   }
+  // (state row, element) of row_load's two loads
+  __device__ __forceinline__ static void row_index(const Nb& nb, int e, int c, int& rx, int& ex, int& ry, int& ey) {
+    const bool up = c < NA * NF;
+    const int n = nb.get(c / NF);
+    rx = up ? c : c - NA * NF;
+    ex = (up && n >= 0) ? n : e;
+    ry = rx;
+    ey = ex;
+  }
   __device__ __forceinline__ static int own_row(int r) { return NA * NF + r; }
   static constexpr bool kSelfSum = false;
 };
@@ -264,6 +273,14 @@ struct SweFam {
   template <class V>
   __device__ __forceinline__ static V row_combine(const Nb& nb, int c, V own, V other) {
     return own + (nb.get(c / NF) >= 0 ? other : own);
+  }
+  __device__ __forceinline__ static void row_index(const Nb& nb, int e, int c, int& rx, int& ex, int& ry, int& ey) {
+    const int f = c / NF, k = c - f * NF;
+    const int n = nb.get(f);
+    rx = c;
+    ex = e;
+    ry = (f ^ 1) * NF + k;
+    ey = n >= 0 ? n : e;
   }
   __device__ __forceinline__ static int own_row(int) { return -1; }
   static constexpr bool kSelfSum = true;
@@ -312,6 +329,14 @@ struct EulerFam {
   template <class V>
   __device__ __forceinline__ static V row_combine(const Nb& nb, int c, V own, V other) {
     return own + (nb.get(c / (4 * NF)) >= 0 ? other : V(0));
+  }
+  __device__ __forceinline__ static void row_index(const Nb& nb, int e, int c, int& rx, int& ex, int& ry, int& ey) {
+    const int f = c / (4 * NF), rem = c - f * 4 * NF;
+    const int n = nb.get(f);
+    rx = c;
+    ex = e;
+    ry = (f ^ 1) * 4 * NF + rem;
+    ey = n >= 0 ? n : e;
   }
   __device__ __forceinline__ static int own_row(int) { return -1; }
   static constexpr bool kSelfSum = true;
@@ -570,35 +595,48 @@ struct Tiling64 {
 // front w loads k tiles w, w + WPG, ...), double-buffered, with the next tile's loads
 // in flight while the current tile's MFMAs run; wavefront w then applies row tiles
 // [w MTW, (w + 1) MTW) with its register-resident operator fragments a.
-//   colval(c, es, nb): input column c (< COLS) of element es (a valid element index)
-//   init(row, es, aux): C entry of output row (< ROWS); may also set aux (a value the
-//                      epilogue needs, loaded together with the C entries)
+//   colload(c, es, nb, x, y): issue the loads of input column c (< COLS) of element es (a
+//                      valid element index) into x, y, without using their values
+//   colcombine(c, nb, x, y): the column's value from those loads
+//   init(row, es, aux, keep): C entry of output row (< ROWS), used if keep (else 0); may
+//                      also set aux (a value the epilogue needs, loaded together with
+//                      the C entries)
 //   epi(row, e, v, aux): result of output row for element e (valid lanes only)
-template <class F, int ROWS, int COLS, int MTW, int WPG, class ColVal, class Init, class Epi>
+// Loads complete in order and any use of a loaded value (even a select) waits for it, so
+// the combination and the masking of the prefetched columns happen when they are staged,
+// after this tile's MFMAs, and the C entries are masked after the prefetch is issued.
+template <class F, int ROWS, int COLS, int MTW, int WPG, class ColLoad, class ColCombine, class Init, class Epi>
 __device__ __forceinline__ void mfma64_shared_b(const MeshDev& m, const double (&a)[MTW][(COLS + 3) / 4], int t0,
-                                                int t1, double* lds, ColVal colval, Init init, Epi epi) {
+                                                int t1, double* lds, ColLoad colload, ColCombine colcombine,
+                                                Init init, Epi epi) {
   constexpr int KT = (COLS + 3) / 4, KTW = (KT + WPG - 1) / WPG, BT = KT * 4 * 16;
   const int lane = threadIdx.x & 63, w = wave_id();
+  // the workgroup is WPG wavefronts: with w bounded, the compiler resolves which k tiles
+  // hold which kind of column, and drops loads that a column kind does not need
+  __builtin_assume(w >= 0 && w < WPG);
   const int j = lane & 15, kq = lane >> 4;
-  double v[KTW];
+  double vx[KTW], vy[KTW];
+  Nb gnb;
+  bool gvalid = false;
   auto gather = [&](int t) {
     const int e = t * 16 + j;
-    const bool valid = e < m.nel;
-    const int es = valid ? e : 0;
-    Nb nb;
-    F::neighbours(m, es, nb);
+    gvalid = e < m.nel;
+    const int es = gvalid ? e : 0;
+    F::neighbours(m, es, gnb);
 #pragma unroll
     for (int i = 0; i < KTW; ++i) {
       const int kt = w + i * WPG, c = 4 * kt + kq;
-      const double x = colval(c < COLS ? c : COLS - 1, es, nb);
-      v[i] = (valid && c < COLS) ? x : 0.0;
+      colload(c < COLS ? c : COLS - 1, es, gnb, vx[i], vy[i]);
     }
   };
   auto stage = [&](double* buf) {
 #pragma unroll
     for (int i = 0; i < KTW; ++i) {
-      const int kt = w + i * WPG;
-      if (kt < KT) buf[(4 * kt + kq) * 16 + j] = v[i];
+      const int kt = w + i * WPG, c = 4 * kt + kq;
+      if (kt < KT) {
+        const double x = colcombine(c < COLS ? c : COLS - 1, gnb, vx[i], vy[i]);
+        buf[(4 * kt + kq) * 16 + j] = (gvalid && c < COLS) ? x : 0.0;
+      }
     }
   };
   if (t0 < t1) {
@@ -613,17 +651,27 @@ __device__ __forceinline__ void mfma64_shared_b(const MeshDev& m, const double (
     const bool valid = e < m.nel;
     const int es = valid ? e : 0;
     // C entries of this tile first (their loads are waited for before the prefetch's)
-    doublex4_t acc[MTW];
-    double aux[MTW][4];
+    double c0[MTW][4], aux[MTW][4];
+    bool keep[MTW][4];
 #pragma unroll
     for (int u = 0; u < MTW; ++u)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * (w * MTW + u) + kq + 4 * r;
-        const double c0 = init(row < ROWS ? row : ROWS - 1, es, aux[u][r]);
-        acc[u][r] = (valid && row < ROWS) ? c0 : 0.0;
+        c0[u][r] = init(row < ROWS ? row : ROWS - 1, es, aux[u][r], keep[u][r]);
       }
-    if (t + 1 < t1) gather(t + 1);
+    // unconditional, so that the count of loads in flight is the same on every path (the
+    // last tile gathers itself again, and does not stage it)
+    gather(t + 1 < t1 ? t + 1 : t);
+    __builtin_amdgcn_sched_barrier(0);  // the prefetch is issued before the MFMAs
+    doublex4_t acc[MTW];
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (w * MTW + u) + kq + 4 * r;
+        acc[u][r] = (valid && row < ROWS && keep[u][r]) ? c0[u][r] : 0.0;
+      }
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
       const double b = bcur[(4 * kt + kq) * 16 + j];
@@ -805,9 +853,12 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
     }
     __shared__ double bt[2 * KT * 4 * 16];
     mfma64_shared_b<F, F::S, F::I, MTW, TL::WPG>(
-        m, a, t0, t1, bt, [&](int c, int es, const Nb& nb) { return F::row(m, es, nb, ld, c); },
-        [&](int row, int es, double& old) {
+        m, a, t0, t1, bt,
+        [&](int c, int es, const Nb& nb, double& x, double& y) { F::row_load(m, es, nb, ld, c, x, y); },
+        [&](int c, const Nb& nb, double x, double y) { return F::row_combine(nb, c, x, y); },
+        [&](int row, int es, double& old, bool& keep) {
           old = ld(row, es);
+          keep = true;
           return g[(size_t)row * nel + es];
         },
         [&](int row, int e, double v, double old) {
@@ -1113,9 +1164,15 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
   if constexpr (TL::WPG > 1) {
     __shared__ double bt[2 * KT * 4 * 16];
     mfma64_shared_b<F, F::S, F::I, MTW, TL::WPG>(
-        m, a, t0, t1, bt, [&](int c, int es, const Nb& nb) { return (double)F::row(m, es, nb, ld, c); },
-        [&](int row, int es, double& own) {
+        m, a, t0, t1, bt,
+        [&](int c, int es, const Nb& nb, double& x, double& y) {
+          x = (double)F::row(m, es, nb, ld, c);
+          y = 0.0;
+        },
+        [&](int, const Nb&, double x, double) { return x; },
+        [&](int row, int es, double& own, bool& keep) {
           own = ld(row, es);
+          keep = true;
           return g[(size_t)row * nel + es];
         },
         [&](int row, int e, double v, double own) {
@@ -1436,14 +1493,50 @@ __device__ __forceinline__ void step_mfma_body(MeshDev m, ST* s0, ST* s1, const 
       v = F::row(m, es, nb, ld, c - N);
     return v;
   };
-  auto init = [&](int q, int es, double&) {
+  // the same split into loads and combination for the shared-tile engine
+  // FP64 state: no branch, two loads per column whatever its kind (a u row loads its value
+  // twice, from one cache line), so the count of loads in flight is the same on every path
+  auto colload = [&](int c, int es, const Nb& nb, double& x, double& y) {
+    if constexpr (std::is_same_v<ST, double>) {
+      const bool uc = c < N;
+      int rx, ex, ry, ey;
+      F::row_index(nb, es, uc ? 0 : c - N, rx, ex, ry, ey);
+      const double* px = uc ? u_old + (size_t)c * nel + es : ld.p + (size_t)rx * nel + ex;
+      const double* py = uc ? px : ld.p + (size_t)ry * nel + ey;
+      x = *px;
+      y = *py;
+    } else {
+      if (c < N)
+        x = u_old[(size_t)c * nel + es];
+      else
+        x = (double)F::row(m, es, nb, ld, c - N);
+      y = 0.0;
+    }
+  };
+  auto colcombine = [&](int c, const Nb& nb, double x, double y) {
+    if constexpr (std::is_same_v<ST, double>)
+      return c < N ? x : F::row_combine(nb, c - N, x, y);
+    else
+      return x;
+  };
+  auto init = [&](int q, int es, double&, bool& keep) {
     double c0 = 0.0;
     if (q < N) {
       if (w_src) c0 = w_src[(size_t)q * nel + es];
     } else if (gbe) {
       c0 = gbe[(size_t)(q - N) * nel + es];
     }
+    keep = true;
     return c0;
+  };
+  // for the shared-tile engine: one load per entry on every path (without a source, a u
+  // row already in the caches), the source's absence applied as a mask
+  auto init_flat = [&](int q, int es, double&, bool& keep) {
+    const bool uq = q < N;
+    const double* src = uq ? w_src : gbe;
+    keep = src != nullptr;
+    const double* base = keep ? src : u_old;
+    return base[(size_t)(uq ? q : q - N) * nel + es];
   };
   auto epi = [&](int q, int e, double v, double) {
     if (q < N)
@@ -1453,7 +1546,7 @@ __device__ __forceinline__ void step_mfma_body(MeshDev m, ST* s0, ST* s1, const 
   };
   if constexpr (TL::WPG > 1) {
     __shared__ double bt[2 * KT * 4 * 16];
-    mfma64_shared_b<F, ROWS, COLS, MTW, TL::WPG>(m, a, t0, t1, bt, colval, init, epi);
+    mfma64_shared_b<F, ROWS, COLS, MTW, TL::WPG>(m, a, t0, t1, bt, colload, colcombine, init_flat, epi);
   } else {
     for (int t = t0 + slot; t < t1; t += TL::TS) {
       const int e = t * 16 + j;
@@ -1475,7 +1568,8 @@ __device__ __forceinline__ void step_mfma_body(MeshDev m, ST* s0, ST* s1, const 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int q = 16 * (w * MTW + u) + kq + 4 * r;
-          const double c0 = init(q < ROWS ? q : ROWS - 1, es, unused);
+          bool keep;
+          const double c0 = init(q < ROWS ? q : ROWS - 1, es, unused, keep);
           acc[u][r] = (valid && q < ROWS) ? c0 : 0.0;
         }
 #pragma unroll
