@@ -1166,10 +1166,19 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
     mfma64_shared_b<F, F::S, F::I, MTW, TL::WPG>(
         m, a, t0, t1, bt,
         [&](int c, int es, const Nb& nb, double& x, double& y) {
-          x = (double)F::row(m, es, nb, ld, c);
-          y = 0.0;
+          if constexpr (APPLIED) {
+            F::row_load(m, es, nb, ld, c, x, y);
+          } else {
+            x = (double)F::row(m, es, nb, ld, c);
+            y = 0.0;
+          }
         },
-        [&](int, const Nb&, double x, double) { return x; },
+        [&](int c, const Nb& nb, double x, double y) {
+          if constexpr (APPLIED)
+            return F::row_combine(nb, c, x, y);
+          else
+            return x;
+        },
         [&](int row, int es, double& own, bool& keep) {
           own = ld(row, es);
           keep = true;
