@@ -771,17 +771,22 @@ __device__ __forceinline__ const double* lagged_parts(const ResidArgs& ra, const
   return ra.partials + (size_t)((lag.seq - 1u) & 1u) * lag.stride;
 }
 
-// The rest of lagged_begin once the partials' loads are issued (pf): callers may issue
-// other loads in between, whose latency then overlaps the sum.
-template <int NW>
-__device__ __forceinline__ int lagged_finish(const ResidArgs& ra, const LagArgs& lag, int nb, int bid,
-                                             const CtrlHead& ch, unsigned seg, const PartialPrefetch<NW>& pf,
-                                             const double* parts) {
-  __shared__ double sq[kVirtLanes / 64][2];
+// The control block's done flag as workgroup 0's first wavefront read it, the same for
+// every wavefront of the workgroup (a launch queued past convergence leaves on it).
+__device__ __forceinline__ int uniform_done(const CtrlHead& ch) {
   __shared__ int s_done;
   if (threadIdx.x == 0) s_done = ch.done;
   __syncthreads();
-  if (s_done) return 0;
+  return s_done;
+}
+
+// The stopping test of the previous sweep once its partials' loads are issued (pf) and the
+// segment is known to be running: callers may issue other loads in between, whose latency
+// then overlaps the sum.  Returns k (> 0), or 0 if the test stops the segment.
+template <int NW>
+__device__ __forceinline__ int lagged_test(const ResidArgs& ra, const LagArgs& lag, int nb, int bid, unsigned seg,
+                                           const PartialPrefetch<NW>& pf, const double* parts) {
+  __shared__ double sq[kVirtLanes / 64][2];
   pf.consume(parts, nb, sq);
   __syncthreads();
   const int k = (int)(lag.seq - seg);
@@ -800,7 +805,8 @@ __device__ __forceinline__ int lagged_begin(const ResidArgs& ra, const LagArgs& 
   const double* parts = lagged_parts(ra, lag);
   PartialPrefetch<NW> pf;
   pf.issue(parts, nb);
-  return lagged_finish<NW>(ra, lag, nb, bid, ch, seg, pf, parts);
+  if (uniform_done(ch)) return 0;
+  return lagged_test<NW>(ra, lag, nb, bid, seg, pf, parts);
 }
 
 // End of a lagged sweep, all threads: the workgroup's partial sums into set seq & 1.
@@ -913,15 +919,19 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
     pf.issue(parts, nbk);
     __builtin_amdgcn_sched_barrier(0);  // keep the partials' loads ahead of the tile's
   }
-  // unconditional (a branch around the loads would make the compiler wait for them before
-  // the sum): a wavefront without a tile, or a launch past convergence, reads element 0
-  TileIn cur;
-  const int tf = t0 + slot;
-  load_tile(tf, !ch.done && tf < t1, cur);
+  // a launch past convergence leaves before any tile load (the same decision for the whole
+  // workgroup); the loads are then unconditional (a branch around them would make the
+  // compiler wait for them before the sum): a wavefront without a tile reads element 0
   if constexpr (LAGGED) {
-    if (lagged_finish<TL::NW>(ra, lag, nbk, bid, ch, seg, pf, parts) == 0) return;
+    if (uniform_done(ch)) return;
   } else {
     if (ch.done) return;
+  }
+  TileIn cur;
+  const int tf = t0 + slot;
+  load_tile(tf, tf < t1, cur);
+  if constexpr (LAGGED) {
+    if (lagged_test<TL::NW>(ra, lag, nbk, bid, seg, pf, parts) == 0) return;
   }
   doublex4_t pend[MTW];
   int pend_e = -1;
