@@ -664,13 +664,17 @@ __device__ __forceinline__ void mfma64_shared_b(const MeshDev& m, const double (
     // last tile gathers itself again, and does not stage it)
     gather(t + 1 < t1 ? t + 1 : t);
     __builtin_amdgcn_sched_barrier(0);  // the prefetch is issued before the MFMAs
+    // With one row tile per wavefront the products start from zero and the C entries are
+    // added after them, so the C entries' loads are in flight during the MFMAs instead of
+    // ahead of them (with more row tiles the registers this holds would cost occupancy)
+    constexpr bool kAddAfter = MTW == 1;
     doublex4_t acc[MTW];
 #pragma unroll
     for (int u = 0; u < MTW; ++u)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * (w * MTW + u) + kq + 4 * r;
-        acc[u][r] = (valid && row < ROWS && keep[u][r]) ? c0[u][r] : 0.0;
+        acc[u][r] = (!kAddAfter && valid && row < ROWS && keep[u][r]) ? c0[u][r] : 0.0;
       }
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
@@ -684,7 +688,10 @@ __device__ __forceinline__ void mfma64_shared_b(const MeshDev& m, const double (
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * (w * MTW + u) + kq + 4 * r;
-          if (row < ROWS) epi(row, e, (double)acc[u][r], aux[u][r]);
+          if (row < ROWS) {
+            const double v = kAddAfter ? (double)acc[u][r] + (keep[u][r] ? c0[u][r] : 0.0) : (double)acc[u][r];
+            epi(row, e, v, aux[u][r]);
+          }
         }
     }
     if (t + 1 < t1) stage(lds + (cur ^ 1) * BT);
