@@ -1272,7 +1272,7 @@ struct Inner32Tiling {
   static constexpr int value = TL::NW;
 };
 
-template <class F>
+template <class F, bool PIPE>
 __global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_inner32_mfma(
     MeshDev m, Ld32 ld, const float* __restrict__ r_lo, const float* __restrict__ Tf, float* __restrict__ out,
     const Ctrl* ctrl, int tiles_per_group) {
@@ -1292,28 +1292,57 @@ __global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_inner32_mfma(
   const int ntiles = (m.nel + 15) >> 4;
   const int t0 = remap_block(blockIdx.x, gridDim.x) * tiles_per_group;
   const int t1 = min(t0 + tiles_per_group, ntiles);
-  for (int t = t0 + slot; t < t1; t += TL::TS) {
+  // PIPE: software-pipelined over the wavefront's tiles: the next tile's loads (gather
+  // parts and C entries, values unused until its turn) are issued before this tile's
+  // MFMAs; they are unconditional (the last tile loads itself again), so that the count
+  // of loads in flight is the same on every path.  Without PIPE each tile loads at its
+  // turn.  Either way the C entries are added after the products, so their loads overlap
+  // the MFMAs.  (PIPE pays while the FP32 state is served from the Infinity Cache and
+  // costs when it streams from HBM; the launcher chooses by the state's size.)
+  struct In32 {
+    float x[KT], y[KT];
+    float c[MTW][4];
+    Nb nb;
+  };
+  auto load = [&](int t, In32& in) {
+    const int e = t * 16 + j;
+    const int es = e < m.nel ? e : 0;
+    F::neighbours(m, es, in.nb);
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      const int c = 4 * kt + kq;
+      F::row_load(m, es, in.nb, ld, c < F::I ? c : F::I - 1, in.x[kt], in.y[kt]);
+    }
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (w * MTW + u) + 4 * kq + r;
+        in.c[u][r] = r_lo[(size_t)(row < F::S ? row : F::S - 1) * nel + es];
+      }
+  };
+  const int tf = t0 + slot;
+  In32 cur, nxt;
+  if constexpr (PIPE) load(tf < t1 ? tf : t0, cur);
+  for (int t = tf; t < t1; t += TL::TS) {
+    if constexpr (PIPE)
+      load(t + TL::TS < t1 ? t + TL::TS : t, nxt);
+    else
+      load(t, cur);
     const int e = t * 16 + j;
     const bool valid = e < m.nel;
-    const int es = valid ? e : 0;
-    Nb nb;
-    F::neighbours(m, es, nb);
     float b[KT];
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
       const int c = 4 * kt + kq;
-      const float v = F::row(m, es, nb, ld, c < F::I ? c : F::I - 1);
+      const float v = F::row_combine(cur.nb, c < F::I ? c : F::I - 1, cur.x[kt], cur.y[kt]);
       b[kt] = (valid && c < F::I) ? v : 0.0f;
     }
     floatx4_t acc[MTW];
 #pragma unroll
     for (int u = 0; u < MTW; ++u)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * (w * MTW + u) + 4 * kq + r;
-        const float rv = r_lo[(size_t)(row < F::S ? row : F::S - 1) * nel + es];
-        acc[u][r] = (valid && row < F::S) ? rv : 0.0f;
-      }
+      for (int r = 0; r < 4; ++r) acc[u][r] = 0.0f;
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
@@ -1324,9 +1353,10 @@ __global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_inner32_mfma(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * (w * MTW + u) + 4 * kq + r;
-          if (row < F::S) out[(size_t)row * nel + e] = acc[u][r];
+          if (row < F::S) out[(size_t)row * nel + e] = acc[u][r] + cur.c[u][r];
         }
     }
+    if constexpr (PIPE) cur = nxt;
   }
 }
 
@@ -1896,8 +1926,9 @@ struct Family {
     static const int r = resident_groups(k_step_mfma<F>, 64 * StepTiling<F>::value);
     return r;
   }
+  template <bool PIPE>
   static int res_inner32() {
-    static const int r = resident_groups(k_inner32_mfma<F>, 64 * Inner32Tiling<F>::value);
+    static const int r = resident_groups(k_inner32_mfma<F, PIPE>, 64 * Inner32Tiling<F>::value);
     return r;
   }
   static int res_sweep32() {
@@ -2040,13 +2071,23 @@ struct Family {
       refine_mfma(dp, LdSum<LDD>{Ld64{dp.s[0], ne}, d, 1}, store, tol, st);
     }
   }
-  static void inner32(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
+  // the pipelined correction sweep while the FP32 state (S values per element) is at most
+  // 64 MB, a quarter of the Infinity Cache
+  static constexpr size_t kPipeBytes = (size_t)64 << 20;
+  template <bool PIPE>
+  static void inner32_as(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
     using TL = typename Inner32Tiling<F>::TL;
     int tpg, groups;
-    mfma_groups(dp.mesh.nel, TL::TS, res_inner32(), tpg, groups);
-    hipLaunchKernelGGL((k_inner32_mfma<F>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh,
+    mfma_groups(dp.mesh.nel, TL::TS, res_inner32<PIPE>(), tpg, groups);
+    hipLaunchKernelGGL((k_inner32_mfma<F, PIPE>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh,
                        Ld32{(const float*)lo_in, (size_t)dp.mesh.nel}, (const float*)r_lo, dp.Tf32,
                        (float*)lo_out, (const Ctrl*)dp.ctrl, tpg);
+  }
+  static void inner32(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
+    if ((size_t)F::S * dp.mesh.nel * sizeof(float) <= kPipeBytes)
+      inner32_as<true>(dp, r_lo, lo_in, lo_out, st);
+    else
+      inner32_as<false>(dp, r_lo, lo_in, lo_out, st);
   }
 };
 
