@@ -1385,15 +1385,10 @@ __device__ __forceinline__ void sweep32_body(const MeshDev& m, const float* __re
   for (int u = 0; u < MTW; ++u)
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) a[u][kt] = Tf[((w * MTW + u) * KT + kt) * 64 + lane];
-  int k;
-  if constexpr (LAGGED) {
-    k = lagged_begin<TL::NW>(ra, lag, nbk, bid, ch, seg);
-    if (k == 0) return;
-  } else {
-    if (ch.done) return;
-    k = ch.iters + 1;
-  }
-  const int parity = (ch.base + k - 1) & 1;  // s^(k-1) of the segment
+  // as in the FP64 sweep: the input buffer follows from the control block head; the
+  // previous sweep's partials are loaded first and the first tile's loads overlap their sum
+  const int kpre = LAGGED ? (int)(lag.seq - seg) : ch.iters + 1;
+  const int parity = (ch.base + kpre - 1) & 1;  // s^(k-1) of the segment
   const size_t nel = (size_t)m.nel;
   const Ld32 ld{parity ? s1 : s0, nel};
   float* __restrict__ out = parity ? s0 : s1;
@@ -1401,28 +1396,65 @@ __device__ __forceinline__ void sweep32_body(const MeshDev& m, const float* __re
   const int t0 = remap_block(m.order ? nbk - 1 - bid : bid, nbk) * tiles_per_group;
   const int t1 = min(t0 + tiles_per_group, ntiles);
   double d2 = 0.0, n2 = 0.0;
-  for (int t = t0 + slot; t < t1; t += TL::TS) {
+  // Tile inputs as loads only (gather parts, g, the element's own state); the values are
+  // combined and masked at the tile's turn.  g is added after the products, so its loads
+  // overlap the MFMAs.
+  struct In32 {
+    float x[KT], y[KT];
+    float g0[MTW][4], old[MTW][4];
+    Nb nb;
+  };
+  auto load = [&](int t, bool active, In32& in) {
+    const int e = t * 16 + j;
+    const int es = (active && e < m.nel) ? e : 0;
+    F::neighbours(m, es, in.nb);
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      const int c = 4 * kt + kq;
+      F::row_load(m, es, in.nb, ld, c < F::I ? c : F::I - 1, in.x[kt], in.y[kt]);
+    }
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (w * MTW + u) + 4 * kq + r;
+        const int rc = row < F::S ? row : F::S - 1;
+        in.g0[u][r] = g[(size_t)rc * nel + es];
+        in.old[u][r] = ld(rc, es);
+      }
+  };
+  const double* parts = nullptr;
+  PartialPrefetch<TL::NW> pf;
+  if constexpr (LAGGED) {
+    parts = lagged_parts(ra, lag);
+    pf.issue(parts, nbk);
+    __builtin_amdgcn_sched_barrier(0);  // keep the partials' loads ahead of the tile's
+    if (uniform_done(ch)) return;
+  } else {
+    if (ch.done) return;
+  }
+  const int tf = t0 + slot;
+  In32 cur;
+  load(tf, tf < t1, cur);
+  if constexpr (LAGGED) {
+    if (lagged_test<TL::NW>(ra, lag, nbk, bid, seg, pf, parts) == 0) return;
+  }
+  for (int t = tf; t < t1; t += TL::TS) {
+    if (t != tf) load(t, true, cur);
     const int e = t * 16 + j;
     const bool valid = e < m.nel;
-    const int es = valid ? e : 0;
-    Nb nb;
-    F::neighbours(m, es, nb);
     float b[KT];
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
       const int c = 4 * kt + kq;
-      const float v = F::row(m, es, nb, ld, c < F::I ? c : F::I - 1);
+      const float v = F::row_combine(cur.nb, c < F::I ? c : F::I - 1, cur.x[kt], cur.y[kt]);
       b[kt] = (valid && c < F::I) ? v : 0.0f;
     }
     floatx4_t acc[MTW];
 #pragma unroll
     for (int u = 0; u < MTW; ++u)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * (w * MTW + u) + 4 * kq + r;
-        const float gv = g[(size_t)(row < F::S ? row : F::S - 1) * nel + es];
-        acc[u][r] = (valid && row < F::S) ? gv : 0.0f;
-      }
+      for (int r = 0; r < 4; ++r) acc[u][r] = 0.0f;
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
@@ -1432,10 +1464,9 @@ __device__ __forceinline__ void sweep32_body(const MeshDev& m, const float* __re
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * (w * MTW + u) + 4 * kq + r;
-        const float old = ld(row < F::S ? row : F::S - 1, es);
         if (valid && row < F::S) {
-          const float v = acc[u][r];
-          const double dd = (double)v - (double)old;
+          const float v = acc[u][r] + cur.g0[u][r];
+          const double dd = (double)v - (double)cur.old[u][r];
           d2 += dd * dd;
           n2 += (double)v * (double)v;
           out[(size_t)row * nel + e] = v;
@@ -1983,8 +2014,9 @@ struct Family {
     const ResidArgs ra = resid_args(dp, tol, tol >= 0.0 ? 1 : 0);
     int tpg, groups;
     tuned_groups(dp.mesh.nel, TL::TS, res_sweep32(), dp.sweep_tpg, tpg, groups);
-    hipLaunchKernelGGL((k_sweep32_mfma<F>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, (const float*)dp.g32,
-                       dp.Tf32, ra, (float*)dp.s[0], (float*)dp.s[1], tpg, LagArgs{seq, dp.partial_stride});
+    hipLaunchKernelGGL((k_sweep32_mfma<F>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh,
+                       (const float*)dp.g32, dp.Tf32, ra, (float*)dp.s[0], (float*)dp.s[1], tpg,
+                       LagArgs{seq, dp.partial_stride});
   }
   static void sweep32_groups(int nel, int* tpg, int* groups) {
     using TL = typename Inner32Tiling<F>::TL;
@@ -2072,7 +2104,7 @@ struct Family {
     }
   }
   // the pipelined correction sweep while the FP32 state (S values per element) is at most
-  // 64 MB, a quarter of the Infinity Cache
+  // 64 MB, a quarter of the Infinity Cache, and each wavefront has two or more tiles
   static constexpr size_t kPipeBytes = (size_t)64 << 20;
   template <bool PIPE>
   static void inner32_as(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
@@ -2084,7 +2116,11 @@ struct Family {
                        (float*)lo_out, (const Ctrl*)dp.ctrl, tpg);
   }
   static void inner32(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
-    if ((size_t)F::S * dp.mesh.nel * sizeof(float) <= kPipeBytes)
+    using TL = typename Inner32Tiling<F>::TL;
+    int tpg, groups;
+    mfma_groups(dp.mesh.nel, TL::TS, res_inner32<true>(), tpg, groups);
+    // pipelined with two or more tiles per wavefront (one would only load itself again)
+    if (tpg >= 2 * TL::TS && (size_t)F::S * dp.mesh.nel * sizeof(float) <= kPipeBytes)
       inner32_as<true>(dp, r_lo, lo_in, lo_out, st);
     else
       inner32_as<false>(dp, r_lo, lo_in, lo_out, st);
