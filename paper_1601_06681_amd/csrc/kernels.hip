@@ -2139,13 +2139,12 @@ struct Family {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef unsigned short ushort4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmaTilesPerWave = 8;
-
 template <class F>
 __global__ __launch_bounds__(kThreads) void k_inner_mfma(MeshDev m, const uint16_t* __restrict__ lo_in,
                                                           const uint16_t* __restrict__ r_lo,
                                                           const uint16_t* __restrict__ T16,
-                                                          uint16_t* __restrict__ lo_out, const Ctrl* ctrl) {
+                                                          uint16_t* __restrict__ lo_out, const Ctrl* ctrl,
+                                                          int tiles_per_wave) {
   static_assert(F::S == 48 && F::I == 96 && F::NF == 16, "tiling assumes S = 48, I = 96");
   if (ctrl->done) return;
   const int lane = threadIdx.x & 63, w = wave_id();
@@ -2157,42 +2156,66 @@ __global__ __launch_bounds__(kThreads) void k_inner_mfma(MeshDev m, const uint16
 #pragma unroll
     for (int kt = 0; kt < 3; ++kt)
       a[mt][kt] = *reinterpret_cast<const bf16x8_t*>(T16 + (size_t)(mt * 16 + j) * 96 + kt * 32 + 8 * kg);
-  const int tile0 = (remap_block(blockIdx.x, gridDim.x) * kWaves + w) * kMfmaTilesPerWave;
-  for (int t = 0; t < kMfmaTilesPerWave; ++t) {
-    const int e = (tile0 + t) * 16 + j;
-    const bool valid = e < m.nel;
-    const int es = valid ? e : 0;
+  const int ntiles = (m.nel + 15) >> 4;
+  const int t0 = (remap_block(blockIdx.x, gridDim.x) * kWaves + w) * tiles_per_wave;
+  const int t1 = min(t0 + tiles_per_wave, ntiles);
+  // A tile's inputs as loads only: the B fragments (inputs 8q .. 8q+7, q = 4 kt + kg:
+  // q < 6 -> the upwind neighbour of face q/2, its state rows 8q..; q >= 6 -> the own
+  // state rows 8q - 48 ..) and the r entries of the lane's result rows.  Every load is
+  // unconditional, at an in-bounds element (the lane's own for an inflow boundary or an
+  // idle lane), and the zero of an inflow boundary is selected at the tile's turn.  r is
+  // added after the products, so its loads overlap the MFMAs, and the next tile's loads
+  // are issued before this tile's MFMAs (the last tile loads itself again).
+  struct In16 {
+    bf16x8_t b[3];
+    ushort4_t r[3];
+    bool up[3];
+  };
+  auto load = [&](int t, In16& in) {
+    const int e = t * 16 + j;
+    const int es = e < m.nel ? e : 0;
     Nb nb;
     F::neighbours(m, es, nb);
+#pragma unroll
+    for (int kt = 0; kt < 3; ++kt) {
+      const int q = 4 * kt + kg;
+      const int src = q < 6 ? nb.get(q >> 1) : es;
+      const int row = q < 6 ? 8 * q : 8 * q - 48;
+      in.up[kt] = src >= 0;
+      in.b[kt] = *reinterpret_cast<const bf16x8_t*>(lo_in + (size_t)(src >= 0 ? src : es) * 48 + row);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 3; ++mt)
+      in.r[mt] = *reinterpret_cast<const ushort4_t*>(r_lo + (size_t)es * 48 + mt * 16 + 4 * kg);
+  };
+  In16 cur, nxt;
+  load(t0 < t1 ? t0 : 0, cur);
+  for (int t = t0; t < t1; ++t) {
+    load(t + 1 < t1 ? t + 1 : t, nxt);
+    const int e = t * 16 + j;
+    const bool valid = e < m.nel;
     floatx4_t acc[3];
 #pragma unroll
     for (int mt = 0; mt < 3; ++mt) acc[mt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kt = 0; kt < 3; ++kt) {
-      // inputs 8q .. 8q+7, q = 4 kt + kg: q < 6 -> upwind neighbour of face q/2, its
-      // state rows 8q..; q >= 6 -> own state rows 8q - 48 ..
-      const int q = 4 * kt + kg;
-      const int src = q < 6 ? nb.get(q >> 1) : es;
-      const int row = q < 6 ? 8 * q : 8 * q - 48;
-      // unconditional load at an in-bounds element, then the zero for an inflow
-      // boundary or an idle lane is selected
-      const bf16x8_t ld = *reinterpret_cast<const bf16x8_t*>(lo_in + (size_t)(src >= 0 ? src : es) * 48 + row);
-      const bf16x8_t b = (valid && src >= 0) ? ld : bf16x8_t{};
+      const bf16x8_t b = (valid && cur.up[kt]) ? cur.b[kt] : bf16x8_t{};
 #pragma unroll
       for (int mt = 0; mt < 3; ++mt) acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][kt], b, acc[mt], 0, 0, 0);
     }
-    if (!valid) continue;
+    if (valid) {
 #pragma unroll
-    for (int mt = 0; mt < 3; ++mt) {
-      const size_t off = (size_t)e * 48 + mt * 16 + 4 * kg;
-      const ushort4_t rr = *reinterpret_cast<const ushort4_t*>(r_lo + off);
-      ushort4_t o;
-      o.x = f32_to_bf16(acc[mt].x + bf16_to_f32(rr.x));
-      o.y = f32_to_bf16(acc[mt].y + bf16_to_f32(rr.y));
-      o.z = f32_to_bf16(acc[mt].z + bf16_to_f32(rr.z));
-      o.w = f32_to_bf16(acc[mt].w + bf16_to_f32(rr.w));
-      *reinterpret_cast<ushort4_t*>(lo_out + off) = o;
+      for (int mt = 0; mt < 3; ++mt) {
+        const ushort4_t rr = cur.r[mt];
+        ushort4_t o;
+        o.x = f32_to_bf16(acc[mt].x + bf16_to_f32(rr.x));
+        o.y = f32_to_bf16(acc[mt].y + bf16_to_f32(rr.y));
+        o.z = f32_to_bf16(acc[mt].z + bf16_to_f32(rr.z));
+        o.w = f32_to_bf16(acc[mt].w + bf16_to_f32(rr.w));
+        *reinterpret_cast<ushort4_t*>(lo_out + (size_t)e * 48 + mt * 16 + 4 * kg) = o;
+      }
     }
+    cur = nxt;
   }
 }
 
@@ -2214,11 +2237,15 @@ struct Bf16Ops<F, true> {
       Family<F>::refine_mfma(dp, Ld64{dp.s[0], ne}, store, tol, st);
   }
   static void inner(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
+    // tiles per wavefront: 4 while that fits the grid in one round of resident
+    // workgroups, else 8 (longer pipelines over fewer waves)
+    static const int resident = resident_groups(k_inner_mfma<F>, kThreads);
     const int tiles = (dp.mesh.nel + 15) / 16;
-    const int per_group = kWaves * kMfmaTilesPerWave;
+    const int tpw = tiles <= (size_t)resident * kWaves * 4 ? 4 : 8;
+    const int per_group = kWaves * tpw;
     const dim3 grid((tiles + per_group - 1) / per_group), block(kThreads);
     hipLaunchKernelGGL(k_inner_mfma<F>, grid, block, 0, st, dp.mesh, (const uint16_t*)lo_in, (const uint16_t*)r_lo,
-                       dp.T16, (uint16_t*)lo_out, (const Ctrl*)dp.ctrl);
+                       dp.T16, (uint16_t*)lo_out, (const Ctrl*)dp.ctrl, tpw);
   }
 };
 
