@@ -43,6 +43,7 @@ struct ehdg_problem {
   int predict = 4;        // sweeps the next solve / step is expected to need
   int predict_outer = 2;  // refinements the next mixed-precision solve / step is expected to need
   unsigned seq = 0;       // launch number of the last FP64 sweep queued (the sweeps' lagged tests)
+  unsigned stamp = 0;     // last stamp given to a refinement's last correction sweep (never 0)
   std::string err;
 };
 
@@ -270,7 +271,8 @@ void recover(ehdg_problem* h, int buf, hipStream_t st = nullptr) {
 struct Outer {
   ehdg_problem* h;
   const void* lo_prev = nullptr;
-  int k = 0;  // refinements queued (selects the residual buffer)
+  unsigned applied = 0;  // stamp of the last correction sweep queued (0: none)
+  int k = 0;             // refinements queued (selects the residual buffer)
   void queue(double tol) {
     DevProblem& dp = h->dp;
     if (!mixed(h)) {
@@ -283,11 +285,17 @@ struct Outer {
     // refinement k writes residual buffer rlo[k & 1]; the correction it reads is
     // the previous refinement's last inner iterate, never that buffer
     void* r = dp.rlo[k & 1];
-    refine(dp, lo_prev, r, tol, h->stream);
+    refine(dp, lo_prev, r, tol, applied, h->stream);
+    applied = 0;
     const void* cur = r;
     for (int q = 1; q < h->desc.inner_sweeps; ++q) {
       void* out = dp.lo[q & 1];
-      inner(dp, r, cur, out, h->stream);
+      // the last correction sweep may store s' for the next refinement (stamped)
+      if (q + 1 == h->desc.inner_sweeps) {
+        if (++h->stamp == 0u) ++h->stamp;
+        applied = h->stamp;
+      }
+      inner(dp, r, cur, out, applied, h->stream);
       cur = out;
     }
     lo_prev = cur;

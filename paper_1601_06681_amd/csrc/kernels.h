@@ -44,7 +44,8 @@ struct Ctrl {
   unsigned seg_seq;   // FP64 sweeps: launch number of the sweep before the segment's first
   int ucur;           // solution buffer holding the current time level
   int steps_done;     // backward-Euler steps completed since the last initial state
-  unsigned unused1;
+  unsigned applied;   // refinement forms: stamp of the last correction sweep that also
+                      // stored s' = s + correction (the next refinement finds it in place)
   double last_res;    // last relative increment
   double pad[3];
 };
@@ -161,12 +162,19 @@ struct KernelSet {
   void (*step)(const DevProblem&, int lag, unsigned seq_next, double tol, int lagged, hipStream_t);
   // mixed precision outer step: s' = s^k + lo_in (lo_in ignored on the segment's
   // first refinement); r = g + T in(s') - s' in FP64 into r_out (low precision);
-  // s' stored as s^{k+1}; reduction of ||r|| / ||s' + r||
-  void (*refine32)(const DevProblem&, const void* lo_in, void* r_out, double tol, hipStream_t);
-  // inner sweep on the correction: lo_out = r_lo + T_lo in(lo_in)
-  void (*inner32)(const DevProblem&, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t);
-  void (*refine16)(const DevProblem&, const void* lo_in, void* r_out, double tol, hipStream_t);
-  void (*inner16)(const DevProblem&, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t);
+  // s' stored as s^{k+1}; reduction of ||r|| / ||s' + r||.  stamp != 0: if the control
+  // block's `applied` equals it, s' is already in place (the previous correction sweep
+  // stored it) and only r and the reduction remain
+  void (*refine32)(const DevProblem&, const void* lo_in, void* r_out, double tol, unsigned stamp, hipStream_t);
+  // inner sweep on the correction: lo_out = r_lo + T_lo in(lo_in).  stamp != 0 (the last
+  // sweep of a refinement): where the family's refinement applies the correction in a
+  // pass of its own, this sweep stores s' = s + lo_out in its place (not lo_out) and sets
+  // the control block's `applied` to stamp; elsewhere stamp is ignored
+  void (*inner32)(const DevProblem&, const void* r_lo, const void* lo_in, void* lo_out, unsigned stamp,
+                  hipStream_t);
+  void (*refine16)(const DevProblem&, const void* lo_in, void* r_out, double tol, unsigned stamp, hipStream_t);
+  void (*inner16)(const DevProblem&, const void* r_lo, const void* lo_in, void* lo_out, unsigned stamp,
+                  hipStream_t);
   // workgroups of the FP64 sweep / step completion for n_el elements (the same shape a
   // single problem launches with, so batched and single results agree bit for bit);
   // sweep_groups takes a tuned tiles-per-workgroup in *tiles_per_group (0: default)

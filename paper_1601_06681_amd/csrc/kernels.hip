@@ -1109,9 +1109,10 @@ __global__ __launch_bounds__(kThreads) void k_volume(MeshDev m, const ST* __rest
 // One thread per element: the FP64 state is component-major (coalesced per row), the
 // correction either component-major (FP32) or element-major (BF16, S values per element).
 template <class F, class LDD>
-__global__ __launch_bounds__(256) void k_apply_correction(const Ctrl* ctrl, double* s0, double* s1, LDD d, int nel) {
+__global__ __launch_bounds__(256) void k_apply_correction(const Ctrl* ctrl, double* s0, double* s1, LDD d, int nel,
+                                                          unsigned stamp) {
   const CtrlHead ch = ctrl_head(ctrl);
-  if (ch.done) return;
+  if (ch.done || (stamp != 0u && ctrl->applied == stamp)) return;  // s' already stored
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= nel) return;
   const int parity = (ch.base + ch.iters) & 1;
@@ -1257,6 +1258,34 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
   finish_residual<TL::NW>(d2, n2, ra, ch.iters);
 }
 
+// The last correction sweep of a refinement, where the refinement applies the correction
+// in a pass of its own (k_apply_correction): the sweep stores s' = s + correction (the
+// FP64 value that pass would store, from the same low-precision correction value) in
+// place of the correction, and stamps the control block, so that the pass finds s' in
+// place and returns at once.  The correction itself is not stored: a later pass reads it
+// only when the stamp does not match, which happens only once the control block has
+// moved on (a new step or segment: iteration count 0, so that pass copies s unchanged).
+struct FusedApply {
+  double* s0;
+  double* s1;
+  unsigned stamp;
+  // i: index of value (row, element) in the component-major state
+  __device__ __forceinline__ double load(const CtrlHead& ch, size_t i) const {
+    return ((ch.base + ch.iters) & 1 ? s1 : s0)[i];
+  }
+  __device__ __forceinline__ void put(const CtrlHead& ch, size_t i, double v, double corr) const {
+    ((ch.base + ch.iters) & 1 ? s0 : s1)[i] = ch.iters > 0 ? v + corr : v;
+  }
+  __device__ __forceinline__ void store(const CtrlHead& ch, size_t i, double corr) const {
+    put(ch, i, load(ch, i), corr);
+  }
+  // the stamp lies outside the control block head the other workgroups read, so writing
+  // it while they run changes nothing they see
+  __device__ __forceinline__ void mark(Ctrl* ctrl) const {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->applied = stamp;
+  }
+};
+
 // FP32 correction sweep on the matrix cores: lo_out = r_lo + T in(lo_in) with
 // v_mfma_f32_16x16x4f32 (same fragments as the FP64 sweep, in FP32; the FP32 result
 // fragment holds D[4 (l / 16) + r][l % 16]).
@@ -1272,13 +1301,14 @@ struct Inner32Tiling {
   static constexpr int value = TL::NW;
 };
 
-template <class F, bool PIPE>
+template <class F, bool PIPE, bool FUSE = false>
 __global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_inner32_mfma(
     MeshDev m, Ld32 ld, const float* __restrict__ r_lo, const float* __restrict__ Tf, float* __restrict__ out,
-    const Ctrl* ctrl, int tiles_per_group) {
+    Ctrl* ctrl, int tiles_per_group, FusedApply fa) {
   using TL = typename Inner32Tiling<F>::TL;
   constexpr int MTW = TL::MTW, KT = TL::KT;
-  const int done = ctrl->done;
+  const CtrlHead ch = ctrl_head(ctrl);
+  const int done = ch.done;
   const int lane = threadIdx.x & 63, wave = wave_id();
   const int w = wave % TL::WPG, slot = wave / TL::WPG;
   const int j = lane & 15, kq = lane >> 4;
@@ -1331,6 +1361,20 @@ __global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_inner32_mfma(
       load(t, cur);
     const int e = t * 16 + j;
     const bool valid = e < m.nel;
+    // FUSE with PIPE: the state values s' is formed from, loaded (unconditionally, in
+    // bounds) ahead of the products so that they arrive during them; without PIPE they are
+    // loaded in the epilogue (ahead, their registers would cost a wavefront per SIMD)
+    constexpr bool kEarly = FUSE && PIPE;
+    double sv[kEarly ? MTW : 1][4];
+    if constexpr (kEarly) {
+#pragma unroll
+      for (int u = 0; u < MTW; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (w * MTW + u) + 4 * kq + r;
+          sv[u][r] = fa.load(ch, (size_t)(row < F::S ? row : F::S - 1) * nel + (valid ? e : 0));
+        }
+    }
     float b[KT];
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
@@ -1353,11 +1397,20 @@ __global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_inner32_mfma(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * (w * MTW + u) + 4 * kq + r;
-          if (row < F::S) out[(size_t)row * nel + e] = acc[u][r] + cur.c[u][r];
+          if (row < F::S) {
+            const float v = acc[u][r] + cur.c[u][r];
+            if constexpr (kEarly)
+              fa.put(ch, (size_t)row * nel + e, sv[u][r], (double)v);
+            else if constexpr (FUSE)
+              fa.store(ch, (size_t)row * nel + e, (double)v);
+            else
+              out[(size_t)row * nel + e] = v;
+          }
         }
     }
     if constexpr (PIPE) cur = nxt;
   }
+  if constexpr (FUSE) fa.mark(ctrl);
 }
 
 // Plain FP32 sweep on the matrix cores: s_out = g + T in(s_in) with FP32 state, g and
@@ -1957,9 +2010,9 @@ struct Family {
     static const int r = resident_groups(k_step_mfma<F>, 64 * StepTiling<F>::value);
     return r;
   }
-  template <bool PIPE>
+  template <bool PIPE, bool FUSE = false>
   static int res_inner32() {
-    static const int r = resident_groups(k_inner32_mfma<F, PIPE>, 64 * Inner32Tiling<F>::value);
+    static const int r = resident_groups(k_inner32_mfma<F, PIPE, FUSE>, 64 * Inner32Tiling<F>::value);
     return r;
   }
   static int res_sweep32() {
@@ -2071,11 +2124,12 @@ struct Family {
                        (const double*)(dp.has_src ? dp.gbe : nullptr), dp.g, dp.ctrl, dp.counters + kCounterSet,
                        dp.step_iters, dp.step_cap, lag, tpg, sl);
   }
-  static void refine32(const DevProblem& dp, const void* lo_in, void* r_out, double tol, hipStream_t st) {
+  static void refine32(const DevProblem& dp, const void* lo_in, void* r_out, double tol, unsigned stamp,
+                       hipStream_t st) {
     const size_t ne = (size_t)dp.mesh.nel;
     const StSoa32 store{(float*)r_out, ne};
     if (lo_in)
-      refine_corrected(dp, Ld32{(const float*)lo_in, ne}, store, tol, st);
+      refine_corrected(dp, Ld32{(const float*)lo_in, ne}, store, tol, stamp, st);
     else
       refine_mfma(dp, Ld64{dp.s[0], ne}, store, tol, st);
   }
@@ -2090,14 +2144,16 @@ struct Family {
   }
   // A refinement after the segment's first: where the refinement shares element tiles
   // among wavefronts (the wide families), s' = s + correction is applied by a streaming
-  // kernel first and the refinement gathers s' alone; elsewhere the refinement gathers
+  // kernel first (which returns at once where the last correction sweep already stored
+  // s', stamp) and the refinement gathers s' alone; elsewhere the refinement gathers
   // both and adds them itself.
   template <class LDD, class ST>
-  static void refine_corrected(const DevProblem& dp, const LDD& d, const ST& store, double tol, hipStream_t st) {
+  static void refine_corrected(const DevProblem& dp, const LDD& d, const ST& store, double tol, unsigned stamp,
+                               hipStream_t st) {
     const size_t ne = (size_t)dp.mesh.nel;
     if constexpr (Tiling64<F::S, F::I>::WPG > 1) {
       hipLaunchKernelGGL((k_apply_correction<F, LDD>), dim3((dp.mesh.nel + 255) / 256), dim3(256), 0, st,
-                         (const Ctrl*)dp.ctrl, dp.s[0], dp.s[1], d, dp.mesh.nel);
+                         (const Ctrl*)dp.ctrl, dp.s[0], dp.s[1], d, dp.mesh.nel, stamp);
       refine_mfma<Ld64, ST, true>(dp, Ld64{dp.s[0], ne}, store, tol, st);
     } else {
       refine_mfma(dp, LdSum<LDD>{Ld64{dp.s[0], ne}, d, 1}, store, tol, st);
@@ -2106,24 +2162,38 @@ struct Family {
   // the pipelined correction sweep while the FP32 state (S values per element) is at most
   // 64 MB, a quarter of the Infinity Cache, and each wavefront has two or more tiles
   static constexpr size_t kPipeBytes = (size_t)64 << 20;
-  template <bool PIPE>
-  static void inner32_as(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
+  template <bool PIPE, bool FUSE = false>
+  static void inner32_as(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, unsigned stamp,
+                         hipStream_t st) {
     using TL = typename Inner32Tiling<F>::TL;
     int tpg, groups;
-    mfma_groups(dp.mesh.nel, TL::TS, res_inner32<PIPE>(), tpg, groups);
-    hipLaunchKernelGGL((k_inner32_mfma<F, PIPE>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh,
+    mfma_groups(dp.mesh.nel, TL::TS, res_inner32<PIPE, FUSE>(), tpg, groups);
+    hipLaunchKernelGGL((k_inner32_mfma<F, PIPE, FUSE>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh,
                        Ld32{(const float*)lo_in, (size_t)dp.mesh.nel}, (const float*)r_lo, dp.Tf32,
-                       (float*)lo_out, (const Ctrl*)dp.ctrl, tpg);
+                       (float*)lo_out, dp.ctrl, tpg, FusedApply{dp.s[0], dp.s[1], stamp});
   }
-  static void inner32(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
+  static void inner32(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, unsigned stamp,
+                      hipStream_t st) {
     using TL = typename Inner32Tiling<F>::TL;
     int tpg, groups;
     mfma_groups(dp.mesh.nel, TL::TS, res_inner32<true>(), tpg, groups);
     // pipelined with two or more tiles per wavefront (one would only load itself again)
-    if (tpg >= 2 * TL::TS && (size_t)F::S * dp.mesh.nel * sizeof(float) <= kPipeBytes)
-      inner32_as<true>(dp, r_lo, lo_in, lo_out, st);
+    const bool pipe = tpg >= 2 * TL::TS && (size_t)F::S * dp.mesh.nel * sizeof(float) <= kPipeBytes;
+    // the last sweep of a refinement stores s' itself where the refinement would apply
+    // the correction in a pass of its own
+    if constexpr (Tiling64<F::S, F::I>::WPG > 1) {
+      if (stamp) {
+        if (pipe)
+          inner32_as<true, true>(dp, r_lo, lo_in, lo_out, stamp, st);
+        else
+          inner32_as<false, true>(dp, r_lo, lo_in, lo_out, stamp, st);
+        return;
+      }
+    }
+    if (pipe)
+      inner32_as<true>(dp, r_lo, lo_in, lo_out, 0u, st);
     else
-      inner32_as<false>(dp, r_lo, lo_in, lo_out, st);
+      inner32_as<false>(dp, r_lo, lo_in, lo_out, 0u, st);
   }
 };
 
@@ -2139,14 +2209,15 @@ struct Family {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef unsigned short ushort4_t __attribute__((ext_vector_type(4)));
 
-template <class F>
+template <class F, bool FUSE = false>
 __global__ __launch_bounds__(kThreads) void k_inner_mfma(MeshDev m, const uint16_t* __restrict__ lo_in,
                                                           const uint16_t* __restrict__ r_lo,
                                                           const uint16_t* __restrict__ T16,
-                                                          uint16_t* __restrict__ lo_out, const Ctrl* ctrl,
-                                                          int tiles_per_wave) {
+                                                          uint16_t* __restrict__ lo_out, Ctrl* ctrl,
+                                                          int tiles_per_wave, FusedApply fa) {
   static_assert(F::S == 48 && F::I == 96 && F::NF == 16, "tiling assumes S = 48, I = 96");
-  if (ctrl->done) return;
+  const CtrlHead ch = ctrl_head(ctrl);
+  if (ch.done) return;
   const int lane = threadIdx.x & 63, w = wave_id();
   const int j = lane & 15, kg = lane >> 4;
   // A fragments of T (3 row tiles x 3 k tiles), held for the whole wave
@@ -2212,11 +2283,21 @@ __global__ __launch_bounds__(kThreads) void k_inner_mfma(MeshDev m, const uint16
         o.y = f32_to_bf16(acc[mt].y + bf16_to_f32(rr.y));
         o.z = f32_to_bf16(acc[mt].z + bf16_to_f32(rr.z));
         o.w = f32_to_bf16(acc[mt].w + bf16_to_f32(rr.w));
-        *reinterpret_cast<ushort4_t*>(lo_out + (size_t)e * 48 + mt * 16 + 4 * kg) = o;
+        if constexpr (FUSE) {
+          // s' in the component-major FP64 state: rows mt * 16 + 4 kg + 0..3 of element e
+          const size_t i0 = (size_t)(mt * 16 + 4 * kg) * m.nel + e, st = (size_t)m.nel;
+          fa.store(ch, i0, (double)bf16_to_f32(o.x));
+          fa.store(ch, i0 + st, (double)bf16_to_f32(o.y));
+          fa.store(ch, i0 + 2 * st, (double)bf16_to_f32(o.z));
+          fa.store(ch, i0 + 3 * st, (double)bf16_to_f32(o.w));
+        } else {
+          *reinterpret_cast<ushort4_t*>(lo_out + (size_t)e * 48 + mt * 16 + 4 * kg) = o;
+        }
       }
     }
     cur = nxt;
   }
+  if constexpr (FUSE) fa.mark(ctrl);
 }
 
 // BF16-MFMA refinement launchers (only where the tiling applies)
@@ -2228,24 +2309,33 @@ struct Bf16Ops {
 
 template <class F>
 struct Bf16Ops<F, true> {
-  static void refine(const DevProblem& dp, const void* lo_in, void* r_out, double tol, hipStream_t st) {
+  static void refine(const DevProblem& dp, const void* lo_in, void* r_out, double tol, unsigned stamp,
+                     hipStream_t st) {
     const size_t ne = (size_t)dp.mesh.nel;
     const StAos16<F::S> store{(uint16_t*)r_out};
     if (lo_in)
-      Family<F>::refine_corrected(dp, Ld16Aos<F::S>{(const uint16_t*)lo_in}, store, tol, st);
+      Family<F>::refine_corrected(dp, Ld16Aos<F::S>{(const uint16_t*)lo_in}, store, tol, stamp, st);
     else
       Family<F>::refine_mfma(dp, Ld64{dp.s[0], ne}, store, tol, st);
   }
-  static void inner(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, hipStream_t st) {
+  static void inner(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, unsigned stamp,
+                    hipStream_t st) {
     // tiles per wavefront: 4 while that fits the grid in one round of resident
     // workgroups, else 8 (longer pipelines over fewer waves)
     static const int resident = resident_groups(k_inner_mfma<F>, kThreads);
     const int tiles = (dp.mesh.nel + 15) / 16;
-    const int tpw = tiles <= (size_t)resident * kWaves * 4 ? 4 : 8;
+    const int tpw = tiles <= (long long)resident * kWaves * 4 ? 4 : 8;
     const int per_group = kWaves * tpw;
     const dim3 grid((tiles + per_group - 1) / per_group), block(kThreads);
-    hipLaunchKernelGGL(k_inner_mfma<F>, grid, block, 0, st, dp.mesh, (const uint16_t*)lo_in, (const uint16_t*)r_lo,
-                       dp.T16, (uint16_t*)lo_out, (const Ctrl*)dp.ctrl, tpw);
+    const FusedApply fa{dp.s[0], dp.s[1], stamp};
+    // this family's refinement applies the correction in a pass of its own (wide tiles)
+    static_assert(Tiling64<F::S, F::I>::WPG > 1, "fused application assumes the separate pass");
+    if (stamp)
+      hipLaunchKernelGGL((k_inner_mfma<F, true>), grid, block, 0, st, dp.mesh, (const uint16_t*)lo_in,
+                         (const uint16_t*)r_lo, dp.T16, (uint16_t*)lo_out, dp.ctrl, tpw, fa);
+    else
+      hipLaunchKernelGGL((k_inner_mfma<F, false>), grid, block, 0, st, dp.mesh, (const uint16_t*)lo_in,
+                         (const uint16_t*)r_lo, dp.T16, (uint16_t*)lo_out, dp.ctrl, tpw, fa);
   }
 };
 
