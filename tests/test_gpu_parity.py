@@ -286,11 +286,14 @@ def test_fp32_refine_transport3d_ragged(n, p, beta):
 
 
 @pytest.mark.parametrize("prec", [1, 2])
-def test_refine_forms_transport3d_be_steps_and_resume(prec):
+@pytest.mark.parametrize("inner", [1, 2, 4])
+def test_refine_forms_transport3d_be_steps_and_resume(prec, inner):
     """Backward-Euler steps of the degree-3 3D family in the FP32 and BF16 correction
     forms: there the last correction sweep of a refinement stores s' = s + correction for
     the next refinement (stamped), and a refinement that finds no matching stamp (the
-    first after a new step or a new call) applies the correction in its own pass.  Steps
+    first after a new step or a new call) applies the correction in its own pass.  With
+    one sweep per refinement there is no correction sweep and the pass applies the
+    residual itself; with two the only correction sweep is the one that stores s'.  Steps
     split over two calls, and a solve stopped at its iteration cap then resumed, must
     reach the oracle's FP64 results."""
     import torch
@@ -300,16 +303,16 @@ def test_refine_forms_transport3d_be_steps_and_resume(prec):
     u0 = op.interpolate(lambda X: np.cos(3 * X[..., 0]) * np.sin(2 * X[..., 1]) + X[..., 2])
     load = lambda um: op.load(lambda X: f(X, np), um)
     ref_u, _ = O.be_steps(op, u0, 5, tol=1e-14, load=load)
-    prob = gpu_transport(n, (1.0, 0.9, 0.8), p, beta, 0.5, dt=dt, precision=prec, inner=4)
+    prob = gpu_transport(n, (1.0, 0.9, 0.8), p, beta, 0.5, dt=dt, precision=prec, inner=inner)
     prob.set_initial(torch.tensor(u0.reshape(op.mesh.nel, 1, -1), device=prob.device))
     prob.step(2, 1e-12, 4000)
     prob.step(3, 1e-12, 4000)
     assert rel_err(_gpu_u(prob), ref_u) < 1e-8
-    # steady solve from zero: stopped at a cap of 12 sweeps (3 refinements), then resumed
+    # steady solve from zero: stopped at a cap of 3 refinements, then resumed
     op_s, F_s, _, _ = oracle_transport(n, (1.0, 0.9, 0.8), p, beta, 0.5)
     ref = O.solve(op_s, F_s, np.zeros((op_s.mesh.nel, op_s.ref.Np)), tol=1e-14, max_iter=20000)
-    prob_s = gpu_transport(n, (1.0, 0.9, 0.8), p, beta, 0.5, precision=prec, inner=4)
-    rc, its, res = prob_s.solve(1e-12, 12, allow=(E.EHDG_OK, E.EHDG_ERR_NOT_CONVERGED))
+    prob_s = gpu_transport(n, (1.0, 0.9, 0.8), p, beta, 0.5, precision=prec, inner=inner)
+    rc, its, res = prob_s.solve(1e-12, 3 * inner, allow=(E.EHDG_OK, E.EHDG_ERR_NOT_CONVERGED))
     assert rc == E.EHDG_ERR_NOT_CONVERGED
     rc, its, res = prob_s.solve(1e-12, 50000)
     assert res < 1e-12
