@@ -227,8 +227,9 @@ struct TransportFam {
     ry = rx;
     ey = ex;
   }
-  __device__ __forceinline__ static int own_row(int r) { return NA * NF + r; }
-  static constexpr bool kSelfSum = false;
+  // input column of the element's own state row 0 (row r is column kOwnCol + r; row_load's
+  // x is its raw value)
+  static constexpr int kOwnCol = NA * NF;
 };
 
 // Shallow water, P1 = p + 1.  State per element side f: c_f = (phi + sqrt(Phi)
@@ -282,8 +283,7 @@ struct SweFam {
     ry = (f ^ 1) * NF + k;
     ey = n >= 0 ? n : e;
   }
-  __device__ __forceinline__ static int own_row(int) { return -1; }
-  static constexpr bool kSelfSum = true;
+  static constexpr int kOwnCol = 0;
 };
 
 // Linearized Euler, P1 = p + 1.  State per element side f: the outgoing part
@@ -338,8 +338,7 @@ struct EulerFam {
     ry = (f ^ 1) * 4 * NF + rem;
     ey = n >= 0 ? n : e;
   }
-  __device__ __forceinline__ static int own_row(int) { return -1; }
-  static constexpr bool kSelfSum = true;
+  static constexpr int kOwnCol = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -891,10 +890,16 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
   // stopping test is summed, so their latency overlaps it; a launch that stops discards
   // them (they are only read).
   // (only loads here: every use of a loaded value, even a select, waits for it)
+  // The element's previous state rows, for the increment: in the FP64 result layout a
+  // lane's output rows are kq + 4 r of its row tiles, so where the family's own-state
+  // columns start at a multiple of 4 the lane has already gathered them (x of k tile
+  // kOwnCol / 4 + 4 (row tile) + r); elsewhere they are loaded.  (This path runs only with
+  // WPG == 1: wider tiles took the shared-tile engine above.)
+  constexpr bool kOwnRegs = F::kOwnCol % 4 == 0 && TL::WPG == 1;
   struct TileIn {
     double x[KT], y[KT];
     double g0[MTW][4];
-    double old[MTW][4];
+    double old[kOwnRegs ? 1 : MTW][4];
     Nb nb;
   };
   auto load_tile = [&](int t, bool active, TileIn& in) {
@@ -913,7 +918,7 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
         const int row = 16 * (w * MTW + u) + kq + 4 * r;
         const int rc = row < F::S ? row : F::S - 1;
         in.g0[u][r] = g[(size_t)rc * nel + es];
-        in.old[u][r] = ld(rc, es);
+        if constexpr (!kOwnRegs) in.old[u][r] = ld(rc, es);
       }
   };
   // issue order: the partials (addresses from the launch's arguments), then the tile
@@ -973,7 +978,14 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
         const int row = 16 * (w * MTW + u) + kq + 4 * r;
         if (valid && row < F::S) {
           const double v = acc[u][r];
-          const double dd = v - cur.old[u][r];
+          constexpr int k0 = F::kOwnCol / 4;
+          const int ko = k0 + 4 * u + r;  // WPG == 1: the wavefront's row tiles are 0 .. MTW - 1
+          double o;
+          if constexpr (kOwnRegs)
+            o = cur.x[ko < KT ? ko : KT - 1];
+          else
+            o = cur.old[u][r];
+          const double dd = v - o;
           d2 += dd * dd;
           n2 += v * v;
         }
@@ -1413,6 +1425,27 @@ __global__ __launch_bounds__(64 * Inner32Tiling<F>::value) void k_inner32_mfma(
   if constexpr (FUSE) fa.mark(ctrl);
 }
 
+// 4 x 4 transpose across a wavefront's four 16-lane rows: on entry v[k] of row q (lanes
+// 16 q .. 16 q + 15) is element (q, k); on return v[r] of row q is element (r, q), each lane
+// keeping its column l % 16.  Two stages of register-pair swaps: lanes 32 apart
+// (v_permlane32_swap), then lanes 16 apart (v_permlane16_swap).
+__device__ __forceinline__ void transpose_rows4(float (&v)[4]) {
+  unsigned r0 = __float_as_uint(v[0]), r1 = __float_as_uint(v[1]);
+  unsigned r2 = __float_as_uint(v[2]), r3 = __float_as_uint(v[3]);
+  const auto s02 = __builtin_amdgcn_permlane32_swap(r0, r2, false, false);
+  const auto s13 = __builtin_amdgcn_permlane32_swap(r1, r3, false, false);
+  r0 = s02[0];
+  r2 = s02[1];
+  r1 = s13[0];
+  r3 = s13[1];
+  const auto s01 = __builtin_amdgcn_permlane16_swap(r0, r1, false, false);
+  const auto s23 = __builtin_amdgcn_permlane16_swap(r2, r3, false, false);
+  v[0] = __uint_as_float(s01[0]);
+  v[1] = __uint_as_float(s01[1]);
+  v[2] = __uint_as_float(s23[0]);
+  v[3] = __uint_as_float(s23[1]);
+}
+
 // Plain FP32 sweep on the matrix cores: s_out = g + T in(s_in) with FP32 state, g and
 // operator fragments (v_mfma_f32_16x16x4f32, the correction sweep's tiling), and the
 // stopping test of the FP64 sweep: the increment norms ||s_out - s_in||^2 and
@@ -1452,9 +1485,16 @@ __device__ __forceinline__ void sweep32_body(const MeshDev& m, const float* __re
   // Tile inputs as loads only (gather parts, g, the element's own state); the values are
   // combined and masked at the tile's turn.  g is added after the products, so its loads
   // overlap the MFMAs.
+  // The element's previous state rows, for the increment: the lane's output rows are
+  // 4 kq + r of its row tiles, and the own-state columns it gathered are those of its
+  // 16-lane row, kq mod 4.  Where those columns start at a multiple of 4 and a wavefront
+  // takes all row tiles of its element tile (so that the register index is fixed), each
+  // row tile's values are a 4 x 4 transpose of gathered registers across the wavefront's
+  // four 16-lane rows (transpose_rows4); elsewhere they are loaded.
+  constexpr bool kOwnRegs = F::kOwnCol % 4 == 0 && TL::WPG == 1;
   struct In32 {
     float x[KT], y[KT];
-    float g0[MTW][4], old[MTW][4];
+    float g0[MTW][4], old[kOwnRegs ? 1 : MTW][4];
     Nb nb;
   };
   auto load = [&](int t, bool active, In32& in) {
@@ -1473,7 +1513,7 @@ __device__ __forceinline__ void sweep32_body(const MeshDev& m, const float* __re
         const int row = 16 * (w * MTW + u) + 4 * kq + r;
         const int rc = row < F::S ? row : F::S - 1;
         in.g0[u][r] = g[(size_t)rc * nel + es];
-        in.old[u][r] = ld(rc, es);
+        if constexpr (!kOwnRegs) in.old[u][r] = ld(rc, es);
       }
   };
   const double* parts = nullptr;
@@ -1503,6 +1543,20 @@ __device__ __forceinline__ void sweep32_body(const MeshDev& m, const float* __re
       const float v = F::row_combine(cur.nb, c < F::I ? c : F::I - 1, cur.x[kt], cur.y[kt]);
       b[kt] = (valid && c < F::I) ? v : 0.0f;
     }
+    float old[MTW][4];
+#pragma unroll
+    for (int u = 0; u < MTW; ++u) {
+      if constexpr (kOwnRegs) {
+        constexpr int k0 = F::kOwnCol / 4;
+        const int kb = k0 + 4 * u;  // WPG == 1: the wavefront's row tiles are 0 .. MTW - 1
+#pragma unroll
+        for (int q = 0; q < 4; ++q) old[u][q] = cur.x[kb + q < KT ? kb + q : KT - 1];
+        transpose_rows4(old[u]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) old[u][r] = cur.old[u][r];
+      }
+    }
     floatx4_t acc[MTW];
 #pragma unroll
     for (int u = 0; u < MTW; ++u)
@@ -1519,7 +1573,7 @@ __device__ __forceinline__ void sweep32_body(const MeshDev& m, const float* __re
         const int row = 16 * (w * MTW + u) + 4 * kq + r;
         if (valid && row < F::S) {
           const float v = acc[u][r] + cur.g0[u][r];
-          const double dd = (double)v - (double)cur.old[u][r];
+          const double dd = (double)v - (double)old[u][r];
           d2 += dd * dd;
           n2 += (double)v * (double)v;
           out[(size_t)row * nel + e] = v;
