@@ -228,8 +228,9 @@ struct TransportFam {
     ey = ex;
   }
   // input column of the element's own state row 0 (row r is column kOwnCol + r; row_load's
-  // x is its raw value)
+  // x is its raw value); kOwnRaw: the combined input of such a column is that raw value
   static constexpr int kOwnCol = NA * NF;
+  static constexpr bool kOwnRaw = true;
 };
 
 // Shallow water, P1 = p + 1.  State per element side f: c_f = (phi + sqrt(Phi)
@@ -284,6 +285,7 @@ struct SweFam {
     ey = n >= 0 ? n : e;
   }
   static constexpr int kOwnCol = 0;
+  static constexpr bool kOwnRaw = false;  // the input is the trace c_own + c_neighbour
 };
 
 // Linearized Euler, P1 = p + 1.  State per element side f: the outgoing part
@@ -339,6 +341,7 @@ struct EulerFam {
     ey = n >= 0 ? n : e;
   }
   static constexpr int kOwnCol = 0;
+  static constexpr bool kOwnRaw = false;  // the input is the trace c_own + c_neighbour
 };
 
 // ---------------------------------------------------------------------------
@@ -601,10 +604,14 @@ struct Tiling64 {
 //                      also set aux (a value the epilogue needs, loaded together with
 //                      the C entries)
 //   epi(row, e, v, aux): result of output row for element e (valid lanes only)
+//   OWN_LDS: aux is instead the staged input column F::kOwnCol + row of the element (the
+//                      element's own state row, where F::kOwnRaw: the gather stages it
+//                      unchanged), read from the LDS tile; init then need not load it
 // Loads complete in order and any use of a loaded value (even a select) waits for it, so
 // the combination and the masking of the prefetched columns happen when they are staged,
 // after this tile's MFMAs, and the C entries are masked after the prefetch is issued.
-template <class F, int ROWS, int COLS, int MTW, int WPG, class ColLoad, class ColCombine, class Init, class Epi>
+template <class F, int ROWS, int COLS, int MTW, int WPG, bool OWN_LDS = false, class ColLoad, class ColCombine,
+          class Init, class Epi>
 __device__ __forceinline__ void mfma64_shared_b(const MeshDev& m, const double (&a)[MTW][(COLS + 3) / 4], int t0,
                                                 int t1, double* lds, ColLoad colload, ColCombine colcombine,
                                                 Init init, Epi epi) {
@@ -689,7 +696,14 @@ __device__ __forceinline__ void mfma64_shared_b(const MeshDev& m, const double (
           const int row = 16 * (w * MTW + u) + kq + 4 * r;
           if (row < ROWS) {
             const double v = kAddAfter ? (double)acc[u][r] + (keep[u][r] ? c0[u][r] : 0.0) : (double)acc[u][r];
-            epi(row, e, v, aux[u][r]);
+            double own;
+            if constexpr (OWN_LDS) {
+              static_assert(F::kOwnRaw && F::kOwnCol + ROWS <= COLS, "own rows must be staged unchanged");
+              own = bcur[(F::kOwnCol + row) * 16 + j];
+            } else {
+              own = aux[u][r];
+            }
+            epi(row, e, v, own);
           }
         }
     }
@@ -864,12 +878,18 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
       if (ch.done) return;
     }
     __shared__ double bt[2 * KT * 4 * 16];
-    mfma64_shared_b<F, F::S, F::I, MTW, TL::WPG>(
+    // the previous state rows, for the increment, from the staged tile where the family
+    // stages them unchanged
+    constexpr bool kOwnLds = F::kOwnRaw;
+    mfma64_shared_b<F, F::S, F::I, MTW, TL::WPG, kOwnLds>(
         m, a, t0, t1, bt,
         [&](int c, int es, const Nb& nb, double& x, double& y) { F::row_load(m, es, nb, ld, c, x, y); },
         [&](int c, const Nb& nb, double x, double y) { return F::row_combine(nb, c, x, y); },
         [&](int row, int es, double& old, bool& keep) {
-          old = ld(row, es);
+          if constexpr (kOwnLds)
+            old = 0.0;
+          else
+            old = ld(row, es);
           keep = true;
           return g[(size_t)row * nel + es];
         },
@@ -1193,7 +1213,10 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
   double d2 = 0.0, n2 = 0.0;
   if constexpr (TL::WPG > 1) {
     __shared__ double bt[2 * KT * 4 * 16];
-    mfma64_shared_b<F, F::S, F::I, MTW, TL::WPG>(
+    // the own state rows (the residual's s') from the staged tile where the family stages
+    // them unchanged
+    constexpr bool kOwnLds = F::kOwnRaw;
+    mfma64_shared_b<F, F::S, F::I, MTW, TL::WPG, kOwnLds>(
         m, a, t0, t1, bt,
         [&](int c, int es, const Nb& nb, double& x, double& y) {
           if constexpr (APPLIED) {
@@ -1210,7 +1233,10 @@ __global__ __launch_bounds__(64 * SweepWaves<F>::value) void k_refine_mfma(
             return x;
         },
         [&](int row, int es, double& own, bool& keep) {
-          own = ld(row, es);
+          if constexpr (kOwnLds)
+            own = 0.0;
+          else
+            own = ld(row, es);
           keep = true;
           return g[(size_t)row * nel + es];
         },
