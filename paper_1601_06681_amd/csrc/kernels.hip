@@ -1513,11 +1513,13 @@ __device__ __forceinline__ void sweep32_body(const MeshDev& m, const float* __re
   // overlap the MFMAs.
   // The element's previous state rows, for the increment: the lane's output rows are
   // 4 kq + r of its row tiles, and the own-state columns it gathered are those of its
-  // 16-lane row, kq mod 4.  Where those columns start at a multiple of 4 and a wavefront
-  // takes all row tiles of its element tile (so that the register index is fixed), each
-  // row tile's values are a 4 x 4 transpose of gathered registers across the wavefront's
-  // four 16-lane rows (transpose_rows4); elsewhere they are loaded.
-  constexpr bool kOwnRegs = F::kOwnCol % 4 == 0 && TL::WPG == 1;
+  // 16-lane row, kq mod 4.  Where a wavefront takes all row tiles of its element tile (so
+  // that the register index is fixed), each row tile's values come from gathered registers
+  // by 4 x 4 transposes across the wavefront's four 16-lane rows (transpose_rows4): with
+  // o = kOwnCol mod 4, output row r of the tile is own column kOwnCol + 16 u + 4 kq + r, in
+  // row (o + r) mod 4 of the transpose of registers k0 + 4 u + (o + r) / 4 + (0 .. 3)
+  // (k0 = kOwnCol / 4): one transpose if o = 0, two otherwise.  Elsewhere they are loaded.
+  constexpr bool kOwnRegs = TL::WPG == 1;
   struct In32 {
     float x[KT], y[KT];
     float g0[MTW][4], old[kOwnRegs ? 1 : MTW][4];
@@ -1573,11 +1575,19 @@ __device__ __forceinline__ void sweep32_body(const MeshDev& m, const float* __re
 #pragma unroll
     for (int u = 0; u < MTW; ++u) {
       if constexpr (kOwnRegs) {
-        constexpr int k0 = F::kOwnCol / 4;
+        constexpr int k0 = F::kOwnCol / 4, o = F::kOwnCol % 4;
         const int kb = k0 + 4 * u;  // WPG == 1: the wavefront's row tiles are 0 .. MTW - 1
+        float t0[4], t1[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) old[u][q] = cur.x[kb + q < KT ? kb + q : KT - 1];
-        transpose_rows4(old[u]);
+        for (int q = 0; q < 4; ++q) t0[q] = cur.x[kb + q < KT ? kb + q : KT - 1];
+        transpose_rows4(t0);
+        if constexpr (o != 0) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) t1[q] = cur.x[kb + 1 + q < KT ? kb + 1 + q : KT - 1];
+          transpose_rows4(t1);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) old[u][r] = (o + r) < 4 ? t0[(o + r) & 3] : t1[(o + r) & 3];
       } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r) old[u][r] = cur.old[u][r];
