@@ -126,6 +126,11 @@ struct Ld16Aos {  // BF16, element-major: the S values of an element are contigu
   const uint16_t* p;
   __device__ __forceinline__ float operator()(int r, int e) const { return bf16_to_f32(p[(size_t)e * S + r]); }
 };
+template <int S>
+struct Ld32Aos {  // FP32, element-major
+  const float* p;
+  __device__ __forceinline__ float operator()(int r, int e) const { return p[(size_t)e * S + r]; }
+};
 // loader of a component-major state of element type ST (double or float)
 template <typename ST>
 using LdOf = std::conditional_t<std::is_same_v<ST, float>, Ld32, Ld64>;
@@ -1057,6 +1062,11 @@ struct StSoa32 {  // FP32, component-major
   float* p;
   size_t nel;
   __device__ __forceinline__ void operator()(int r, int e, double v) const { p[(size_t)r * nel + e] = (float)v; }
+};
+template <int S>
+struct StAos32 {  // FP32, element-major
+  float* p;
+  __device__ __forceinline__ void operator()(int r, int e, double v) const { p[(size_t)e * S + r] = (float)v; }
 };
 template <int S>
 struct StAos16 {  // BF16, element-major
@@ -2429,6 +2439,112 @@ struct Bf16Ops<F, true> {
   }
 };
 
+// FP32 correction sweep with element-major correction and residual (3D transport, degree 3:
+// S = 48, I = 96): lo_out = r + T in(lo_in) with v_mfma_f32_16x16x4f32 as in k_inner32_mfma,
+// but with the contraction's columns taken in a permuted order, so that a lane's inputs
+// are consecutive state rows: k tile 4 b + s gives lane (j, kq) input column
+// 16 b + 4 kq + s, so the four k tiles 4 b .. 4 b + 3 of a lane are one 16-byte load of rows
+// 16 b + 4 kq .. + 3 of one element (b < 3: the upwind neighbour across face b, whose
+// state rows 16 b .. are that face's inflow; b >= 3: the element's own rows).  The operator
+// fragments are read in the same permuted order from the FP32 fragment array.  The result
+// rows 4 kq + 0..3 of a row tile are consecutive too: the residual is one 16-byte load and
+// the correction one 16-byte store per row tile.  Tiles and pipelining as in k_inner_mfma;
+// FUSE as in k_inner32_mfma, unpipelined, with the FP64 state values s' is formed from
+// loaded in the epilogue (the next tile's loads, or those values, held over the products
+// would cost a wavefront per SIMD).
+typedef float floatx4v_t __attribute__((ext_vector_type(4)));
+
+template <class F, bool FUSE = false>
+__global__ __launch_bounds__(kThreads) void k_inner32_aos(MeshDev m, const float* __restrict__ lo_in,
+                                                           const float* __restrict__ r_lo,
+                                                           const float* __restrict__ Tf,
+                                                           float* __restrict__ lo_out, Ctrl* ctrl,
+                                                           int tiles_per_wave, FusedApply fa) {
+  static_assert(F::S == 48 && F::I == 96 && F::NF == 16, "tiling assumes S = 48, I = 96");
+  constexpr int KT = 24;  // the FP32 fragment array's k tiles (96 columns)
+  const CtrlHead ch = ctrl_head(ctrl);
+  if (ch.done) return;
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int j = lane & 15, kq = lane >> 4;
+  // A[16 mt + j][16 b + 4 kq + s] for k tile 4 b + s; the fragment array holds A[16 mt +
+  // l % 16][4 k + l / 16] of k tile k at lane l
+  float a[3][KT];
+#pragma unroll
+  for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) a[mt][4 * b + s4] = Tf[(mt * KT + 4 * b + kq) * 64 + 16 * s4 + j];
+  const int ntiles = (m.nel + 15) >> 4;
+  const int t0 = (remap_block(blockIdx.x, gridDim.x) * kWaves + w) * tiles_per_wave;
+  const int t1 = min(t0 + tiles_per_wave, ntiles);
+  // a tile's inputs as loads only (unconditional, at an in-bounds element: the lane's own
+  // for an inflow boundary or an idle lane; the zero of an inflow boundary is selected at
+  // the tile's turn), and the next tile's loads in flight over this tile's MFMAs
+  struct In32a {
+    floatx4v_t b[6];
+    floatx4v_t r[3];
+    bool up[3];
+  };
+  auto load = [&](int t, In32a& in) {
+    const int e = t * 16 + j;
+    const int es = e < m.nel ? e : 0;
+    Nb nb;
+    F::neighbours(m, es, nb);
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      const int src = b < 3 ? nb.get(b) : es;
+      if (b < 3) in.up[b] = src >= 0;
+      const int row = 16 * (b < 3 ? b : b - 3) + 4 * kq;
+      in.b[b] = *reinterpret_cast<const floatx4v_t*>(lo_in + (size_t)(src >= 0 ? src : es) * 48 + row);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 3; ++mt)
+      in.r[mt] = *reinterpret_cast<const floatx4v_t*>(r_lo + (size_t)es * 48 + 16 * mt + 4 * kq);
+  };
+  In32a cur, nxt;
+  if constexpr (!FUSE) load(t0 < t1 ? t0 : 0, cur);
+  for (int t = t0; t < t1; ++t) {
+    const int e = t * 16 + j;
+    const bool valid = e < m.nel;
+    if constexpr (FUSE)
+      load(t, cur);
+    else
+      load(t + 1 < t1 ? t + 1 : t, nxt);
+    floatx4_t acc[3];
+#pragma unroll
+    for (int mt = 0; mt < 3; ++mt) acc[mt] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      const bool use = valid && (b >= 3 || cur.up[b < 3 ? b : 0]);
+      const floatx4v_t bv = use ? cur.b[b] : floatx4v_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int mt = 0; mt < 3; ++mt)
+          acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt][4 * b + s4], bv[s4], acc[mt], 0, 0, 0);
+    }
+    if (valid) {
+#pragma unroll
+      for (int mt = 0; mt < 3; ++mt) {
+        floatx4v_t o;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] = acc[mt][r] + cur.r[mt][r];
+        if constexpr (FUSE) {
+          // s' in the component-major FP64 state: rows 16 mt + 4 kq + 0..3 of element e
+          const size_t i0 = (size_t)(16 * mt + 4 * kq) * m.nel + e, st = (size_t)m.nel;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) fa.store(ch, i0 + r * st, (double)o[r]);
+        } else {
+          *reinterpret_cast<floatx4v_t*>(lo_out + (size_t)e * 48 + 16 * mt + 4 * kq) = o;
+        }
+      }
+    }
+    if constexpr (!FUSE) cur = nxt;
+  }
+  if constexpr (FUSE) fa.mark(ctrl);
+}
+
 template <class F>
 struct HasMfmaTiling {
   static constexpr bool value = false;
@@ -2438,14 +2554,72 @@ struct HasMfmaTiling<TransportFam<3, 3, 4>> {
   static constexpr bool value = true;
 };
 
+// The FP32 correction form's refinement and correction sweep: element-major correction
+// and residual where the family has the tiling of k_inner32_aos and the FP32 state is
+// larger than a quarter of the Infinity Cache (64 MB; below that the component-major
+// state is served from that cache and its pipelined sweep measured as fast), else the
+// component-major form of Family<F>.  The choice is a function of the element count, so
+// a problem's refinement, correction sweeps and correction application all take the same
+// layout.
+template <class F, bool AOS>
+struct Fp32Ops {
+  static void refine(const DevProblem& dp, const void* lo_in, void* r_out, double tol, unsigned stamp,
+                     hipStream_t st) {
+    Family<F>::refine32(dp, lo_in, r_out, tol, stamp, st);
+  }
+  static void inner(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, unsigned stamp,
+                    hipStream_t st) {
+    Family<F>::inner32(dp, r_lo, lo_in, lo_out, stamp, st);
+  }
+};
+
+template <class F>
+struct Fp32Ops<F, true> {
+  static bool aos(const DevProblem& dp) { return (size_t)F::S * dp.mesh.nel * sizeof(float) > Family<F>::kPipeBytes; }
+  static void refine(const DevProblem& dp, const void* lo_in, void* r_out, double tol, unsigned stamp,
+                     hipStream_t st) {
+    if (!aos(dp)) {
+      Family<F>::refine32(dp, lo_in, r_out, tol, stamp, st);
+      return;
+    }
+    const size_t ne = (size_t)dp.mesh.nel;
+    const StAos32<F::S> store{(float*)r_out};
+    if (lo_in)
+      Family<F>::refine_corrected(dp, Ld32Aos<F::S>{(const float*)lo_in}, store, tol, stamp, st);
+    else
+      Family<F>::refine_mfma(dp, Ld64{dp.s[0], ne}, store, tol, st);
+  }
+  static void inner(const DevProblem& dp, const void* r_lo, const void* lo_in, void* lo_out, unsigned stamp,
+                    hipStream_t st) {
+    if (!aos(dp)) {
+      Family<F>::inner32(dp, r_lo, lo_in, lo_out, stamp, st);
+      return;
+    }
+    // tiles per wavefront as in the BF16 correction sweep
+    static const int resident = resident_groups(k_inner32_aos<F>, kThreads);
+    const int tiles = (dp.mesh.nel + 15) / 16;
+    const int tpw = tiles <= (long long)resident * kWaves * 4 ? 4 : 8;
+    const int per_group = kWaves * tpw;
+    const dim3 grid((tiles + per_group - 1) / per_group), block(kThreads);
+    const FusedApply fa{dp.s[0], dp.s[1], stamp};
+    static_assert(Tiling64<F::S, F::I>::WPG > 1, "fused application assumes the separate pass");
+    if (stamp)
+      hipLaunchKernelGGL((k_inner32_aos<F, true>), grid, block, 0, st, dp.mesh, (const float*)lo_in,
+                         (const float*)r_lo, dp.Tf32, (float*)lo_out, dp.ctrl, tpw, fa);
+    else
+      hipLaunchKernelGGL((k_inner32_aos<F, false>), grid, block, 0, st, dp.mesh, (const float*)lo_in,
+                         (const float*)r_lo, dp.Tf32, (float*)lo_out, dp.ctrl, tpw, fa);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // registry
 // ---------------------------------------------------------------------------
 template <class F>
 static const KernelSet* set_of() {
   static const KernelSet ks = {&Family<F>::sweep64,       &Family<F>::volume,
-                               &Family<F>::step,          &Family<F>::refine32,
-                               &Family<F>::inner32,       Bf16Ops<F, HasMfmaTiling<F>::value>::refine,
+                               &Family<F>::step,          &Fp32Ops<F, HasMfmaTiling<F>::value>::refine,
+                               &Fp32Ops<F, HasMfmaTiling<F>::value>::inner, Bf16Ops<F, HasMfmaTiling<F>::value>::refine,
                                Bf16Ops<F, HasMfmaTiling<F>::value>::inner,
                                &Family<F>::sweep_groups,  &Family<F>::step_groups,
                                &Family<F>::sweep64_batch, &Family<F>::step_batch,
