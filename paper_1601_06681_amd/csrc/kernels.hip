@@ -915,12 +915,15 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
   // stopping test is summed, so their latency overlaps it; a launch that stops discards
   // them (they are only read).
   // (only loads here: every use of a loaded value, even a select, waits for it)
-  // The element's previous state rows, for the increment: in the FP64 result layout a
-  // lane's output rows are kq + 4 r of its row tiles, so where the family's own-state
-  // columns start at a multiple of 4 the lane has already gathered them (x of k tile
-  // kOwnCol / 4 + 4 (row tile) + r); elsewhere they are loaded.  (This path runs only with
-  // WPG == 1: wider tiles took the shared-tile engine above.)
-  constexpr bool kOwnRegs = F::kOwnCol % 4 == 0 && TL::WPG == 1;
+  // The element's previous state rows, for the increment, from the gathered registers: in
+  // the FP64 result layout a lane's output rows are kq + 4 r of its row tiles; with
+  // o = kOwnCol mod 4 and k0 = kOwnCol / 4, output row r of row tile u is own column
+  // kOwnCol + 16 u + kq + 4 r, held by 16-lane row (kq + o) mod 4 in register
+  // k0 + 4 u + r + (kq + o >= 4).  For o = 0 that is the lane itself; otherwise each lane
+  // offers register k0 + 4 u + r + (its row < o) and reads it from the lane 16 o further
+  // on (a shuffle over the whole wavefront).  (This path runs only with WPG == 1: wider
+  // tiles took the shared-tile engine above.)
+  constexpr bool kOwnRegs = TL::WPG == 1;
   struct TileIn {
     double x[KT], y[KT];
     double g0[MTW][4];
@@ -996,6 +999,25 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
 #pragma unroll
       for (int u = 0; u < MTW; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][kt], b[kt], acc[u], 0, 0, 0);
     // the increment against the element's own previous state
+    double prev[MTW][4];
+#pragma unroll
+    for (int u = 0; u < MTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if constexpr (kOwnRegs) {
+          constexpr int k0 = F::kOwnCol / 4, o = F::kOwnCol % 4;
+          const int ka = k0 + 4 * u + r;  // WPG == 1: the wavefront's row tiles are 0 .. MTW - 1
+          const double xa = cur.x[ka < KT ? ka : KT - 1];
+          if constexpr (o == 0) {
+            prev[u][r] = xa;
+          } else {
+            const double xb = cur.x[ka + 1 < KT ? ka + 1 : KT - 1];
+            prev[u][r] = __shfl(kq < o ? xb : xa, (lane + 16 * o) & 63);
+          }
+        } else {
+          prev[u][r] = cur.old[u][r];
+        }
+      }
 #pragma unroll
     for (int u = 0; u < MTW; ++u)
 #pragma unroll
@@ -1003,14 +1025,7 @@ __device__ __forceinline__ void sweep_mfma_body(MeshDev m, Ld64 ld, const double
         const int row = 16 * (w * MTW + u) + kq + 4 * r;
         if (valid && row < F::S) {
           const double v = acc[u][r];
-          constexpr int k0 = F::kOwnCol / 4;
-          const int ko = k0 + 4 * u + r;  // WPG == 1: the wavefront's row tiles are 0 .. MTW - 1
-          double o;
-          if constexpr (kOwnRegs)
-            o = cur.x[ko < KT ? ko : KT - 1];
-          else
-            o = cur.old[u][r];
-          const double dd = v - o;
+          const double dd = v - prev[u][r];
           d2 += dd * dd;
           n2 += v * v;
         }

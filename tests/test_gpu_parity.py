@@ -248,6 +248,31 @@ def test_transport3d_full_size_first_sweeps():
     assert rel_err(_gpu_u(prob), u) < ITER_TOL
 
 
+# (n, p, beta): the element's own state starts at input column S = (active axes) x (face
+# nodes); the one-tile-per-wavefront sweep takes the previous state rows for the increment
+# from its gathered registers, by a row shuffle that depends on S mod 4
+@pytest.mark.parametrize("n,p,beta", [
+    ((13, 7), 3, (1.0, 0.5)),          # S = 8: 0 mod 4
+    ((13, 7), 4, (0.0, -0.9)),         # S = 5: 1 mod 4
+    ((13, 7), 2, (-0.8, 0.6)),         # S = 6: 2 mod 4
+    ((13, 7), 2, (1.0, 0.0)),          # S = 3: 3 mod 4
+    ((9, 7, 5), 2, (0.0, 1.0, -0.6)),  # S = 18: 2 mod 4
+    ((9, 7, 5), 2, (1.0, 0.7, 0.3)),   # S = 27: 3 mod 4
+])
+def test_fp64_increments_match_oracle_history(n, p, beta):
+    """The FP64 sweep's recorded relative increments over the first 10 sweeps against the
+    oracle's: the same quantities in FP64, summed in another order (1e-9 relative)."""
+    from paper_1601_06681_amd import ehdg as E
+    L = (1.0, 0.8, 0.7)[:len(n)]
+    op, F, _, _ = oracle_transport(n, L, p, beta, 1.0)
+    k = 10
+    ref = O.solve(op, F, np.zeros((op.mesh.nel, op.ref.Np)), tol=0.0, max_iter=k)
+    prob = gpu_transport(n, L, p, beta, 1.0)
+    prob.solve(0.0, k, allow=(E.EHDG_OK, E.EHDG_ERR_NOT_CONVERGED))
+    np.testing.assert_allclose(prob.residuals(0, k), np.asarray(ref["hist"][:k]), rtol=1e-9)
+    prob.close()
+
+
 @pytest.mark.parametrize("inner", [2, 6])
 def test_bf16_mfma_refine_transport3d(inner):
     """BF16 correction sweeps on MFMA (FP32 accumulation) + FP64 residual refinement
