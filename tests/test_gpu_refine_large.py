@@ -50,6 +50,21 @@ def test_fp32_form_element_major_reaches_fp64_fixed_point(fp64_fixed_point, inne
     prob.close()
 
 
+def test_bf16_form_eight_tiles_per_wavefront_reaches_fp64_fixed_point(fp64_fixed_point):
+    """The BF16 correction sweep takes 8 tiles per wavefront once the grid at 4 would need
+    more than one round of resident workgroups.  At 100 or more registers per lane at most
+    5 wavefronts fit per SIMD, at most 1280 workgroups of 4 wavefronts: 64^3 (16 384 tiles)
+    runs 4 per wavefront, this mesh (23 324 tiles) 8, with the last correction sweep
+    storing s'."""
+    prob = gpu_transport(N, L, P, BETA, SIGMA, precision=2, inner=8)
+    rc, its, res = prob.solve(1e-11, 100000)
+    assert res < 1e-11
+    err = rel_err(_u(prob), fp64_fixed_point)
+    print(f"\n[large] BF16 form, 8 sweeps per refinement: {its} equivalent sweeps, rel err {err:.2e}")
+    assert err < 1e-8
+    prob.close()
+
+
 def test_fp32_form_element_major_be_steps_equal_fp64():
     import torch
     dt = 0.05
