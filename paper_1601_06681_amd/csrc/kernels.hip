@@ -717,6 +717,131 @@ __device__ __forceinline__ void mfma64_shared_b(const MeshDev& m, const double (
   }
 }
 
+// Matrix-core engine with the whole operator in LDS, for contractions whose operator
+// fits there (the step completion of the smaller families): the workgroup has copied the
+// fragment-major operator Mf (MT row tiles x KT k tiles x 64 lanes) into LDS (lds_a_copy,
+// at the start of the kernel, so that the copy overlaps the kernel's set-up).  Each
+// wavefront owns TPW element tiles (t0 + w + i NW below t1): gather() loads the B
+// fragments of all of them straight into registers at once, and apply() runs all MT row
+// tiles over each in turn as independent accumulator chains, reading the operator
+// fragments from LDS: the later tiles' loads are in flight during the first tile's
+// products, and each tile's stores during the next one's.  (A fixed count of tiles, not
+// a loop over tiles: in a loop the compiler keeps every column's address across
+// iterations, beyond the register budget.)  Each row tile takes its k tiles in order,
+// from the C entries (C_FIRST) or from zero with the C entries added after the products,
+// whichever the other engine does for the same family, so that the two give bitwise the
+// same results.
+//   colload / colcombine / epi as for mfma64_shared_b; init(row, es, aux, keep) as there
+template <int ROWS, int COLS, int NW>
+__device__ __forceinline__ void lds_a_copy(const double* __restrict__ Mf, double* la) {
+  constexpr int kTotal = ((ROWS + 15) / 16) * ((COLS + 3) / 4) * 64;
+#pragma unroll
+  for (int i0 = 0; i0 < kTotal; i0 += 64 * NW) {
+    const int i = i0 + (int)threadIdx.x;
+    if (i < kTotal) la[i] = Mf[i];
+  }
+}
+template <class F, int ROWS, int COLS, int NW, int TPW, int MH, bool C_FIRST>
+struct LdsAEngine {
+  static constexpr int MT = (ROWS + 15) / 16, KT = (COLS + 3) / 4;
+  double b[TPW][KT];
+  int ev[TPW];
+  // the B fragments of this wavefront's tiles (zero past t1 and past the last element)
+  template <class ColLoad, class ColCombine>
+  __device__ __forceinline__ void gather(const MeshDev& m, int t0, int t1, ColLoad colload, ColCombine colcombine) {
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const int j = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int t = t0 + w + i * NW;
+      const int e = t * 16 + j;
+      const bool valid = t < t1 && e < m.nel;
+      const int es = valid ? e : 0;
+      ev[i] = valid ? e : -1;
+      Nb nb;
+      F::neighbours(m, es, nb);
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) {
+        const int c = 4 * kt + kq, cc = c < COLS ? c : COLS - 1;
+        double x, y;
+        colload(cc, es, nb, x, y);
+        const double v = colcombine(cc, nb, x, y);
+        b[i][kt] = (valid && c < COLS) ? v : 0.0;
+      }
+    }
+  }
+  // the products and the epilogue (la: the operator in LDS, copied by every thread of the
+  // workgroup before this call)
+  template <class Init, class Epi>
+  __device__ __forceinline__ void apply(const double* la, int t0, int t1, Init init, Epi epi) {
+    __syncthreads();  // the operator copy is complete
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const int kq = lane >> 4;
+    if (t0 + w >= t1) return;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      if (t0 + w + i * NW >= t1) break;  // wavefront-uniform
+      const int e = ev[i];
+      const bool valid = e >= 0;
+      const int es = valid ? e : 0;
+      // the row tiles in passes of MH (the accumulators of a pass and the B fragments within
+      // the register budget); the next k tile's operator fragments are read from LDS while
+      // this k tile's products run
+#pragma unroll
+      for (int h = 0; h < MT; h += MH) {
+        doublex4_t acc[MH];
+        double ac[MH], an[MH], aux[MH][4];
+#pragma unroll
+        for (int u = 0; u < MH; ++u) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (h + u) + kq + 4 * r;
+            bool keep = false;
+            double c0 = 0.0;
+            if constexpr (C_FIRST) c0 = init(row < ROWS ? row : ROWS - 1, es, aux[u][r], keep);
+            acc[u][r] = (C_FIRST && valid && h + u < MT && row < ROWS && keep) ? c0 : 0.0;
+          }
+          ac[u] = h + u < MT ? la[((h + u) * KT) * 64 + lane] : 0.0;
+        }
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+#pragma unroll
+          for (int u = 0; u < MH; ++u)
+            an[u] = (kt + 1 < KT && h + u < MT) ? la[((h + u) * KT + kt + 1) * 64 + lane] : 0.0;
+#pragma unroll
+          for (int u = 0; u < MH; ++u)
+            if (h + u < MT) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[u], b[i][kt], acc[u], 0, 0, 0);
+#pragma unroll
+          for (int u = 0; u < MH; ++u) ac[u] = an[u];
+          // the LDS reads ahead of the products (the compiler would otherwise issue them
+          // after the products and wait for them at once)
+          __builtin_amdgcn_sched_group_barrier(0x100, MH, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, MH, 0);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (valid) {
+#pragma unroll
+          for (int u = 0; u < MH; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * (h + u) + kq + 4 * r;
+              if (h + u < MT && row < ROWS) {
+                if constexpr (C_FIRST) {
+                  epi(row, e, (double)acc[u][r], aux[u][r]);
+                } else {
+                  double a1;
+                  bool keep;
+                  const double c0 = init(row, es, a1, keep);
+                  epi(row, e, (double)acc[u][r] + (keep ? c0 : 0.0), a1);
+                }
+              }
+            }
+        }
+      }
+    }
+  }
+};
+
 template <class F>
 struct SweepWaves {  // wavefronts per workgroup of the matrix-core sweep
   static constexpr int value = Tiling64<F::S, F::I>::NW;
@@ -1668,6 +1793,17 @@ struct StepTiling {
   using TL = Tiling64<F::N + F::S, F::N + F::I, kStepMaxA>;
   static constexpr int value = TL::NW;
 };
+// The step completion with the stacked operator in LDS (LdsAEngine): workgroups of
+// kStepLdsWaves wavefronts, kStepLdsTiles element tiles per wavefront, for families whose
+// operator fits in 96 KB and whose B fragments (all tiles) and the accumulators of half
+// the row tiles fit well within half of the register file (two wavefronts per SIMD).
+constexpr int kStepLdsWaves = 8, kStepLdsTiles = 2;
+template <class F>
+struct StepLdsA {
+  static constexpr int MT = (F::N + F::S + 15) / 16, KT = (F::N + F::I + 3) / 4, MH = (MT + 1) / 2;
+  static constexpr size_t bytes = (size_t)MT * KT * 64 * 8;
+  static constexpr bool ok = bytes <= 96 * 1024 && 2 * KT * kStepLdsTiles + 8 * MH <= 160;
+};
 
 // Lagged stopping test of a step's last sweep (lagged FP64 sweeps leave it pending).
 struct StepLag {
@@ -1682,7 +1818,7 @@ struct StepLag {
 
 // ST: element type of the trace state and of g (FP64, or FP32 in the plain FP32 form;
 // the contraction itself is FP64 either way).
-template <class F, typename ST = double>
+template <class F, typename ST = double, bool LDSA = false>
 __device__ __forceinline__ void step_mfma_body(MeshDev m, ST* s0, ST* s1, const double* __restrict__ Mf,
                                                double* u0, double* u1, const double* __restrict__ w_src,
                                                const double* __restrict__ gbe, ST* __restrict__ g_out,
@@ -1690,16 +1826,22 @@ __device__ __forceinline__ void step_mfma_body(MeshDev m, ST* s0, ST* s1, const 
                                                int tiles_per_group, int bid, int nbk, const StepLag& sl) {
   using TL = typename StepTiling<F>::TL;
   constexpr int MTW = TL::MTW, KT = TL::KT, N = F::N, ROWS = F::N + F::S, COLS = F::N + F::I;
+  constexpr int NW = LDSA ? kStepLdsWaves : TL::NW;
   const CtrlHead ch = ctrl_head(ctrl);
   const unsigned seg = ctrl->seg_seq;
   const int lane = threadIdx.x & 63, wave = wave_id();
   const int w = wave % TL::WPG, slot = wave / TL::WPG;
   const int j = lane & 15, kq = lane >> 4;
   double a[MTW][KT];
+  if constexpr (LDSA) {
+    // the operator into LDS while the control block and the partial sums are read
+    lds_a_copy<ROWS, COLS, NW>(Mf, reinterpret_cast<double*>(g_smem));
+  } else {
 #pragma unroll
-  for (int u = 0; u < MTW; ++u)
+    for (int u = 0; u < MTW; ++u)
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt) a[u][kt] = Mf[((w * MTW + u) * KT + kt) * 64 + lane];
+      for (int kt = 0; kt < KT; ++kt) a[u][kt] = Mf[((w * MTW + u) * KT + kt) * 64 + lane];
+  }
   // K: sweeps of this step (its last local solve read s^(K-1)); conv: the step converged
   int K = ch.iters;
   bool conv = ch.status == 1, reduced = false;
@@ -1707,7 +1849,7 @@ __device__ __forceinline__ void step_mfma_body(MeshDev m, ST* s0, ST* s1, const 
   if (sl.lagged) {
     __shared__ double sq[kVirtLanes / 64][2];
     __shared__ int s_done, s_status;
-    canonical_sums<TL::NW, false>(sl.partials + (size_t)((sl.seq_next - 1u) & 1u) * sl.stride, sl.nb, sq);
+    canonical_sums<NW, false>(sl.partials + (size_t)((sl.seq_next - 1u) & 1u) * sl.stride, sl.nb, sq);
     if (threadIdx.x == 0) {
       s_done = ch.done;
       s_status = ch.status;
@@ -1799,7 +1941,14 @@ __device__ __forceinline__ void step_mfma_body(MeshDev m, ST* s0, ST* s1, const 
     else if (g_out)
       g_out[(size_t)(q - N) * nel + e] = (ST)v;
   };
-  if constexpr (TL::WPG > 1) {
+  if constexpr (LDSA) {
+    // the shared-tile engine adds the C entries after the products where a wavefront has one
+    // row tile; it and the one-tile-per-wavefront path start from them otherwise
+    constexpr bool kCFirst = !(TL::WPG > 1 && TL::MTW == 1);
+    LdsAEngine<F, ROWS, COLS, NW, kStepLdsTiles, StepLdsA<F>::MH, kCFirst> eng;
+    eng.gather(m, t0, t1, colload, colcombine);
+    eng.apply(reinterpret_cast<const double*>(g_smem), t0, t1, init, epi);
+  } else if constexpr (TL::WPG > 1) {
     __shared__ double bt[2 * KT * 4 * 16];
     mfma64_shared_b<F, ROWS, COLS, MTW, TL::WPG>(m, a, t0, t1, bt, colload, colcombine, init_flat, epi);
   } else {
@@ -1872,6 +2021,15 @@ __global__ __launch_bounds__(64 * StepTiling<F>::value) void k_step_mfma(
     unsigned* cnt, int* step_iters, int step_cap, int lag, int tiles_per_group, StepLag sl) {
   step_mfma_body<F, ST>(m, s0, s1, Mf, u0, u1, w_src, gbe, g_out, ctrl, cnt, step_iters, step_cap, lag,
                         tiles_per_group, (int)blockIdx.x, (int)gridDim.x, sl);
+}
+// The same with the stacked operator in LDS (dynamic LDS of StepLdsA<F>::bytes).
+template <class F, typename ST = double>
+__global__ __launch_bounds__(64 * kStepLdsWaves) void k_step_lds(
+    MeshDev m, ST* s0, ST* s1, const double* __restrict__ Mf, double* u0, double* u1,
+    const double* __restrict__ w_src, const double* __restrict__ gbe, ST* __restrict__ g_out, Ctrl* ctrl,
+    unsigned* cnt, int* step_iters, int step_cap, int lag, int tiles_per_group, StepLag sl) {
+  step_mfma_body<F, ST, true>(m, s0, s1, Mf, u0, u1, w_src, gbe, g_out, ctrl, cnt, step_iters, step_cap, lag,
+                              tiles_per_group, (int)blockIdx.x, (int)gridDim.x, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -2057,11 +2215,12 @@ static inline int ngroups(int nel) { return (nel + kLanes - 1) / kLanes; }
 // Workgroups of a kernel that the device holds at once (its occupancy by registers,
 // LDS and wave slots, times the compute units).
 template <typename K>
-static int resident_groups(K kernel, int threads) {
+static int resident_groups(K kernel, int threads, size_t lds = 0) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
   return per_cu * cus;
 }
 
@@ -2124,6 +2283,38 @@ struct Family {
   static int res_step() {
     static const int r = resident_groups(k_step_mfma<F>, 64 * StepTiling<F>::value);
     return r;
+  }
+  // The operator-in-LDS step completion, where the family's operator fits and the mesh
+  // fills at least half of a round of its workgroups; else the shared-tile one.  The two
+  // give bitwise the same results.
+  template <typename ST>
+  static int res_step_lds() {
+    static const int r = [] {
+      allow_lds(k_step_lds<F, ST>, StepLdsA<F>::bytes);
+      return resident_groups(k_step_lds<F, ST>, 64 * kStepLdsWaves, StepLdsA<F>::bytes);
+    }();
+    return r;
+  }
+  template <typename ST>
+  static bool step_lds(int nel) {
+    if constexpr (StepLdsA<F>::ok) {
+      const long ntiles = (nel + kMfmaTileElems - 1) / kMfmaTileElems;
+      return ntiles >= (long)kStepLdsWaves * kStepLdsTiles / 2 * res_step_lds<ST>();
+    } else {
+      return false;
+    }
+  }
+  template <typename ST>
+  static void step_lds_launch(const DevProblem& dp, ST* g_out, const StepLag& sl, int lag, hipStream_t st) {
+    if constexpr (StepLdsA<F>::ok) {
+      const int ntiles = (dp.mesh.nel + kMfmaTileElems - 1) / kMfmaTileElems;
+      const int tpg = kStepLdsWaves * kStepLdsTiles, groups = (ntiles + tpg - 1) / tpg;
+      hipLaunchKernelGGL((k_step_lds<F, ST>), dim3(groups), dim3(64 * kStepLdsWaves), StepLdsA<F>::bytes, st,
+                         dp.mesh, (ST*)dp.s[0], (ST*)dp.s[1], dp.Mf64, dp.u2[0], dp.u2[1],
+                         (const double*)(dp.has_src ? dp.w_src : nullptr),
+                         (const double*)(dp.has_src ? dp.gbe : nullptr), g_out, dp.ctrl, dp.counters + kCounterSet,
+                         dp.step_iters, dp.step_cap, lag, tpg, sl);
+    }
   }
   template <bool PIPE, bool FUSE = false>
   static int res_inner32() {
@@ -2202,9 +2393,13 @@ struct Family {
   }
   static void step32(const DevProblem& dp, int lag, unsigned seq_next, double tol, int lagged, hipStream_t st) {
     using TL = typename StepTiling<F>::TL;
+    const StepLag sl{lagged, seq_next, tol, dp.partials, dp.partial_stride, dp.nb_sweep, dp.hist, dp.hist_cap};
+    if (step_lds<float>(dp.mesh.nel)) {
+      step_lds_launch<float>(dp, dp.g32, sl, lag, st);
+      return;
+    }
     int tpg, groups;
     mfma_groups(dp.mesh.nel, TL::TS, res_step32(), tpg, groups);
-    const StepLag sl{lagged, seq_next, tol, dp.partials, dp.partial_stride, dp.nb_sweep, dp.hist, dp.hist_cap};
     hipLaunchKernelGGL((k_step_mfma<F, float>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, (float*)dp.s[0],
                        (float*)dp.s[1], dp.Mf64, dp.u2[0], dp.u2[1], (const double*)(dp.has_src ? dp.w_src : nullptr),
                        (const double*)(dp.has_src ? dp.gbe : nullptr), dp.g32, dp.ctrl, dp.counters + kCounterSet,
@@ -2231,9 +2426,13 @@ struct Family {
   }
   static void step(const DevProblem& dp, int lag, unsigned seq_next, double tol, int lagged, hipStream_t st) {
     using TL = typename StepTiling<F>::TL;
+    const StepLag sl{lagged, seq_next, tol, dp.partials, dp.partial_stride, dp.nb_sweep, dp.hist, dp.hist_cap};
+    if (step_lds<double>(dp.mesh.nel)) {
+      step_lds_launch<double>(dp, dp.g, sl, lag, st);
+      return;
+    }
     int tpg, groups;
     mfma_groups(dp.mesh.nel, TL::TS, res_step(), tpg, groups);
-    const StepLag sl{lagged, seq_next, tol, dp.partials, dp.partial_stride, dp.nb_sweep, dp.hist, dp.hist_cap};
     hipLaunchKernelGGL((k_step_mfma<F>), dim3(groups), dim3(64 * TL::NW), 0, st, dp.mesh, dp.s[0], dp.s[1],
                        dp.Mf64, dp.u2[0], dp.u2[1], (const double*)(dp.has_src ? dp.w_src : nullptr),
                        (const double*)(dp.has_src ? dp.gbe : nullptr), dp.g, dp.ctrl, dp.counters + kCounterSet,
