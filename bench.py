@@ -590,7 +590,7 @@ def run_counter_sample(torch, args):
 
 PMC_KERNELS = {  # summary tag -> kernel name prefix (as rocprofv3 prints it)
     "swe_sweep_p4_256x256": "void ehdg::k_sweep_mfma<ehdg::SweFam<5>, true>",
-    "swe_step_p4_256x256": "void ehdg::k_step_mfma<ehdg::SweFam<5>, double>",
+    "swe_step_p4_256x256": "void ehdg::k_step_lds<ehdg::SweFam<5>, double>",
     "transport3d_sweep_p3_64x64x64": "void ehdg::k_sweep_mfma<ehdg::TransportFam<3, 3, 4>, true>",
     "variable_sweep_p4_256x256": "void ehdg::k_sweep_var<ehdg::TransportFam<2, 2, 5> >",
 }
