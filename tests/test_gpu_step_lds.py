@@ -101,3 +101,25 @@ def test_euler_step_lds_equals_shared_tile():
         prob.set_initial(_fns(2))
         return prob
     _solo_equals_batch(make, 2, 1e-10)
+
+
+def test_swe_full_size_steps_match_oracle():
+    """The benchmark workload itself (256^2, degree 4, the Gaussian hump, dt 5e-5): two
+    backward-Euler steps with the operator-in-LDS step completion against the oracle's,
+    the same iteration counts and the element solution within the parity tolerance."""
+    from oracle import ehdg as O
+    from paper_1601_06681_amd import workloads as W
+    from tests._cases import oracle_swe, rel_err, swe_initial_fns
+    from tests.test_gpu_parity import CONV_TOL, _gpu_swe, _gpu_u
+    print("swe full-size steps vs oracle", flush=True)
+    cfg = W.SWE2D
+    op = oracle_swe(cfg["n"], cfg["degree"], cfg["Phi"], cfg["dt"], True)
+    fns = swe_initial_fns(cfg["seed"])
+    u0 = op.interpolate([lambda X, fn=fn: fn(X, np) for fn in fns])
+    ref_u, ref_its = O.be_steps(op, u0, 2, tol=1e-10)
+    prob = _gpu_swe(cfg["n"], cfg["degree"], cfg["Phi"], cfg["dt"], True)
+    prob.set_initial(fns)
+    rc, its = prob.step(2, 1e-10, 1000)
+    assert its == ref_its
+    assert rel_err(_gpu_u(prob), ref_u) < CONV_TOL
+    prob.close()
